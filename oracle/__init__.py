@@ -1,0 +1,313 @@
+"""Plain FP64 CPU oracle for the APR-SPH hot path (Nealon & Price 2024).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product library never does.  It
+shares no code with the GPU library.  Arrays are numpy; the arithmetic lives in
+``apr_oracle.c`` (brute-force O(N^2) neighbour search, FP64, no FMA
+contraction) and, for gradients, in ``adjoint.py`` (dense PyTorch CPU float64).
+
+Every function below marshals arguments only.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+_d = C.POINTER(C.c_double)
+_i8 = C.POINTER(C.c_int8)
+_i32 = C.POINTER(C.c_int32)
+_i64 = C.POINTER(C.c_int64)
+
+
+def lib():
+    """Load liboracle.so, building it first if it is not there."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_m4_f.restype = C.c_double
+        L.orc_m4_f.argtypes = [C.c_double]
+        L.orc_m4_df.restype = C.c_double
+        L.orc_m4_df.argtypes = [C.c_double]
+        L.orc_m4_d2f.restype = C.c_double
+        L.orc_m4_d2f.argtypes = [C.c_double]
+        L.orc_w.restype = C.c_double
+        L.orc_w.argtypes = [C.c_double, C.c_double]
+        L.orc_dwdh.restype = C.c_double
+        L.orc_dwdh.argtypes = [C.c_double, C.c_double]
+        L.orc_density.restype = C.c_int64
+        L.orc_density.argtypes = [C.c_int64, _d, _d, _d, _i8, C.c_double, C.c_double,
+                                  C.c_double, C.c_int32, C.c_int32, _d, _d, C.c_int64, _i64,
+                                  _d, _d, _d, _d, _i32, _d, _i32]
+        L.orc_neighbours.restype = None
+        L.orc_neighbours.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_int32, C.c_int32, _d, _d,
+                                     C.c_int64, _i64, _i64, _i64, _i64]
+        L.orc_eos.restype = None
+        L.orc_eos.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_double,
+                              C.c_double, _d, _d, _d, _d, _d, _d]
+        L.orc_forces.restype = None
+        L.orc_forces.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, _d, _i8, _d, _d, _d,
+                                 C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.c_int32, _d, _d,
+                                 C.c_int64, _i64, _d, _d, _d, _d, _d, _d, _d]
+        L.orc_kick.restype = None
+        L.orc_kick.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, C.c_double]
+        L.orc_drift.restype = None
+        L.orc_drift.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, C.c_double, C.c_int32,
+                                _d, _d]
+        L.orc_sink_gravity.restype = None
+        L.orc_sink_gravity.argtypes = [C.c_int64, _d, _d, _d, C.c_int32, _d, _d, _d,
+                                       C.c_double, _d, _d, _d]
+        L.orc_splitmix64.restype = C.c_uint64
+        L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_zone_level.restype = C.c_int32
+        L.orc_zone_level.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, _d, _i32,
+                                     _d, _i32, C.c_int32, C.c_int32]
+        L.orc_pair_tree.restype = C.c_int64
+        L.orc_pair_tree.argtypes = [C.c_int64, _i64, _d, _d, _d, _i64, _d, _d, C.c_int64,
+                                    _i64]
+        L.orc_split_merge.restype = C.c_int32
+        L.orc_split_merge.argtypes = [C.c_int64, C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d,
+                                      _i8, _i64, _i64, _d, C.c_int32, _d, _i32, _d, _i32,
+                                      C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      C.c_int32, C.c_uint64, C.c_int64, C.c_int32, _d, _d,
+                                      C.c_int32, C.c_int32, _i64, _i64, _i64, _i64]
+        _LIB = L
+    return _LIB
+
+
+def _p(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _box(lo, hi):
+    return _f64(np.asarray(lo, dtype=np.float64).reshape(3)), _f64(
+        np.asarray(hi, dtype=np.float64).reshape(3))
+
+
+# --------------------------------------------------------------------- kernel
+def m4_f(q):
+    return lib().orc_m4_f(float(q))
+
+
+def m4_df(q):
+    return lib().orc_m4_df(float(q))
+
+
+def m4_d2f(q):
+    return lib().orc_m4_d2f(float(q))
+
+
+def w(r, h):
+    return lib().orc_w(float(r), float(h))
+
+
+def dwdh(r, h):
+    return lib().orc_dwdh(float(r), float(h))
+
+
+# -------------------------------------------------------------------- density
+def density(x, y, z, level, h_in, *, m0, hfact=1.2, tol=1e-12, max_iter=50, periodic=False,
+            lo=(0, 0, 0), hi=(1, 1, 1), targets=None):
+    """h-rho Newton solve for every target (all particles if targets is None).
+
+    h_in is indexed like the targets.  Returns a dict of per-target arrays
+    h, rho, omega, nneigh (self included), dnn, iters, and 'failures'."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    n = x.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    h_in = _f64(h_in)
+    assert h_in.shape[0] == nt
+    lo, hi = _box(lo, hi)
+    out = dict(h=np.empty(nt), rho=np.empty(nt), omega=np.empty(nt),
+               nneigh=np.empty(nt, np.int32), dnn=np.empty(nt), iters=np.empty(nt, np.int32))
+    fails = lib().orc_density(n, _p(x, _d), _p(y, _d), _p(z, _d), _p(level, _i8), m0, hfact,
+                              tol, max_iter, int(bool(periodic)), _p(lo, _d), _p(hi, _d), nt,
+                              _p(tg, _i64), _p(h_in, _d), _p(out["h"], _d),
+                              _p(out["rho"], _d), _p(out["omega"], _d),
+                              _p(out["nneigh"], _i32), _p(out["dnn"], _d),
+                              _p(out["iters"], _i32))
+    out["failures"] = int(fails)
+    return out
+
+
+# ----------------------------------------------------------------- neighbours
+def neighbours(x, y, z, h, *, symmetric=False, periodic=False, lo=(0, 0, 0), hi=(1, 1, 1),
+               targets=None):
+    """Brute-force neighbour lists (b != a) for a given h; returns a list of
+    int64 arrays in ascending index order, one per target."""
+    x, y, z, h = _f64(x), _f64(y), _f64(z), _f64(h)
+    n = x.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    lo, hi = _box(lo, hi)
+    counts = np.zeros(nt, np.int64)
+    args = (n, _p(x, _d), _p(y, _d), _p(z, _d), _p(h, _d), int(bool(symmetric)),
+            int(bool(periodic)), _p(lo, _d), _p(hi, _d), nt, _p(tg, _i64))
+    lib().orc_neighbours(*args, _p(counts, _i64), None, None)
+    offs = np.zeros(nt + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    lst = np.empty(max(int(offs[-1]), 1), np.int64)
+    lib().orc_neighbours(*args, _p(counts, _i64), _p(offs, _i64), _p(lst, _i64))
+    return [lst[offs[t]:offs[t + 1]].copy() for t in range(nt)]
+
+
+# ------------------------------------------------------------------------ eos
+EOS_ISOTHERMAL, EOS_LOCALLY_ISOTHERMAL, EOS_ADIABATIC = 0, 1, 2
+
+
+def eos(x, y, rho, u=None, *, eos, cs0=1.0, q_cs=0.25, r_ref=1.0, gamma=5.0 / 3.0):
+    x, y, rho = _f64(x), _f64(y), _f64(rho)
+    u = None if u is None else _f64(u)
+    n = x.shape[0]
+    P, c = np.empty(n), np.empty(n)
+    lib().orc_eos(n, eos, cs0, q_cs, r_ref, gamma, _p(x, _d), _p(y, _d), _p(rho, _d),
+                  _p(u, _d), _p(P, _d), _p(c, _d))
+    return P, c
+
+
+# --------------------------------------------------------------------- forces
+def forces(x, y, z, vx, vy, vz, u, level, h, rho, omega, *, m0, eos, cs0=1.0, q_cs=0.25,
+           r_ref=1.0, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, lo=(0, 0, 0),
+           hi=(1, 1, 1), targets=None):
+    """Hydro acceleration, du/dt, vsig and the L1 bounds anorm, unorm per target."""
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz)]
+    u = None if u is None else _f64(u)
+    level = np.ascontiguousarray(level, dtype=np.int8)
+    h, rho, omega = _f64(h), _f64(rho), _f64(omega)
+    n = arrs[0].shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    lo, hi = _box(lo, hi)
+    out = {k: np.empty(nt) for k in ("ax", "ay", "az", "dudt", "vsig", "anorm", "unorm")}
+    lib().orc_forces(n, *[_p(a, _d) for a in arrs], _p(u, _d), _p(level, _i8), _p(h, _d),
+                     _p(rho, _d), _p(omega, _d), m0, eos, cs0, q_cs, r_ref, gamma, alpha,
+                     beta, int(bool(periodic)), _p(lo, _d), _p(hi, _d), nt, _p(tg, _i64),
+                     *[_p(out[k], _d) for k in ("ax", "ay", "az", "dudt", "vsig", "anorm",
+                                                 "unorm")])
+    return out
+
+
+# ---------------------------------------------------------------- integration
+def kick(vx, vy, vz, u, ax, ay, az, dudt, dt):
+    """v += dt a, u += dt du/dt, in place."""
+    n = vx.shape[0]
+    lib().orc_kick(n, _p(vx, _d), _p(vy, _d), _p(vz, _d), _p(u, _d), _p(_f64(ax), _d),
+                   _p(_f64(ay), _d), _p(_f64(az), _d),
+                   None if dudt is None else _p(_f64(dudt), _d), dt)
+
+
+def drift(x, y, z, vx, vy, vz, dt, *, periodic=False, lo=(0, 0, 0), hi=(1, 1, 1)):
+    """x += dt v (wrapped into the box if periodic), in place."""
+    lo, hi = _box(lo, hi)
+    lib().orc_drift(x.shape[0], _p(x, _d), _p(y, _d), _p(z, _d), _p(_f64(vx), _d),
+                    _p(_f64(vy), _d), _p(_f64(vz), _d), dt, int(bool(periodic)), _p(lo, _d),
+                    _p(hi, _d))
+
+
+def sink_gravity(x, y, z, sinks_x, sinks_m, sinks_eps, G, ax, ay, az):
+    """Adds the point-mass gravity of the sinks to ax, ay, az in place."""
+    sx = _f64(np.asarray(sinks_x).reshape(-1))
+    sm, se = _f64(sinks_m), _f64(sinks_eps)
+    lib().orc_sink_gravity(x.shape[0], _p(_f64(x), _d), _p(_f64(y), _d), _p(_f64(z), _d),
+                           sm.shape[0], _p(sx, _d), _p(sm, _d), _p(se, _d), G, _p(ax, _d),
+                           _p(ay, _d), _p(az, _d))
+
+
+# ----------------------------------------------------------------------- APR
+def splitmix64(state, k):
+    """k-th SplitMix64 output (k >= 1) from the given state."""
+    return int(lib().orc_splitmix64(C.c_uint64(state & (2**64 - 1)), C.c_uint64(k)))
+
+
+def _zones_arrays(zones):
+    nz = len(zones)
+    zc = np.zeros((max(nz, 1), 3))
+    zn = np.zeros(max(nz, 1), np.int32)
+    zr = np.zeros((max(nz, 1), 8))
+    ze = np.zeros((max(nz, 1), 8), np.int32)
+    for k, zd in enumerate(zones):
+        zc[k] = zd["c"]
+        rr = list(zd["r"])
+        ll = list(zd["ell"])
+        zn[k] = len(rr)
+        zr[k, :len(rr)] = rr
+        ze[k, :len(ll)] = ll
+    return nz, zc, zn, zr, ze
+
+
+def zone_level(x, y, z, zones, background=0, derefine=False):
+    nz, zc, zn, zr, ze = _zones_arrays(zones)
+    return int(lib().orc_zone_level(float(x), float(y), float(z), nz, _p(zc, _d),
+                                    _p(zn, _i32), _p(zr, _d), _p(ze, _i32), background,
+                                    int(bool(derefine))))
+
+
+def pair_tree(cand, x, y, z, ids, lo, hi):
+    """Leaf pairs of the merge pairing tree over particle indices cand."""
+    cand = np.ascontiguousarray(cand, dtype=np.int64)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    lo, hi = _box(lo, hi)
+    n = x.shape[0]
+    pairs = np.empty(max(n, 2), np.int64)
+    np_ = lib().orc_pair_tree(cand.shape[0], _p(cand, _i64), _p(x, _d), _p(y, _d), _p(z, _d),
+                              _p(ids, _i64), _p(lo, _d), _p(hi, _d), n, _p(pairs, _i64))
+    return pairs[:2 * np_].reshape(-1, 2).copy()
+
+
+def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_mode=0,
+                background=0, derefine=False, periodic=False, lo=(0, 0, 0), hi=(1, 1, 1),
+                dnn=None, cap=None, do_split=True, do_merge=True):
+    """One split/merge pass on a dict of numpy SoA arrays.
+
+    st holds x, y, z, vx, vy, vz, u, h (float64), level (int8), id (int64) and
+    next_id (int).  Returns a new dict (arrays trimmed to the new n) plus the
+    counts n_split, n_merged, n_spare."""
+    n = st["x"].shape[0]
+    cap = cap if cap is not None else 2 * n + 2
+    w = {}
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h"):
+        a = np.zeros(cap)
+        a[:n] = st[k]
+        w[k] = a
+    lev = np.zeros(cap, np.int8)
+    lev[:n] = st["level"]
+    ids = np.zeros(cap, np.int64)
+    ids[:n] = st["id"]
+    nid = C.c_int64(int(st["next_id"]))
+    nz, zc, zn, zr, ze = _zones_arrays(zones)
+    lo, hi = _box(lo, hi)
+    dn = None if dnn is None else _f64(dnn)
+    n_out, ns, nm, nsp = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    rc = lib().orc_split_merge(n, cap, *[_p(w[k], _d) for k in ("x", "y", "z", "vx", "vy", "vz",
+                                                                 "u", "h")],
+                               _p(lev, _i8), _p(ids, _i64), C.byref(nid), _p(dn, _d), nz,
+                               _p(zc, _d), _p(zn, _i32), _p(zr, _d), _p(ze, _i32), background,
+                               int(bool(derefine)), r_sep_factor, nn_cap, split_mode,
+                               C.c_uint64(seed & (2**64 - 1)), step, int(bool(periodic)),
+                               _p(lo, _d), _p(hi, _d), int(bool(do_split)),
+                               int(bool(do_merge)), C.byref(n_out), C.byref(ns), C.byref(nm),
+                               C.byref(nsp))
+    if rc != 0:
+        raise RuntimeError("oracle split_merge: capacity %d too small, need %d" % (cap, ns.value))
+    m = n_out.value
+    out = {k: w[k][:m].copy() for k in w}
+    out["level"] = lev[:m].copy()
+    out["id"] = ids[:m].copy()
+    out["next_id"] = nid.value
+    out["n_split"], out["n_merged"], out["n_spare"] = ns.value, nm.value, nsp.value
+    return out
