@@ -1,0 +1,223 @@
+/*
+ * apr.h -- C ABI of libapr.so, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of adaptive particle refinement (APR) for
+ * compressible SPH (Nealon & Price 2024): neighbour search, the
+ * variable-smoothing-length density sum with its h-rho Newton iteration, the
+ * pressure-gradient + artificial-viscosity + du/dt force sum over particles of
+ * mixed mass, the split/merge pass at refinement-zone boundaries, leapfrog
+ * integration, and the adjoint of the density and force sums.
+ *
+ * Conventions
+ *  - Every call returns an int status (APR_OK = 0 or an APR_ERR_* code) and
+ *    never throws.  apr_last_error() gives a message for the last failure.
+ *  - Particle arrays are caller-owned DEVICE pointers (one GPU), structure of
+ *    arrays, n valid entries out of `capacity` allocated ones.  The library
+ *    owns only its workspace (sort buffers, cells, tree, per-particle
+ *    derived values), which lives in the context and grows as needed.
+ *  - Calls enqueue work on the context's HIP stream and return without
+ *    waiting, except where a call says it synchronises.
+ *  - Mass is never passed: a particle of level l has mass m0 / 2^l (paper
+ *    Sec. 2.1, rules 4 and 5).
+ *  - "void *" arrays are float * when params.precision == APR_FP32 and
+ *    double * when it is APR_FP64.
+ *  - Kernel: M4 cubic spline with support 2h (paper appendix A, kernel table;
+ *    h_fact = 1.2 there).
+ */
+#ifndef APR_H
+#define APR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    APR_OK = 0,
+    APR_ERR_INVALID = 1,    /* bad argument, size or parameter */
+    APR_ERR_CAPACITY = 2,   /* splits need more than state->capacity */
+    APR_ERR_NOCONVERGE = 3, /* some h-rho Newton solves did not converge */
+    APR_ERR_HIP = 4,        /* a HIP runtime call failed */
+    APR_ERR_OVERFLOW = 5    /* a fixed-size internal list overflowed */
+};
+
+enum { APR_FP64 = 0, APR_FP32 = 1 };
+enum { APR_EOS_ISOTHERMAL = 0, APR_EOS_LOCALLY_ISOTHERMAL = 1, APR_EOS_ADIABATIC = 2 };
+enum { APR_SPLIT_TANGENTIAL = 0, APR_SPLIT_RANDOM = 1 };
+
+typedef struct apr_ctx apr_ctx;
+
+/* Particle state, structure of arrays of device pointers.  ax..dudt hold the
+ * total acceleration (hydro + sink gravity) and du/dt that the leapfrog needs
+ * between steps; they may be NULL for calls that do not integrate. */
+typedef struct {
+    int64_t n;        /* particles in use */
+    int64_t capacity; /* particles every array has room for */
+    int64_t next_id;  /* id given to the next particle a split creates (host value) */
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *u;        /* specific thermal energy (adiabatic EOS) */
+    double *h;        /* smoothing length */
+    double *ax, *ay, *az, *dudt;
+    int8_t *level;    /* refinement level l, mass m0 / 2^l */
+    int64_t *id;      /* persistent particle id */
+} apr_state;
+
+/* A refinement zone (paper Sec. 2.1, rule 1): nested spheres about one
+ * centre, radii r[0] > r[1] > ... (outer to inner) with levels ell[k].  The
+ * level at a point is that of the innermost sphere with |x - c|^2 < r^2
+ * (strict), or the background level outside them.  Several zones combine by
+ * max (refinement) or by min (params.derefine != 0; paper Sec. 2.1, rule 3). */
+typedef struct {
+    double c[3];
+    int32_t n;       /* number of spheres, 1..8 */
+    int32_t ell[8];
+    double r[8];
+} apr_zone;
+
+/* A point mass (sink) acting on the gas with gravity G m / (r^2 + eps^2). */
+typedef struct {
+    double x[3];
+    double m;
+    double eps;
+} apr_sink;
+
+typedef struct {
+    int32_t precision;  /* APR_FP64 or APR_FP32 (pair arithmetic and derived outputs) */
+    int32_t eos;        /* APR_EOS_* */
+    double hfact;       /* h = hfact (m / rho)^(1/3); 1.2 for M4 */
+    double tol_h;       /* Newton stops when |dh| < tol_h h */
+    int32_t max_iter;   /* Newton iterations per particle */
+    double cs0;         /* sound speed (isothermal) or its value at R = r_ref */
+    double q_cs;        /* locally isothermal: cs = cs0 (R / r_ref)^-q_cs, R cylindrical */
+    double r_ref;
+    double gamma;       /* adiabatic index */
+    double av_alpha;    /* artificial viscosity: vsig = alpha c + beta |v_ab . rhat| */
+    double av_beta;
+    int32_t periodic;   /* 1: periodic box [box_lo, box_hi) */
+    double box_lo[3];   /* domain box; also the frame of the Morton keys and of the */
+    double box_hi[3];   /* merge tree's quantised coordinates (particles are clamped) */
+    double m0;          /* mass of a level-0 particle */
+    double r_sep_factor;/* split offset r_sep = r_sep_factor h (0.2 in the paper) */
+    double nn_cap;      /* cap r_sep at nn_cap * nearest-neighbour distance; <= 0: off */
+    int32_t split_mode; /* APR_SPLIT_TANGENTIAL (paper) or APR_SPLIT_RANDOM */
+    int32_t ell_background;
+    int32_t derefine;   /* zones combine by min instead of max */
+    uint64_t seed;      /* split-axis random stream */
+    double G;           /* gravitational constant for sinks */
+} apr_params;
+
+/* Fills *p with defaults: FP32, adiabatic, hfact 1.2, tol 1e-6, 50 iterations,
+ * alpha 1, beta 2, gamma 5/3, r_sep 0.2, nn_cap 0.35, tangential, G = 1. */
+void apr_default_params(apr_params *p);
+
+/* Creates a context on the current HIP device.  stream is a hipStream_t (NULL:
+ * the null stream).  Returns APR_ERR_INVALID for bad parameters. */
+int apr_ctx_create(apr_ctx **ctx, const apr_params *p, void *stream);
+int apr_ctx_destroy(apr_ctx *ctx);
+int apr_ctx_set_stream(apr_ctx *ctx, void *stream);
+const char *apr_last_error(const apr_ctx *ctx);
+
+/* Sorts the particles into Morton order IN PLACE (all non-NULL state arrays
+ * are permuted) and builds the cell lists and the cell tree the other calls
+ * search.  perm (device, optional) receives, for every new slot, the slot the
+ * particle came from.  Replaces the k-d tree neighbour search of the paper's
+ * host code (Sec. 2.3) with Morton-ordered leaf cells of at most 64
+ * particles.  Periodic boxes need 2 max(h) < box / 4. */
+int apr_build_cells(apr_ctx *ctx, apr_state *s, int64_t *perm);
+
+/* Density and smoothing length (paper Sec. 2.2, which defers to Phantom's
+ * iterative h-rho solve): for every particle a, solves
+ *   rho_a = sum_b m_b W(|x_a - x_b|, h_a)  (b = a included),
+ *   h_a = hfact (m_a / rho_a)^(1/3)
+ * by Newton from the current h; writes the converged h into s->h and
+ *   Omega_a = 1 + h_a / (3 rho_a) sum_b m_b dW_ab/dh_a.
+ * rho, omega: [n] (float or double); nneigh (optional) counts b with
+ * r_ab < 2 h_a, self included; iters (optional) Newton sums per particle.
+ * Needs apr_build_cells on the same positions.  Asynchronous: failures to
+ * converge are counted on the device; apr_sync_status reports them. */
+int apr_density(apr_ctx *ctx, apr_state *s, void *rho, void *omega, int32_t *nneigh,
+                int32_t *iters);
+
+/* Hydrodynamic acceleration and du/dt (grad-h SPH with a per-particle
+ * artificial viscosity; the paper runs Phantom's compressible SPH):
+ *   a_a = -sum_b m_b [(P_a + q^a)/(Omega_a rho_a^2) F_ab(h_a)
+ *                   + (P_b + q^b)/(Omega_b rho_b^2) F_ab(h_b)] rhat_ab,
+ *   du_a/dt = sum_b m_b (P_a + q^a)/(Omega_a rho_a^2) (v_ab . rhat) F_ab(h_a),
+ * F_ab(h) = W'(r)/... for r < 2h, q^a = -rho_a vsig_a (v_ab . rhat)/2 for
+ * approaching pairs; pairs with r < 2 max(h_a, h_b).  P and c come from the
+ * EOS.  vsig (optional) = max over pairs of alpha c_a + beta max(0, -v_ab.rhat).
+ * rho, omega from apr_density on the same state.  Outputs [n]. */
+int apr_forces(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega, void *ax,
+               void *ay, void *az, void *dudt, void *vsig);
+
+/* Neighbour lists for a given h (device, [n]), with the FP64 predicate
+ * r_ab^2 < (2 h_a)^2 (mode 0) or r_ab^2 < (2 max(h_a, h_b))^2 (mode 1), b != a,
+ * evaluated on absolute positions with the minimum-image convention and no
+ * fused multiply-add.  Call once with list == NULL: counts [n] and offsets
+ * [n + 1] (prefix) are written and the total returned in *total (this
+ * synchronises).  Call again with list of room `cap` to get the neighbour
+ * slots of particle a in list[offsets[a] .. offsets[a+1]).  Test export. */
+int apr_neighbours(apr_ctx *ctx, const apr_state *s, const double *h, int32_t mode,
+                   int64_t *counts, int64_t *offsets, int64_t *list, int64_t cap,
+                   int64_t *total);
+
+/* One split/merge pass (paper Sec. 2.2, 2.3 and 2.5): split from the lowest
+ * level up, then merge from the highest level down; a particle changes level
+ * at most once per pass.
+ * Split: a particle whose level is below its zone level becomes two
+ * children of level + 1, h (1/2)^(1/3), same v and u, at x +- r_sep w with w
+ * tangential to the zone (rotated about x - c by a random angle) or random;
+ * r_sep = r_sep_factor h, capped at nn_cap * (nearest-neighbour distance from
+ * the last apr_density) when nn_cap > 0.  The parent slot keeps the + child;
+ * the - children are appended in ascending parent slot, with ids next_id,
+ * next_id + 1, ...
+ * Random stream: s = F(seed ^ F(id ^ F(step))), F(v) the first SplitMix64
+ * output from state v; rotation angle 2 pi U1 (tangential) or axis from
+ * (U1, U2) (random), Uk = (k-th SplitMix64 output from s >> 11) 2^-53.
+ * Merge, for l = max level .. 1: the level-l particles not changed in this
+ * pass, in ascending id, the highest id left out if their number is odd, are
+ * paired by a k-d tree on 2^21-step quantised coordinates over the box (cut
+ * on the widest axis at the floor of the mean, an even count forced on each
+ * side, leaves of two); a leaf whose centre of mass lies in a zone of level
+ * < l merges: the lower id stays at the centre of mass with the mean velocity
+ * and mean u, level l - 1, h 2^(1/3); the other is removed.  Survivors keep
+ * their order.
+ * Synchronises.  Updates s->n and s->next_id.  flags: bit 0 split, bit 1
+ * merge (0 means both).  If the splits need more than s->capacity the state is
+ * left unchanged, *n_split receives the capacity needed and APR_ERR_CAPACITY
+ * is returned.  After a pass the cells must be rebuilt. */
+int apr_split_merge(apr_ctx *ctx, apr_state *s, const apr_zone *zones, int32_t nzones,
+                    int64_t step, int32_t flags, int64_t *n_split, int64_t *n_merged,
+                    int64_t *n_spare);
+
+/* Kick-drift-kick leapfrog step of size dt on the state (the paper's host
+ * code integrates; the scheme here is the standard KDK):
+ *   v += dt/2 a, u += dt/2 du/dt;  x += dt v (wrapped if periodic);
+ *   rebuild cells, density;  split/merge if nzones > 0 (then rebuild and
+ *   density again);  hydro forces + sink gravity -> a, du/dt;
+ *   v += dt/2 a, u += dt/2 du/dt.
+ * s->ax..dudt must hold the acceleration of the current positions on entry
+ * (apr_accel computes it).  sinks are at their positions for the end of the
+ * step.  Synchronises only if nzones > 0 or on error checks. */
+int apr_step(apr_ctx *ctx, apr_state *s, const apr_zone *zones, int32_t nzones,
+             const apr_sink *sinks, int32_t nsinks, double dt, int64_t step);
+
+/* Rebuilds cells, solves density and writes the total acceleration (hydro +
+ * sinks) and du/dt into s->ax..dudt.  Asynchronous. */
+int apr_accel(apr_ctx *ctx, apr_state *s, const apr_sink *sinks, int32_t nsinks);
+
+/* Courant timestep C min_a h_a / vsig_a from the last apr_accel/apr_step
+ * (0.3 by analogy with the paper's relaxation step, Sec. 2.4).  Synchronises. */
+int apr_timestep(apr_ctx *ctx, const apr_state *s, double C, double *dt);
+
+/* Waits for the stream and returns APR_ERR_NOCONVERGE / APR_ERR_OVERFLOW if
+ * a kernel since the last call flagged one; *count receives the number of
+ * particles that failed to converge (may be NULL).  Clears the flags. */
+int apr_sync_status(apr_ctx *ctx, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APR_H */

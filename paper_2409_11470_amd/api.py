@@ -1,0 +1,259 @@
+"""Python binding of libapr.so with the C ABI's names.
+
+Arguments are marshalled from torch tensors (device memory) and plain Python
+values; every computation runs in the library.  Each apr_* function raises
+AprError when the C call returns a non-zero status.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._abi import AprError, CState, Params, Sink, Zone, apr_default_params, lib
+
+_DFIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_params(**kw):
+    """apr_params with the library defaults, overridden by keyword values."""
+    p = apr_default_params()
+    for k, v in kw.items():
+        if k in ("box_lo", "box_hi"):
+            getattr(p, k)[:] = [float(a) for a in v]
+        elif k == "seed":
+            p.seed = int(v) & (2 ** 64 - 1)
+        elif not hasattr(p, k):
+            raise KeyError(k)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def make_zones(zones):
+    """ctypes array of apr_zone from dicts {c: (x, y, z), r: radii outer->inner, ell: levels}."""
+    arr = (Zone * max(1, len(zones)))()
+    for k, z in enumerate(zones):
+        arr[k].c[:] = [float(v) for v in z["c"]]
+        r, e = list(z["r"]), list(z["ell"])
+        if not 1 <= len(r) <= 8 or len(e) != len(r):
+            raise ValueError("a zone has 1..8 spheres")
+        arr[k].n = len(r)
+        for i in range(len(r)):
+            arr[k].r[i] = float(r[i])
+            arr[k].ell[i] = int(e[i])
+    return arr, len(zones)
+
+
+def make_sinks(sinks):
+    arr = (Sink * max(1, len(sinks)))()
+    for k, s in enumerate(sinks):
+        arr[k].x[:] = [float(v) for v in s["x"]]
+        arr[k].m = float(s["m"])
+        arr[k].eps = float(s.get("eps", 0.0))
+    return arr, len(sinks)
+
+
+class Context:
+    """Owns an apr_ctx bound to the current torch stream."""
+
+    def __init__(self, params, stream=None):
+        if isinstance(params, dict):
+            params = make_params(**params)
+        self.params = params
+        self.ptr = C.c_void_p()
+        h = _stream_handle() if stream is None else stream
+        rc = lib().apr_ctx_create(C.byref(self.ptr), C.byref(params), C.c_void_p(h))
+        if rc != 0:
+            raise AprError(rc, "apr_ctx_create failed")
+
+    @property
+    def fp32(self):
+        return self.params.precision == 1
+
+    @property
+    def dtype(self):
+        return torch.float32 if self.fp32 else torch.float64
+
+    def error(self):
+        return lib().apr_last_error(self.ptr).decode()
+
+    def check(self, rc):
+        if rc != 0:
+            raise AprError(rc, self.error())
+
+    def close(self):
+        if self.ptr:
+            lib().apr_ctx_destroy(self.ptr)
+            self.ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceState:
+    """Particle arrays on the GPU (structure of arrays) with room for `capacity`."""
+
+    def __init__(self, capacity, device="cuda"):
+        self.capacity = int(capacity)
+        self.n = 0
+        self.next_id = 0
+        self.t = {k: torch.zeros(self.capacity, dtype=torch.float64, device=device)
+                  for k in _DFIELDS}
+        self.t["level"] = torch.zeros(self.capacity, dtype=torch.int8, device=device)
+        self.t["id"] = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+
+    @classmethod
+    def from_numpy(cls, st, capacity=None, device="cuda"):
+        n = st["x"].shape[0]
+        self = cls(capacity or n, device)
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h"):
+            self.t[k][:n] = torch.from_numpy(np.ascontiguousarray(st[k], np.float64))
+        self.t["level"][:n] = torch.from_numpy(np.ascontiguousarray(st["level"], np.int8))
+        self.t["id"][:n] = torch.from_numpy(np.ascontiguousarray(st["id"], np.int64))
+        self.n = n
+        self.next_id = int(st.get("next_id", n))
+        return self
+
+    def to_numpy(self):
+        n = self.n
+        out = {k: v[:n].cpu().numpy() for k, v in self.t.items()}
+        out["next_id"] = self.next_id
+        return out
+
+    def __getitem__(self, k):
+        return self.t[k][:self.n]
+
+    def cstate(self, with_accel=True):
+        cs = CState()
+        cs.n, cs.capacity, cs.next_id = self.n, self.capacity, self.next_id
+        for k in _DFIELDS:
+            if not with_accel and k in ("ax", "ay", "az", "dudt"):
+                continue
+            setattr(cs, k, self.t[k].data_ptr())
+        cs.level = self.t["level"].data_ptr()
+        cs.id = self.t["id"].data_ptr()
+        return cs
+
+    def absorb(self, cs):
+        self.n = int(cs.n)
+        self.next_id = int(cs.next_id)
+
+    def grow(self, capacity):
+        if capacity <= self.capacity:
+            return
+        for k, v in self.t.items():
+            nv = torch.zeros(capacity, dtype=v.dtype, device=v.device)
+            nv[:self.n] = v[:self.n]
+            self.t[k] = nv
+        self.capacity = int(capacity)
+
+
+# ----------------------------------------------------------- C-ABI functions
+def apr_ctx_create(params, stream=None):
+    return Context(params, stream)
+
+
+def apr_ctx_destroy(ctx):
+    ctx.close()
+
+
+def apr_build_cells(ctx, st, perm=None):
+    cs = st.cstate()
+    ctx.check(lib().apr_build_cells(ctx.ptr, C.byref(cs), _ptr(perm)))
+
+
+def apr_density(ctx, st, rho, omega, nneigh=None, iters=None):
+    cs = st.cstate()
+    ctx.check(lib().apr_density(ctx.ptr, C.byref(cs), _ptr(rho), _ptr(omega), _ptr(nneigh),
+                                _ptr(iters)))
+
+
+def apr_forces(ctx, st, rho, omega, ax, ay, az, dudt, vsig=None):
+    cs = st.cstate()
+    ctx.check(lib().apr_forces(ctx.ptr, C.byref(cs), _ptr(rho), _ptr(omega), _ptr(ax), _ptr(ay),
+                               _ptr(az), _ptr(dudt), _ptr(vsig)))
+
+
+def apr_neighbours(ctx, st, h, mode=0):
+    """Neighbour slots per particle for the given h (device float64 [n]).
+    Returns (offsets [n+1], list) as device int64 tensors."""
+    n = st.n
+    dev = h.device
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    offs = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    total = C.c_int64()
+    cs = st.cstate()
+    ctx.check(lib().apr_neighbours(ctx.ptr, C.byref(cs), _ptr(h), mode, _ptr(counts),
+                                   _ptr(offs), None, 0, C.byref(total)))
+    lst = torch.zeros(max(1, total.value), dtype=torch.int64, device=dev)
+    ctx.check(lib().apr_neighbours(ctx.ptr, C.byref(cs), _ptr(h), mode, _ptr(counts),
+                                   _ptr(offs), _ptr(lst), lst.numel(), C.byref(total)))
+    return offs, lst[:total.value]
+
+
+def apr_split_merge(ctx, st, zones, step, flags=0):
+    """One split/merge pass; grows st if the splits need room.  Returns
+    (n_split, n_merged, n_spare)."""
+    zarr, nz = make_zones(zones)
+    while True:
+        cs = st.cstate()
+        ns, nm, nsp = C.c_int64(), C.c_int64(), C.c_int64()
+        rc = lib().apr_split_merge(ctx.ptr, C.byref(cs), zarr, nz, int(step), int(flags),
+                                   C.byref(ns), C.byref(nm), C.byref(nsp))
+        if rc == 2:  # APR_ERR_CAPACITY: grow and retry
+            st.grow(int(ns.value * 5 // 4) + 64)
+            continue
+        ctx.check(rc)
+        st.absorb(cs)
+        return ns.value, nm.value, nsp.value
+
+
+def apr_step(ctx, st, zones, sinks, dt, step):
+    zarr, nz = make_zones(zones)
+    sarr, ns = make_sinks(sinks)
+    if nz > 0:
+        # room for the worst case of this pass (every particle splits)
+        st.grow(2 * st.n + 64)
+    cs = st.cstate()
+    rc = lib().apr_step(ctx.ptr, C.byref(cs), zarr, nz, sarr, ns, float(dt), int(step))
+    ctx.check(rc)
+    st.absorb(cs)
+
+
+def apr_accel(ctx, st, sinks=()):
+    sarr, ns = make_sinks(list(sinks))
+    cs = st.cstate()
+    ctx.check(lib().apr_accel(ctx.ptr, C.byref(cs), sarr, ns))
+
+
+def apr_timestep(ctx, st, C_cfl=0.3):
+    dt = C.c_double()
+    cs = st.cstate()
+    ctx.check(lib().apr_timestep(ctx.ptr, C.byref(cs), float(C_cfl), C.byref(dt)))
+    return dt.value
+
+
+def apr_sync_status(ctx):
+    """Returns the number of unconverged h-rho solves; raises AprError on a flag."""
+    cnt = C.c_int64()
+    rc = lib().apr_sync_status(ctx.ptr, C.byref(cnt))
+    if rc != 0:
+        raise AprError(rc, ctx.error())
+    return cnt.value

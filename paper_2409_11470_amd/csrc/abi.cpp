@@ -1,0 +1,307 @@
+// C ABI of libapr.so: argument checks, the context and its workspace, and
+// the order of kernel launches for each call.  No exceptions cross the ABI.
+#include <cstdio>
+#include <new>
+
+#include "common.hpp"
+
+namespace apr {
+
+int fail(apr_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_check(apr_ctx *c, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, APR_ERR_HIP, m);
+}
+
+void *ws(apr_ctx *c, const char *name, size_t bytes)
+{
+    for (auto &b : c->bufs) {
+        if (b.name == name) {
+            if (b.bytes >= bytes) return b.p;
+            // growing: queued kernels may still use the old buffer
+            if (hipStreamSynchronize(c->stream) != hipSuccess) return nullptr;
+            if (hipFree(b.p) != hipSuccess) return nullptr;
+            b.p = nullptr;
+            size_t nb = bytes + bytes / 4;
+            if (hipMalloc(&b.p, nb) != hipSuccess) {
+                b.bytes = 0;
+                c->err = std::string("workspace allocation failed: ") + name;
+                return nullptr;
+            }
+            b.bytes = nb;
+            return b.p;
+        }
+    }
+    apr_ctx::Buf b;
+    b.name = name;
+    b.bytes = bytes;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        c->err = std::string("workspace allocation failed: ") + name;
+        return nullptr;
+    }
+    c->bufs.push_back(b);
+    return b.p;
+}
+
+}  // namespace apr
+
+using namespace apr;
+
+namespace {
+
+int check_state(apr_ctx *c, const apr_state *s, bool need_vel)
+{
+    if (!c) return APR_ERR_INVALID;
+    if (!s) return fail(c, APR_ERR_INVALID, "null state");
+    if (s->n <= 0 || s->n > s->capacity) return fail(c, APR_ERR_INVALID, "bad n / capacity");
+    if (!s->x || !s->y || !s->z || !s->h || !s->level || !s->id)
+        return fail(c, APR_ERR_INVALID, "state needs x, y, z, h, level, id");
+    if (need_vel && (!s->vx || !s->vy || !s->vz))
+        return fail(c, APR_ERR_INVALID, "state needs vx, vy, vz");
+    return APR_OK;
+}
+
+int check_params(const apr_params *p, std::string &why)
+{
+    if (p->precision != APR_FP32 && p->precision != APR_FP64) return why = "precision", 1;
+    if (p->eos < 0 || p->eos > 2) return why = "eos", 1;
+    if (!(p->hfact > 0) || !(p->tol_h > 0) || p->max_iter < 1) return why = "hfact/tol/max_iter", 1;
+    if (!(p->m0 > 0)) return why = "m0", 1;
+    for (int k = 0; k < 3; ++k)
+        if (!(p->box_hi[k] > p->box_lo[k])) return why = "box", 1;
+    if (p->split_mode != APR_SPLIT_TANGENTIAL && p->split_mode != APR_SPLIT_RANDOM)
+        return why = "split_mode", 1;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void apr_default_params(apr_params *p)
+{
+    std::memset(p, 0, sizeof(*p));
+    p->precision = APR_FP32;
+    p->eos = APR_EOS_ADIABATIC;
+    p->hfact = 1.2;
+    p->tol_h = 1e-6;
+    p->max_iter = 50;
+    p->cs0 = 1.0;
+    p->q_cs = 0.25;
+    p->r_ref = 1.0;
+    p->gamma = 5.0 / 3.0;
+    p->av_alpha = 1.0;
+    p->av_beta = 2.0;
+    p->periodic = 0;
+    for (int k = 0; k < 3; ++k) {
+        p->box_lo[k] = 0.0;
+        p->box_hi[k] = 1.0;
+    }
+    p->m0 = 1.0;
+    p->r_sep_factor = 0.2;
+    p->nn_cap = 0.35;
+    p->split_mode = APR_SPLIT_TANGENTIAL;
+    p->ell_background = 0;
+    p->derefine = 0;
+    p->seed = 0;
+    p->G = 1.0;
+}
+
+int apr_ctx_create(apr_ctx **out, const apr_params *p, void *stream)
+{
+    if (!out || !p) return APR_ERR_INVALID;
+    *out = nullptr;
+    std::string why;
+    if (check_params(p, why)) return APR_ERR_INVALID;
+    apr_ctx *c = new (std::nothrow) apr_ctx();
+    if (!c) return APR_ERR_INVALID;
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    if (hipMalloc(&c->d_status, sizeof(int32_t) * ST_WORDS) != hipSuccess ||
+        hipHostMalloc(&c->h_status, sizeof(int32_t) * ST_WORDS, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * ST_WORDS, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (c->d_status) (void)hipFree(c->d_status);
+        if (c->h_status) (void)hipHostFree(c->h_status);
+        delete c;
+        return APR_ERR_HIP;
+    }
+    *out = c;
+    return APR_OK;
+}
+
+int apr_ctx_destroy(apr_ctx *c)
+{
+    if (!c) return APR_ERR_INVALID;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->bufs)
+        if (b.p) (void)hipFree(b.p);
+    if (c->d_status) (void)hipFree(c->d_status);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    delete c;
+    return APR_OK;
+}
+
+int apr_ctx_set_stream(apr_ctx *c, void *stream)
+{
+    if (!c) return APR_ERR_INVALID;
+    c->stream = (hipStream_t)stream;
+    return APR_OK;
+}
+
+const char *apr_last_error(const apr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int apr_build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
+{
+    int rc = check_state(c, s, false);
+    if (rc) return rc;
+    return build_cells(c, s, perm);
+}
+
+int apr_density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh,
+                int32_t *iters)
+{
+    int rc = check_state(c, s, false);
+    if (rc) return rc;
+    return density(c, s, rho, omega, nneigh, iters);
+}
+
+int apr_forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
+               void *ay, void *az, void *dudt, void *vsig)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    return forces(c, s, rho, omega, ax, ay, az, dudt, vsig);
+}
+
+int apr_neighbours(apr_ctx *c, const apr_state *s, const double *h, int32_t mode,
+                   int64_t *counts, int64_t *offsets, int64_t *list, int64_t cap,
+                   int64_t *total)
+{
+    int rc = check_state(c, s, false);
+    if (rc) return rc;
+    return neighbours(c, s, h, mode, counts, offsets, list, cap, total);
+}
+
+int apr_split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
+                    int64_t step, int32_t flags, int64_t *n_split, int64_t *n_merged,
+                    int64_t *n_spare)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    if (nzones < 0 || (nzones > 0 && !zones)) return fail(c, APR_ERR_INVALID, "zones");
+    for (int k = 0; k < nzones; ++k)
+        if (zones[k].n < 1 || zones[k].n > 8) return fail(c, APR_ERR_INVALID, "zone spheres");
+    if (!s->u) return fail(c, APR_ERR_INVALID, "state needs u");
+    int64_t d0 = 0, d1 = 0, d2 = 0;
+    return split_merge(c, s, zones, nzones, step, flags, n_split ? n_split : &d0,
+                       n_merged ? n_merged : &d1, n_spare ? n_spare : &d2);
+}
+
+// derived-value buffers the step and accel calls own
+static void step_buffers(apr_ctx *c, int64_t cap, void **rho, void **om, void **a, void **vs)
+{
+    size_t e = c->p.precision == APR_FP32 ? 4 : 8;
+    *rho = ws(c, "st_rho", cap * e);
+    *om = ws(c, "st_om", cap * e);
+    *a = ws(c, "st_acc", 4 * cap * e);
+    *vs = ws(c, "st_vsig", cap * e);
+}
+
+static int accel_now(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t nsinks,
+                     bool build)
+{
+    int rc;
+    if (build) {
+        rc = build_cells(c, s, nullptr);
+        if (rc) return rc;
+    }
+    void *rho, *om, *a, *vs;
+    step_buffers(c, s->capacity, &rho, &om, &a, &vs);
+    if (!rho || !om || !a || !vs) return fail(c, APR_ERR_HIP, "step workspace");
+    size_t e = c->p.precision == APR_FP32 ? 4 : 8;
+    char *ab = (char *)a;
+    size_t stride = (size_t)s->capacity * e;
+    rc = density(c, s, rho, om, nullptr, nullptr);
+    if (rc) return rc;
+    rc = forces(c, s, rho, om, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, vs);
+    if (rc) return rc;
+    return total_accel(c, s, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, sinks, nsinks);
+}
+
+int apr_accel(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t nsinks)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    if (!s->ax || !s->ay || !s->az || !s->dudt)
+        return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt");
+    if (nsinks > 0 && !sinks) return fail(c, APR_ERR_INVALID, "sinks");
+    return accel_now(c, s, sinks, nsinks, true);
+}
+
+int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
+             const apr_sink *sinks, int32_t nsinks, double dt, int64_t step)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    if (!s->ax || !s->ay || !s->az || !s->dudt)
+        return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt");
+    if (nsinks > 0 && !sinks) return fail(c, APR_ERR_INVALID, "sinks");
+    rc = kick(c, s, 0.5 * dt);
+    if (rc) return rc;
+    rc = drift(c, s, dt);
+    if (rc) return rc;
+    rc = build_cells(c, s, nullptr);
+    if (rc) return rc;
+    if (nzones > 0) {
+        // density first: the split cap needs nearest-neighbour distances here
+        void *rho, *om, *a, *vs;
+        step_buffers(c, s->capacity, &rho, &om, &a, &vs);
+        rc = density(c, s, rho, om, nullptr, nullptr);
+        if (rc) return rc;
+        int64_t ns = 0, nm = 0, nsp = 0;
+        rc = apr_split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp);
+        if (rc) return rc;
+        if (ns + nm > 0) {
+            rc = build_cells(c, s, nullptr);
+            if (rc) return rc;
+        }
+    }
+    rc = accel_now(c, s, sinks, nsinks, false);
+    if (rc) return rc;
+    return kick(c, s, 0.5 * dt);
+}
+
+int apr_timestep(apr_ctx *c, const apr_state *s, double C, double *dt)
+{
+    int rc = check_state(c, s, false);
+    if (rc) return rc;
+    if (!dt) return fail(c, APR_ERR_INVALID, "dt");
+    if (c->force_n != s->n) return fail(c, APR_ERR_INVALID, "no force evaluation for this state");
+    void *rho, *om, *a, *vs;
+    step_buffers(c, s->capacity, &rho, &om, &a, &vs);
+    return min_timestep(c, s, vs, C, dt);
+}
+
+int apr_sync_status(apr_ctx *c, int64_t *count)
+{
+    if (!c) return APR_ERR_INVALID;
+    APR_HIP(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * ST_WORDS,
+                              hipMemcpyDeviceToHost, c->stream));
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    APR_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * ST_WORDS, c->stream));
+    int32_t nc = c->h_status[ST_NOCONV], ov = c->h_status[ST_OVERFLOW];
+    if (count) *count = nc;
+    if (ov) return fail(c, APR_ERR_OVERFLOW, "an internal candidate list overflowed");
+    if (nc) return fail(c, APR_ERR_NOCONVERGE, std::to_string(nc) + " h-rho solves did not converge");
+    return APR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,382 @@
+// Cell build: Morton keys -> stable radix sort -> in-place permutation of the
+// particle state -> leaf cells of at most 64 consecutive particles -> a
+// 64-ary tree of bounding boxes over the cells.
+//
+// Cells never cross a Morton prefix boundary at the segment level (2 for
+// periodic boxes, so a cell spans at most a quarter of the box per axis;
+// 3 otherwise), which keeps them compact where the Morton curve jumps.
+// All counts stay on the device (Hdr); kernels are sized by upper bounds.
+#include "common.hpp"
+
+namespace apr {
+
+namespace {
+
+constexpr int kKeyBits = 30;  // 10 bits per axis
+
+__device__ inline uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline uint32_t quant10(double x, double lo, double L)
+{
+    double f = floor((x - lo) * (1024.0 / L));
+    if (f < 0.0) f = 0.0;
+    if (f > 1023.0) f = 1023.0;
+    return (uint32_t)f;
+}
+
+__global__ void k_morton(const double *x, const double *y, const double *z, int64_t n, Box b,
+                         uint32_t *keys, uint32_t *vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t qx = quant10(x[i], b.lo[0], b.L[0]);
+    uint32_t qy = quant10(y[i], b.lo[1], b.L[1]);
+    uint32_t qz = quant10(z[i], b.lo[2], b.L[2]);
+    keys[i] = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_seg_count(const uint32_t *keys, int64_t n, int segshift, uint32_t *segcount)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&segcount[keys[i] >> segshift], 1u);
+}
+
+// One block: segment starts, cells per segment and their offsets, the header.
+__global__ __launch_bounds__(1024) void k_seg_scan(const uint32_t *segcount, int nseg,
+                                                   int64_t n, uint32_t *segstart,
+                                                   uint32_t *celloff, Hdr *hdr,
+                                                   int32_t *cell_start, int nlev)
+{
+    __shared__ uint32_t ps[4096], pc[4096];
+    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+        ps[s] = segcount[s];
+        pc[s] = (segcount[s] + kCell - 1) / kCell;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // nseg <= 4096: a serial pass is a few microseconds and keeps this simple
+        uint32_t a = 0, b = 0;
+        for (int s = 0; s < nseg; ++s) {
+            uint32_t ca = ps[s], cb = pc[s];
+            ps[s] = a;
+            pc[s] = b;
+            a += ca;
+            b += cb;
+        }
+        hdr->ncells = (int32_t)b;
+        int64_t m = b;
+        hdr->nnode[0] = (int32_t)m;
+        for (int k = 1; k <= kMaxLev; ++k) {
+            m = k <= nlev ? (m + kFan - 1) / kFan : 0;
+            hdr->nnode[k] = (int32_t)m;
+        }
+        cell_start[b] = (int32_t)n;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+        segstart[s] = ps[s];
+        celloff[s] = pc[s];
+    }
+}
+
+__global__ void k_cell_start(const uint32_t *keys, int64_t n, int segshift,
+                             const uint32_t *segstart, const uint32_t *celloff,
+                             int32_t *cell_start)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t s = keys[i] >> segshift;
+    int64_t r = i - (int64_t)segstart[s];
+    if (r % kCell == 0) cell_start[celloff[s] + r / kCell] = (int32_t)i;
+}
+
+struct PermArgs {
+    double *d[12];     // state double arrays (nullptr entries skipped)
+    double *dt[12];    // temporaries
+    int nd;
+    int8_t *lev, *levt;
+    int64_t *id, *idt;
+    const uint32_t *perm;
+    int64_t *perm_out;
+    int64_t n;
+};
+
+__global__ void k_gather(PermArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t j = a.perm[i];
+    for (int k = 0; k < a.nd; ++k) a.dt[k][i] = a.d[k][j];
+    a.levt[i] = a.lev[j];
+    a.idt[i] = a.id[j];
+    if (a.perm_out) a.perm_out[i] = j;
+}
+
+__global__ void k_scatter_back(PermArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    for (int k = 0; k < a.nd; ++k) a.d[k][i] = a.dt[k][i];
+    a.lev[i] = a.levt[i];
+    a.id[i] = a.idt[i];
+}
+
+template <class T>
+__device__ inline T wave_min(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+template <class T>
+__device__ inline T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// One wavefront per cell: bounding box, centre, rounded-up half extents and
+// h_max; per particle the position relative to the cell centre and the
+// normalised mass 2^-level, in the precision of the pair arithmetic.
+template <class T>
+__global__ __launch_bounds__(256) void k_cell_geo(const Hdr *hdr, const int32_t *cell_start,
+                                                  const double *x, const double *y,
+                                                  const double *z, const double *h,
+                                                  const int8_t *level, Geo *cells,
+                                                  vec4_t<T> *pm, int64_t bound)
+{
+    int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= bound || c >= hdr->ncells) return;
+    int lane = lane_id();
+    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+    int64_t i = s0 + lane;
+    bool in = i < s1;
+    double px = in ? x[i] : 0.0, py = in ? y[i] : 0.0, pz = in ? z[i] : 0.0;
+    double ph = in ? h[i] : 0.0;
+    double inf = __builtin_huge_val();
+    double lx = wave_min(in ? px : inf), ly = wave_min(in ? py : inf), lz = wave_min(in ? pz : inf);
+    double ux = wave_max(in ? px : -inf), uy = wave_max(in ? py : -inf),
+           uz = wave_max(in ? pz : -inf);
+    double hm = wave_max(ph);
+    double cx = 0.5 * (lx + ux), cy = 0.5 * (ly + uy), cz = 0.5 * (lz + uz);
+    if (lane == 0) {
+        Geo g;
+        g.cx = cx; g.cy = cy; g.cz = cz;
+        g.ex = f_up(fmax(ux - cx, cx - lx));
+        g.ey = f_up(fmax(uy - cy, cy - ly));
+        g.ez = f_up(fmax(uz - cz, cz - lz));
+        g.hmax = f_up(hm);
+        cells[c] = g;
+    }
+    if (in) {
+        vec4_t<T> v;
+        v.x = (T)(px - cx);
+        v.y = (T)(py - cy);
+        v.z = (T)(pz - cz);
+        v.w = (T)ldexp(1.0, -(int)level[i]);
+        pm[i] = v;
+    }
+}
+
+// One wavefront per node: union of its (up to) 64 children.
+__global__ __launch_bounds__(256) void k_tree_level(const Hdr *hdr, int lev, const Geo *child,
+                                                    Geo *node, int64_t bound)
+{
+    int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (j >= bound || j >= hdr->nnode[lev]) return;
+    int lane = lane_id();
+    int64_t k = j * kFan + lane;
+    bool in = k < hdr->nnode[lev - 1];
+    double inf = __builtin_huge_val();
+    Geo g;
+    if (in) g = child[k];
+    double lx = wave_min(in ? g.cx - (double)g.ex : inf);
+    double ly = wave_min(in ? g.cy - (double)g.ey : inf);
+    double lz = wave_min(in ? g.cz - (double)g.ez : inf);
+    double ux = wave_max(in ? g.cx + (double)g.ex : -inf);
+    double uy = wave_max(in ? g.cy + (double)g.ey : -inf);
+    double uz = wave_max(in ? g.cz + (double)g.ez : -inf);
+    float hm = wave_max(in ? g.hmax : 0.0f);
+    if (lane == 0) {
+        Geo o;
+        o.cx = 0.5 * (lx + ux); o.cy = 0.5 * (ly + uy); o.cz = 0.5 * (lz + uz);
+        o.ex = f_up(fmax(ux - o.cx, o.cx - lx));
+        o.ey = f_up(fmax(uy - o.cy, o.cy - ly));
+        o.ez = f_up(fmax(uz - o.cz, o.cz - lz));
+        o.hmax = hm;
+        node[j] = o;
+    }
+}
+
+// hmax of tree nodes only (boxes unchanged).
+__global__ __launch_bounds__(256) void k_tree_hmax(const Hdr *hdr, int lev, const Geo *child,
+                                                   Geo *node, int64_t bound)
+{
+    int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (j >= bound || j >= hdr->nnode[lev]) return;
+    int lane = lane_id();
+    int64_t k = j * kFan + lane;
+    bool in = k < hdr->nnode[lev - 1];
+    float hm = wave_max(in ? child[k].hmax : 0.0f);
+    if (lane == 0) node[j].hmax = hm;
+}
+
+// Cells' hmax from a given h array.
+__global__ __launch_bounds__(256) void k_cell_hmax(const Hdr *hdr, const int32_t *cell_start,
+                                                   const double *h, Geo *cells, int64_t bound)
+{
+    int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= bound || c >= hdr->ncells) return;
+    int lane = lane_id();
+    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+    int64_t i = s0 + lane;
+    double hm = wave_max(i < s1 ? h[i] : 0.0);
+    if (lane == 0) cells[c].hmax = f_up(hm);
+}
+
+}  // namespace
+
+const Hdr *cell_hdr(apr_ctx *c) { return wsa<Hdr>(c, "cell_hdr", 1); }
+const int32_t *cell_start(apr_ctx *c)
+{
+    return wsa<int32_t>(c, "cell_start", (size_t)c->cells_bound + 1);
+}
+Geo *cell_level(apr_ctx *c, int lev)
+{
+    static const char *names[kMaxLev + 1] = {"geo0", "geo1", "geo2", "geo3", "geo4", "geo5",
+                                             "geo6"};
+    return wsa<Geo>(c, names[lev], (size_t)c->nnode_bound[lev] + 1);
+}
+
+int refit_hmax_from_cells(apr_ctx *c)
+{
+    Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
+    for (int k = 1; k <= c->nlev; ++k) {
+        int64_t b = c->nnode_bound[k];
+        hipLaunchKernelGGL(k_tree_hmax, dim3((unsigned)ceil_div(b, 4)), dim3(256), 0,
+                           c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k), b);
+    }
+    APR_LAUNCHED(c);
+    return APR_OK;
+}
+
+int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
+{
+    if (c->cells_n != n) return fail(c, APR_ERR_INVALID, "cells not built for this state");
+    Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
+    int64_t b = c->cells_bound;
+    hipLaunchKernelGGL(k_cell_hmax, dim3((unsigned)ceil_div(b, 4)), dim3(256), 0, c->stream,
+                       hdr, cell_start(c), h, cell_level(c, 0), b);
+    APR_LAUNCHED(c);
+    return refit_hmax_from_cells(c);
+}
+
+int build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
+{
+    int64_t n = s->n;
+    if (n <= 0) return fail(c, APR_ERR_INVALID, "empty state");
+    if (n >= (int64_t)1 << 31) return fail(c, APR_ERR_INVALID, "too many particles");
+    Box b = make_box(c->p);
+    int seglev = c->p.periodic ? 2 : 3;
+    int segshift = kKeyBits - 3 * seglev;
+    int nseg = 1 << (3 * seglev);
+    // bounds: every segment adds at most one partial cell
+    int64_t cb = ceil_div(n, kCell) + nseg;
+    c->cells_bound = cb;
+    int nlev = 0;
+    int64_t m = cb;
+    c->nnode_bound[0] = cb;
+    while (m > kFan) {
+        m = ceil_div(m, kFan);
+        nlev += 1;
+        c->nnode_bound[nlev] = m;
+    }
+    if (nlev > kMaxLev) return fail(c, APR_ERR_INVALID, "too many cells");
+    c->nlev = nlev;
+
+    uint32_t *keys = wsa<uint32_t>(c, "mkeys", (size_t)n);
+    uint32_t *vals = wsa<uint32_t>(c, "mvals", (size_t)n);
+    uint32_t *segcount = wsa<uint32_t>(c, "segcount", (size_t)nseg);
+    uint32_t *segstart = wsa<uint32_t>(c, "segstart", (size_t)nseg);
+    uint32_t *celloff = wsa<uint32_t>(c, "celloff", (size_t)nseg);
+    Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
+    int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)cb + 1);
+    if (!keys || !vals || !segcount || !segstart || !celloff || !hdr || !cs)
+        return fail(c, APR_ERR_HIP, "cell workspace");
+    unsigned g = (unsigned)ceil_div(n, 256);
+    hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, c->stream, s->x, s->y, s->z, n, b, keys,
+                       vals);
+    APR_LAUNCHED(c);
+    int rc = radix_sort_u32(c, keys, vals, n, kKeyBits);
+    if (rc) return rc;
+
+    // permute the state in place through temporaries
+    PermArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    double *arrs[12] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->h,
+                        s->ax, s->ay, s->az, s->dudt};
+    static const char *tn[12] = {"pt0", "pt1", "pt2", "pt3", "pt4", "pt5",
+                                 "pt6", "pt7", "pt8", "pt9", "pt10", "pt11"};
+    for (int k = 0; k < 12; ++k) {
+        if (!arrs[k]) continue;
+        pa.d[pa.nd] = arrs[k];
+        pa.dt[pa.nd] = wsa<double>(c, tn[pa.nd], (size_t)n);
+        if (!pa.dt[pa.nd]) return fail(c, APR_ERR_HIP, "permute workspace");
+        pa.nd += 1;
+    }
+    pa.lev = s->level;
+    pa.levt = wsa<int8_t>(c, "pt_lev", (size_t)n);
+    pa.id = s->id;
+    pa.idt = wsa<int64_t>(c, "pt_id", (size_t)n);
+    pa.perm = vals;
+    pa.perm_out = perm;
+    pa.n = n;
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, pa);
+    hipLaunchKernelGGL(k_scatter_back, dim3(g), dim3(256), 0, c->stream, pa);
+    APR_LAUNCHED(c);
+
+    rc = fill_u32(c, segcount, 0u, nseg);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
+                       segcount);
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, c->stream, segcount, nseg, n,
+                       segstart, celloff, hdr, cs, nlev);
+    hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
+                       segstart, celloff, cs);
+    APR_LAUNCHED(c);
+
+    Geo *cells = cell_level(c, 0);
+    if (c->p.precision == APR_FP32) {
+        float4 *pm = wsa<float4>(c, "pm32", (size_t)n);
+        hipLaunchKernelGGL(k_cell_geo<float>, dim3((unsigned)ceil_div(cb, 4)), dim3(256), 0,
+                           c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level, cells, pm, cb);
+    } else {
+        double4 *pm = wsa<double4>(c, "pm64", (size_t)n);
+        hipLaunchKernelGGL(k_cell_geo<double>, dim3((unsigned)ceil_div(cb, 4)), dim3(256), 0,
+                           c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level, cells, pm, cb);
+    }
+    APR_LAUNCHED(c);
+    for (int k = 1; k <= nlev; ++k) {
+        int64_t bk = c->nnode_bound[k];
+        hipLaunchKernelGGL(k_tree_level, dim3((unsigned)ceil_div(bk, 4)), dim3(256), 0,
+                           c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k), bk);
+    }
+    APR_LAUNCHED(c);
+    c->cells_n = n;
+    c->dens_n = -1;
+    c->force_n = -1;
+    return APR_OK;
+}
+
+}  // namespace apr

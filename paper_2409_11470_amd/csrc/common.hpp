@@ -1,0 +1,213 @@
+// Internal declarations shared by the translation units of libapr.so.
+// gfx950 only: wave64, 4 SIMD16 per CU, 160 KB LDS per CU, 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/apr.h"
+
+namespace apr {
+
+constexpr int kWave = 64;
+constexpr int kCell = 64;       // particles per leaf cell (one wavefront)
+constexpr int kFan = 64;        // tree fan-out (one wavefront tests all children)
+constexpr int kMaxLev = 6;      // tree levels above the cells
+constexpr int kNumXcd = 8;      // MI355X: workgroups go round-robin over 8 XCDs
+constexpr double kPi = 3.14159265358979323846;
+
+// Status words on the device (ctx->d_status).
+enum { ST_NOCONV = 0, ST_OVERFLOW = 1, ST_WORDS = 4 };
+
+// A leaf cell or a tree node: centre in FP64 and conservative (rounded-up)
+// FP32 half extents and largest smoothing length.
+struct Geo {
+    double cx, cy, cz;
+    float ex, ey, ez;
+    float hmax;
+};
+
+// Counts of the cell structure, written on the device by the cell build so
+// that no host synchronisation is needed; kernels sized by upper bounds read
+// it and retire surplus workgroups.
+struct Hdr {
+    int32_t ncells;
+    int32_t nnode[kMaxLev + 1];  // nnode[0] = ncells
+};
+
+struct Box {
+    double lo[3], L[3];
+    int periodic;
+};
+
+}  // namespace apr
+
+struct apr_ctx {
+    apr_params p;
+    hipStream_t stream = nullptr;
+    std::string err;
+    struct Buf {
+        std::string name;
+        void *p;
+        size_t bytes;
+    };
+    std::vector<Buf> bufs;
+    int32_t *d_status = nullptr;   // apr::ST_WORDS ints
+    int32_t *h_status = nullptr;   // pinned host copy
+    // cell structure of the last apr_build_cells
+    int64_t cells_n = -1;          // particles it was built for
+    int64_t cells_bound = 0;       // upper bound on the cell count
+    int nlev = 0;                  // tree levels above the cells
+    int64_t nnode_bound[apr::kMaxLev + 1] = {};
+    // derived values of the last density / force evaluation (workspace)
+    int64_t dens_n = -1;           // n of the last apr_density (for the split cap)
+    int64_t force_n = -1;          // n of the last force evaluation (for the timestep)
+};
+
+namespace apr {
+
+// Grow-only named device workspace.  Contents are not kept across growth.
+void *ws(apr_ctx *c, const char *name, size_t bytes);
+template <class T>
+T *wsa(apr_ctx *c, const char *name, size_t count)
+{
+    return static_cast<T *>(ws(c, name, count * sizeof(T) + 256));
+}
+
+int fail(apr_ctx *c, int code, const std::string &msg);
+int hip_check(apr_ctx *c, hipError_t e, const char *what);
+#define APR_HIP(ctx, call)                                        \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return apr::hip_check(ctx, e_, #call); \
+    } while (0)
+#define APR_LAUNCHED(ctx)                                                    \
+    do {                                                                     \
+        hipError_t e_ = hipGetLastError();                                   \
+        if (e_ != hipSuccess) return apr::hip_check(ctx, e_, "kernel launch"); \
+    } while (0)
+
+inline Box make_box(const apr_params &p)
+{
+    Box b;
+    for (int k = 0; k < 3; ++k) {
+        b.lo[k] = p.box_lo[k];
+        b.L[k] = p.box_hi[k] - p.box_lo[k];
+    }
+    b.periodic = p.periodic;
+    return b;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------- device side
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// XCD-aware mapping of a 1-D grid: workgroup b runs on XCD b % 8, so give XCD
+// k a contiguous range of work items (neighbouring cells share candidates and
+// hit the same L2).
+__device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb)
+{
+    int64_t per = (nb + kNumXcd - 1) / kNumXcd;
+    int64_t x = b % kNumXcd, r = b / kNumXcd;
+    int64_t full = nb % kNumXcd == 0 ? kNumXcd : nb % kNumXcd;  // XCDs with `per` items
+    // XCDs 0..full-1 own `per` items, the rest own per-1
+    int64_t base = x < full ? x * per : full * per + (x - full) * (per - 1);
+    return base + r;
+}
+
+// Minimum-image component of a displacement (periodic box of side L).
+__device__ inline double min_image(double d, double L, int periodic)
+{
+    if (periodic) {
+        if (d > 0.5 * L) d -= L;
+        else if (d < -0.5 * L) d += L;
+    }
+    return d;
+}
+
+// Squared gap between two boxes (centre, half extent); the centre difference
+// takes the minimum image.  Conservative for culling.
+__device__ inline double gap2(const Geo &a, const Geo &b, const Box &bx)
+{
+    double d[3] = {min_image(a.cx - b.cx, bx.L[0], bx.periodic),
+                   min_image(a.cy - b.cy, bx.L[1], bx.periodic),
+                   min_image(a.cz - b.cz, bx.L[2], bx.periodic)};
+    double e[3] = {(double)a.ex + (double)b.ex, (double)a.ey + (double)b.ey,
+                   (double)a.ez + (double)b.ez};
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double g = fabs(d[k]) - e[k];
+        if (g > 0.0) s += g * g;
+    }
+    return s;
+}
+
+// Round a non-negative double up to a float that is >= it.
+__device__ inline float f_up(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);  // next float up (v >= 0)
+    return f;
+}
+
+template <class T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+template <class T>
+using vec4_t = typename Vec4<T>::type;
+
+// ------------------------------------------------------------ host launchers
+// sort.hip
+int exclusive_scan_u32(apr_ctx *c, const uint32_t *in, uint32_t *out, int64_t n,
+                       uint32_t *total_dev);
+int exclusive_scan_i64(apr_ctx *c, const int64_t *in, int64_t *out, int64_t n,
+                       int64_t *total_dev);
+int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits);
+
+// cells.hip
+int build_cells(apr_ctx *c, apr_state *s, int64_t *perm);
+int refit_hmax_from_cells(apr_ctx *c);   // tree nodes' hmax from the cells' hmax
+int cells_hmax_from(apr_ctx *c, const double *h, int64_t n);  // cells' hmax from h, then refit
+const Hdr *cell_hdr(apr_ctx *c);
+const int32_t *cell_start(apr_ctx *c);
+Geo *cell_level(apr_ctx *c, int lev);
+
+// density.hip / forces.hip
+int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters);
+int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
+           void *ay, void *az, void *dudt, void *vsig);
+
+// neighbours.hip
+int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_t *counts,
+               int64_t *offsets, int64_t *list, int64_t cap, int64_t *total);
+
+// integrate.hip
+int kick(apr_ctx *c, apr_state *s, double dt);
+int drift(apr_ctx *c, apr_state *s, double dt);
+int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
+                const void *dudt, const apr_sink *sinks, int nsinks);
+int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, double *dt);
+
+// splitmerge.hip
+int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
+                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare);
+
+// fill helpers (kernels, so that they can sit inside captured graphs)
+int fill_i32(apr_ctx *c, int32_t *p, int32_t v, int64_t n);
+int fill_u32(apr_ctx *c, uint32_t *p, uint32_t v, int64_t n);
+
+}  // namespace apr

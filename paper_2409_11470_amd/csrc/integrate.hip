@@ -1,0 +1,177 @@
+// Kick-drift-kick leapfrog (FP64), point-mass (sink) gravity and the Courant
+// timestep.  The paper integrates with its host code's individual-timestep
+// scheme; this is the standard global-step KDK.
+#include "common.hpp"
+
+namespace apr {
+
+namespace {
+
+__global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, double *u,
+                       const double *ax, const double *ay, const double *az,
+                       const double *dudt, double dt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    vx[i] += dt * ax[i];
+    vy[i] += dt * ay[i];
+    vz[i] += dt * az[i];
+    if (u && dudt) u[i] += dt * dudt[i];
+}
+
+__global__ void k_drift(int64_t n, double *x, double *y, double *z, const double *vx,
+                        const double *vy, const double *vz, double dt, Box b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double *p[3] = {x, y, z};
+    const double *v[3] = {vx, vy, vz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double xn = p[k][i] + dt * v[k][i];
+        if (b.periodic) {
+            double hi = b.lo[k] + b.L[k];
+            if (xn >= hi) xn -= b.L[k];
+            else if (xn < b.lo[k]) xn += b.L[k];
+        }
+        p[k][i] = xn;
+    }
+}
+
+constexpr int kMaxSinks = 16;
+struct Sinks {
+    int n;
+    double G;
+    double x[kMaxSinks][3], m[kMaxSinks], eps2[kMaxSinks];
+};
+
+template <class T>
+__global__ void k_total_accel(int64_t n, const double *x, const double *y, const double *z,
+                              const T *hax, const T *hay, const T *haz, const T *hdu, Sinks S,
+                              double *ax, double *ay, double *az, double *dudt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double gx = (double)hax[i], gy = (double)hay[i], gz = (double)haz[i];
+    for (int s = 0; s < S.n; ++s) {
+        double dx = x[i] - S.x[s][0], dy = y[i] - S.x[s][1], dz = z[i] - S.x[s][2];
+        double d2 = dx * dx + dy * dy + dz * dz + S.eps2[s];
+        double inv3 = 1.0 / (d2 * sqrt(d2));
+        double f = S.G * S.m[s] * inv3;
+        gx -= f * dx;
+        gy -= f * dy;
+        gz -= f * dz;
+    }
+    ax[i] = gx;
+    ay[i] = gy;
+    az[i] = gz;
+    if (dudt) dudt[i] = (double)hdu[i];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_dt_partial(int64_t n, const double *h, const T *vsig,
+                                                    double *part)
+{
+    __shared__ double s[256];
+    double m = __builtin_huge_val();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double v = (double)vsig[i];
+        if (v > 0.0) m = fmin(m, h[i] / v);
+    }
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, double *out)
+{
+    __shared__ double s[256];
+    double m = __builtin_huge_val();
+    for (int i = threadIdx.x; i < np; i += 256) m = fmin(m, part[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+}  // namespace
+
+int kick(apr_ctx *c, apr_state *s, double dt)
+{
+    if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
+    int64_t n = s->n;
+    double *u = c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
+    hipLaunchKernelGGL(k_kick, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, n,
+                       s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt, dt);
+    APR_LAUNCHED(c);
+    return APR_OK;
+}
+
+int drift(apr_ctx *c, apr_state *s, double dt)
+{
+    int64_t n = s->n;
+    hipLaunchKernelGGL(k_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, n,
+                       s->x, s->y, s->z, s->vx, s->vy, s->vz, dt, make_box(c->p));
+    APR_LAUNCHED(c);
+    c->cells_n = -1;
+    return APR_OK;
+}
+
+int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
+                const void *dudt, const apr_sink *sinks, int nsinks)
+{
+    if (nsinks < 0 || nsinks > kMaxSinks) return fail(c, APR_ERR_INVALID, "too many sinks");
+    if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
+    Sinks S;
+    std::memset(&S, 0, sizeof(S));
+    S.n = nsinks;
+    S.G = c->p.G;
+    for (int k = 0; k < nsinks; ++k) {
+        for (int d = 0; d < 3; ++d) S.x[k][d] = sinks[k].x[d];
+        S.m[k] = sinks[k].m;
+        S.eps2[k] = sinks[k].eps * sinks[k].eps;
+    }
+    int64_t n = s->n;
+    unsigned g = (unsigned)ceil_div(n, 256);
+    if (c->p.precision == APR_FP32)
+        hipLaunchKernelGGL(k_total_accel<float>, dim3(g), dim3(256), 0, c->stream, n, s->x, s->y,
+                           s->z, (const float *)ax, (const float *)ay, (const float *)az,
+                           (const float *)dudt, S, s->ax, s->ay, s->az, s->dudt);
+    else
+        hipLaunchKernelGGL(k_total_accel<double>, dim3(g), dim3(256), 0, c->stream, n, s->x,
+                           s->y, s->z, (const double *)ax, (const double *)ay,
+                           (const double *)az, (const double *)dudt, S, s->ax, s->ay, s->az,
+                           s->dudt);
+    APR_LAUNCHED(c);
+    return APR_OK;
+}
+
+int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, double *dt)
+{
+    int64_t n = s->n;
+    int np = (int)std::min<int64_t>(1024, ceil_div(n, 256));
+    double *part = wsa<double>(c, "dt_part", (size_t)np + 1);
+    double *out = part + np;
+    if (c->p.precision == APR_FP32)
+        hipLaunchKernelGGL(k_dt_partial<float>, dim3(np), dim3(256), 0, c->stream, n, s->h,
+                           (const float *)vsig, part);
+    else
+        hipLaunchKernelGGL(k_dt_partial<double>, dim3(np), dim3(256), 0, c->stream, n, s->h,
+                           (const double *)vsig, part);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, c->stream, part, np, out);
+    APR_LAUNCHED(c);
+    double v = 0.0;
+    APR_HIP(c, hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    *dt = C * v;
+    return APR_OK;
+}
+
+}  // namespace apr

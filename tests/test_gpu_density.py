@@ -1,0 +1,85 @@
+"""GPU density / h-rho Newton vs the FP64 oracle, element by element (per
+particle id) on the same seeded inputs.  Tolerances: relative error of rho,
+h and Omega below 1e-5 for the FP64 form and 1e-3 for the FP32 form."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _gpu import gpu_density, oracle_density, sample_balls
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-5, "fp32": 1e-3}
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b) / np.abs(b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattice_box(prec):
+    st, p = W.lattice_box()
+    g, *_ = gpu_density(st, p, prec)
+    o = oracle_density(st, p)
+    assert g["failures"] == 0
+    assert np.array_equal(g["nneigh"], o["nneigh"])
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k], o[k]) < TOL[prec], k
+    if prec == "fp64":
+        assert _rel(g["rho"], o["rho"]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nside", [23, 17])
+def test_jittered_mixed_mass_box(prec, nside):
+    # several tiles and a ragged tail (23^3 = 12167, 17^3 = 4913 particles)
+    st, p = W.shock_box(nside=nside)
+    p = dict(p, m0=1.0 / nside ** 3)
+    g, *_ = gpu_density(st, p, prec)
+    o = oracle_density(st, p)
+    assert g["failures"] == 0 and o["failures"] == 0
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k], o[k]) < TOL[prec], k
+    if prec == "fp64":
+        assert np.mean(g["nneigh"] == o["nneigh"]) > 0.999
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_disc(prec):
+    st, p = W.planet_disc(n=20000)
+    g, *_ = gpu_density(st, p, prec)
+    o = oracle_density(st, p)
+    ok = o["failures"] == 0
+    assert ok and g["failures"] == 0
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k], o[k]) < TOL[prec], k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_box_sampled(prec):
+    # 64^3 = 262144 particles, the benchmarked workload; the oracle solves
+    # 4 balls of 64 targets
+    st, p = W.shock_box()
+    g, *_ = gpu_density(st, p, prec)
+    assert g["failures"] == 0
+    tg, _ = sample_balls(st, p, 4, 64, seed=11, hscale=1.2 / 64)
+    o = oracle_density(st, p, targets=tg)
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k][tg], o[k]) < TOL[prec], k
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 130])
+def test_tiny_sets(n):
+    # degenerate sizes: one partial cell, exactly one cell, one more
+    st, dx = W.random_cluster(n, seed_k=200 + n)
+    p = dict(m0=1.0, periodic=False, lo=(-1, -1, -1), hi=(2, 2, 2))
+    g, *_ = gpu_density(st, p, "fp64")
+    o = oracle_density(st, p)
+    if n == 1:
+        # a lone particle has no h-rho solution: both report non-convergence
+        assert o["failures"] == 1 and g["failures"] == 1
+        return
+    assert g["failures"] == o["failures"]
+    conv = o["iters"] < 60
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k][conv], o[k][conv]) < 1e-5, k
