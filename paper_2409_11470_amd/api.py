@@ -250,10 +250,13 @@ def apr_timestep(ctx, st, C_cfl=0.3):
     return dt.value
 
 
-def apr_sync_status(ctx):
-    """Returns the number of unconverged h-rho solves; raises AprError on a flag."""
+def apr_sync_status(ctx, raise_noconverge=True):
+    """Waits for the stream; returns the number of unconverged h-rho solves.
+    Raises AprError on any flag (non-convergence only if raise_noconverge)."""
     cnt = C.c_int64()
     rc = lib().apr_sync_status(ctx.ptr, C.byref(cnt))
+    if rc == 3 and not raise_noconverge:
+        return cnt.value
     if rc != 0:
         raise AprError(rc, ctx.error())
     return cnt.value

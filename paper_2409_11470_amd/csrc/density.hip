@@ -33,7 +33,7 @@ template <class T>
 struct StageCap;
 template <>
 struct StageCap<float> {
-    static constexpr int value = 1792;
+    static constexpr int value = 2560;
 };
 template <>
 struct StageCap<double> {
@@ -72,16 +72,53 @@ __device__ inline void m4_fg(T q, T &f, T &g)
     g = inner ? gi : go;
 }
 
+// Per-lane partial sums of one Newton evaluation.
+template <class T>
+struct DSum {
+    Acc<T> w, d;   // sum m f, sum m (3f + q f')
+    int nn, nzero;
+    T dmin;
+    __device__ void zero()
+    {
+        w.zero();
+        d.zero();
+        nn = 0;
+        nzero = 0;
+        dmin = T(3.0e38);
+    }
+    __device__ void pair(T dx, T dy, T dz, T m, T R2, T hinv)
+    {
+        T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < R2) {
+            T r = sqrt(r2);
+            T f, g;
+            m4_fg<T>(r * hinv, f, g);
+            w.add(m * f);
+            d.add(m * g);
+            nn += 1;
+            if (r2 > T(0)) dmin = dmin < r ? dmin : r;
+            else nzero += 1;
+        }
+    }
+    __device__ void reduce16()
+    {
+        w.reduce16();
+        d.reduce16();
+        nn = wsum16(nn);
+        nzero = wsum16(nzero);
+        dmin = wmin16(dmin);
+    }
+};
+
 template <class T>
 __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
 {
     using V = vec4_t<T>;
     constexpr int STAGE = StageCap<T>::value;
-    constexpr int Q = STAGE / kWaves;
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V stg[STAGE];
     __shared__ uint16_t sub[kWaves][kSubCap];
-    __shared__ int s_ncand, s_nstg[kWaves], s_ovf;
+    __shared__ int s_ncand, s_nstg, s_direct, s_ovf;
     __shared__ double s_red[kWaves];
 
     const Tree &tr = a.tree;
@@ -93,7 +130,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
     const int w = threadIdx.x / kWave, lane = lane_id(), grp = lane >> 4, j = lane & 15;
     if (threadIdx.x == 0) s_ovf = 0;
 
-    // per lane: the 4 targets of its group in the wave's 4 sub-blocks
+    // per lane: the target of its group in each of the wave's 4 sub-blocks
     double hreg[4];
     int itc[4];
     bool done[4];
@@ -117,8 +154,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
     double R = 0.0;
     for (int k = 0; k < kWaves; ++k) R = fmax(R, s_red[k]);
     R *= 2.0 * (double)kSigma;
-    const T m0pi = T(a.m0 / kPi);
-    (void)m0pi;
+    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
 
     // each new search follows at least one Newton step of a pending target,
     // so max_iter + 1 rounds always finish every target
@@ -133,18 +169,16 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
             }
         }
         __syncthreads();
-        // ---- 2. stage candidates within R of the target cell box
-        {
-            int nc = s_ncand;
-            int nw = 0;
-            const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
-            const T R2 = (T)(R * R);
+        const int nc = s_ncand;
+        const T R2c = (T)(R * R);
+        // ---- 2. stage candidates within R of the target cell box: count, scan, write
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1 && s_direct) break;
             for (int ci = w; ci < nc; ci += kWaves) {
                 int cc = sA[ci];
-                Geo g = tr.lev[0][cc];
                 int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
                 double sh[3];
-                cell_shift(g, tg, tr.box, sh);
+                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
                 bool hit = false;
                 V p;
                 if (lane < bn) {
@@ -152,20 +186,29 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
                     p.x = p.x + (T)sh[0];
                     p.y = p.y + (T)sh[1];
                     p.z = p.z + (T)sh[2];
-                    hit = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez) < R2;
+                    hit = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez) < R2c;
                 }
                 uint64_t m = __ballot(hit);
-                int pos = nw + __popcll(m & lanemask_lt());
-                if (hit && pos < Q) stg[w * Q + pos] = p;
-                nw += __popcll(m);
+                if (pass == 0) {
+                    if (lane == 0) sB[ci] = __popcll(m);
+                } else if (hit) {
+                    stg[sB[ci] + __popcll(m & lanemask_lt())] = p;
+                }
             }
-            if (nw > Q) {
-                nw = Q;
-                if (lane == 0) s_ovf = 1;
+            __syncthreads();
+            if (pass == 0) {
+                if (w == 0) {
+                    int tot = wave_excl_scan_lds(sB, nc);
+                    if (lane == 0) {
+                        s_nstg = tot;
+                        s_direct = tot > STAGE;
+                    }
+                }
+                __syncthreads();
             }
-            if (lane == 0) s_nstg[w] = nw;
         }
-        __syncthreads();
+        const bool direct = s_direct;
+        const int nstg = s_nstg;
 
         // ---- 3. per sub-block: candidate list, Newton
         double needR = 0.0;
@@ -187,74 +230,69 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
             double h = hreg[sb];
             double ma = valid ? a.m0 * (double)tp.w : 0.0;
 
-            bool need_list = true;
+            bool need_list = true, sub_direct = direct;
             double Rs = 0.0;
             int nsub = 0;
             while (true) {
                 if (need_list) {
                     double hm = wmax_groups(done[sb] ? 0.0 : h);
                     Rs = 2.0 * (double)kSigma * hm;
-                    if (Rs > R) {  // staged set too small: search again
+                    if (Rs > R) {  // candidate set too small: search again
                         needR = fmax(needR, Rs);
                         break;
                     }
-                    // list the staged candidates within Rs of the sub-block box
-                    T Rs2 = (T)(Rs * Rs);
-                    nsub = 0;
-                    wave_sync();  // the previous list is no longer read
-                    for (int r = 0; r < kWaves; ++r) {
-                        int nr = s_nstg[r];
-                        for (int base = 0; base < nr; base += kWave) {
+                    sub_direct = direct;
+                    if (!direct) {
+                        // list the staged candidates within Rs of the sub-block box
+                        T Rs2 = (T)(Rs * Rs);
+                        nsub = 0;
+                        wave_sync();  // the previous list is no longer read
+                        for (int base = 0; base < nstg; base += kWave) {
                             int idx = base + lane;
                             bool hit = false;
-                            if (idx < nr) {
-                                V p = stg[r * Q + idx];
+                            if (idx < nstg) {
+                                V p = stg[idx];
                                 hit = pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez) < Rs2;
                             }
                             uint64_t m = __ballot(hit);
                             int pos = nsub + __popcll(m & lanemask_lt());
-                            if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)(r * Q + idx);
+                            if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)idx;
                             nsub += __popcll(m);
                         }
+                        if (nsub > kSubCap) sub_direct = true;
+                        wave_sync();
                     }
-                    if (nsub > kSubCap) {
-                        nsub = kSubCap;
-                        if (lane == 0) s_ovf = 1;
-                    }
-                    wave_sync();
                     need_list = false;
                 }
-                // one Newton sum for the 4 targets
+                // one Newton evaluation for the 4 targets
                 T hf = (T)h;
                 T hinv = T(1) / hf;
                 T R2 = T(4) * hf * hf;
-                Acc<T> sw, sd;
-                sw.zero();
-                sd.zero();
-                int nn = 0, nzero = 0;
-                T dmin = T(3.0e38);
-                for (int k = j; k < nsub; k += kGroup) {
-                    V p = stg[sub[w][k]];
-                    T dx = tp.x - p.x, dy = tp.y - p.y, dz = tp.z - p.z;
-                    T r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < R2) {
-                        T r = sqrt(r2);
-                        T f, g;
-                        m4_fg<T>(r * hinv, f, g);
-                        sw.add(p.w * f);
-                        sd.add(p.w * g);
-                        nn += 1;
-                        if (r2 > T(0)) dmin = dmin < r ? dmin : r;
-                        else nzero += 1;
+                DSum<T> S;
+                S.zero();
+                if (!sub_direct) {
+                    for (int k = j; k < nsub; k += kGroup) {
+                        V p = stg[sub[w][k]];
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                    }
+                } else {
+                    // from global memory: every particle of every candidate cell
+                    for (int ci = 0; ci < nc; ++ci) {
+                        int cc = sA[ci];
+                        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+                        double sh[3];
+                        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                        T sx = (T)sh[0], sy = (T)sh[1], sz = (T)sh[2];
+                        for (int k = j; k < bn; k += kGroup) {
+                            V p = a.pm[b0 + k];
+                            S.pair(tp.x - (p.x + sx), tp.y - (p.y + sy), tp.z - (p.z + sz), p.w,
+                                   R2, hinv);
+                        }
                     }
                 }
-                sw.reduce16();
-                sd.reduce16();
-                nn = wsum16(nn);
-                nzero = wsum16(nzero);
-                dmin = wmin16(dmin);
+                S.reduce16();
                 // FP64 Newton step (all 16 lanes of a group agree)
-                double W = sw.value(), D = sd.value();
+                double W = S.w.value(), D = S.d.value();
                 double hh = (double)hf;
                 double rhos = a.m0 * W / (kPi * hh * hh * hh);
                 double drho = -a.m0 * D / (kPi * hh * hh * hh * hh);
@@ -274,11 +312,11 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
                             a.h[i] = hh;
                             a.rho[i] = (T)rhos;
                             a.omega[i] = (T)(1.0 - D / (3.0 * W));
-                            if (a.nneigh) a.nneigh[i] = nn;
+                            if (a.nneigh) a.nneigh[i] = S.nn;
                             if (a.iters) a.iters[i] = itc[sb];
                             if (a.dnn)
-                                a.dnn[i] = nzero >= 2 ? T(0)
-                                           : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
+                                a.dnn[i] = S.nzero >= 2 ? T(0)
+                                           : (S.dmin >= T(3.0e38) ? T(__builtin_huge_val()) : S.dmin);
                             if (!conv) atomicAdd(&a.status[ST_NOCONV], 1);
                         }
                         hreg[sb] = hh;

@@ -23,11 +23,11 @@ template <class T>
 struct FStageCap;
 template <>
 struct FStageCap<float> {
-    static constexpr int value = 1280;
+    static constexpr int value = 1024;
 };
 template <>
 struct FStageCap<double> {
-    static constexpr int value = 1024;
+    static constexpr int value = 512;
 };
 
 // Per particle: vh = (vx, vy, vz, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0).
@@ -83,17 +83,51 @@ __device__ inline T m4_df(T q)
     return q < T(1) ? in : out;
 }
 
+// Per-lane partial sums of the force on one target.
+template <class T>
+struct FSum {
+    Acc<T> x, y, z, u;
+    T vs;
+    // target data
+    T tx, ty, tz, tvx, tvy, tvz, ha_inv2, ha_inv4, ha_inv, Pa, Ga, ca, alpha, beta;
+    __device__ void pair(T dx, T dy, T dz, T mb, const vec4_t<T> &v, const vec4_t<T> &tb)
+    {
+        T r2 = dx * dx + dy * dy + dz * dz;
+        T hb_inv2 = v.w * v.w;
+        bool ina = r2 * ha_inv2 < T(4);
+        bool inb = r2 * hb_inv2 < T(4);
+        if ((ina || inb) && r2 > T(0)) {
+            T rinv = T(1) / sqrt(r2);
+            T r = r2 * rinv;
+            T Fa = ina ? m4_df<T>(r * ha_inv) * ha_inv4 : T(0);
+            T Fb = inb ? m4_df<T>(r * v.w) * (hb_inv2 * hb_inv2) : T(0);
+            T vdr = ((tvx - v.x) * dx + (tvy - v.y) * dy + (tvz - v.z) * dz) * rinv;
+            T A = Pa, B = tb.x;
+            if (vdr < T(0)) {
+                T vsa = alpha * ca - beta * vdr;
+                T vsb = alpha * tb.z - beta * vdr;
+                A = Pa - T(0.5) * Ga * vsa * vdr;
+                B = tb.x - T(0.5) * tb.y * vsb * vdr;
+                vs = vs > vsa ? vs : vsa;
+            }
+            T term = mb * (A * Fa + B * Fb) * rinv;
+            x.add(-term * dx);
+            y.add(-term * dy);
+            z.add(-term * dz);
+            u.add(mb * A * vdr * Fa);
+        }
+    }
+};
+
 template <class T>
 __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
 {
     using V = vec4_t<T>;
     constexpr int STAGE = FStageCap<T>::value;
-    constexpr int Q = STAGE / kWaves;
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V spm[STAGE], svh[STAGE], sth[STAGE];
     __shared__ uint16_t sub[kWaves][kSubCap];
-    __shared__ int s_ncand, s_nstg[kWaves], s_ovf;
-    __shared__ float s_red[kWaves];
+    __shared__ int s_ncand, s_nstg, s_direct, s_ovf;
 
     const Tree &tr = a.tree;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -102,7 +136,6 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
     const int w = threadIdx.x / kWave, lane = lane_id(), grp = lane >> 4, j = lane & 15;
-    if (threadIdx.x == 0) s_ovf = 0;
     const double R = 2.0 * (double)tg.hmax;  // targets' own supports
 
     if (w == 0) {
@@ -114,48 +147,55 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
         }
     }
     __syncthreads();
-    // stage candidates b within max(R, 2 h_b) of the target cell box
+    const int nc = s_ncand;
+    // stage candidates b within max(R, 2 h_b) of the target cell box: count, scan, write
     {
-        int nc = s_ncand;
-        int nw = 0;
         const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
         const T R2 = (T)(R * R);
-        for (int ci = w; ci < nc; ci += kWaves) {
-            int cc = sA[ci];
-            Geo g = tr.lev[0][cc];
-            int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-            double sh[3];
-            cell_shift(g, tg, tr.box, sh);
-            bool hit = false;
-            V p, v, t;
-            if (lane < bn) {
-                p = a.pm[b0 + lane];
-                v = a.vh[b0 + lane];
-                t = a.th[b0 + lane];
-                p.x = p.x + (T)sh[0];
-                p.y = p.y + (T)sh[1];
-                p.z = p.z + (T)sh[2];
-                T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
-                hit = d2 < R2 || d2 * v.w * v.w < T(4);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1 && s_direct) break;
+            for (int ci = w; ci < nc; ci += kWaves) {
+                int cc = sA[ci];
+                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+                double sh[3];
+                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                bool hit = false;
+                V p, v;
+                if (lane < bn) {
+                    p = a.pm[b0 + lane];
+                    v = a.vh[b0 + lane];
+                    p.x = p.x + (T)sh[0];
+                    p.y = p.y + (T)sh[1];
+                    p.z = p.z + (T)sh[2];
+                    T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
+                    hit = d2 < R2 || d2 * v.w * v.w < T(4);
+                }
+                uint64_t m = __ballot(hit);
+                if (pass == 0) {
+                    if (lane == 0) sB[ci] = __popcll(m);
+                } else if (hit) {
+                    int pos = sB[ci] + __popcll(m & lanemask_lt());
+                    spm[pos] = p;
+                    svh[pos] = v;
+                    sth[pos] = a.th[b0 + lane];
+                }
             }
-            uint64_t m = __ballot(hit);
-            int pos = nw + __popcll(m & lanemask_lt());
-            if (hit && pos < Q) {
-                spm[w * Q + pos] = p;
-                svh[w * Q + pos] = v;
-                sth[w * Q + pos] = t;
+            __syncthreads();
+            if (pass == 0) {
+                if (w == 0) {
+                    int tot = wave_excl_scan_lds(sB, nc);
+                    if (lane == 0) {
+                        s_nstg = tot;
+                        s_direct = tot > STAGE;
+                    }
+                }
+                __syncthreads();
             }
-            nw += __popcll(m);
         }
-        if (nw > Q) {
-            nw = Q;
-            if (lane == 0) s_ovf = 1;
-        }
-        if (lane == 0) s_nstg[w] = nw;
     }
-    __syncthreads();
+    const bool direct = s_direct;
+    const int nstg = s_nstg;
 
-    const T alpha = (T)a.alpha, beta = (T)a.beta;
     for (int sb = 0; sb < 4; ++sb) {
         int t = 16 * w + 4 * sb + grp;
         bool valid = t < cnt;
@@ -167,8 +207,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
             tt = a.th[s0 + t];
         } else {
             tp.x = tp.y = tp.z = tp.w = T(0);
-            tv.x = tv.y = tv.z = T(0);
-            tv.w = T(0);
+            tv.x = tv.y = tv.z = tv.w = T(0);
             tt.x = tt.y = tt.z = tt.w = T(0);
         }
         T bigT = T(3.0e38);
@@ -183,89 +222,75 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
         T Rs = T(2) / hmin_inv;
         T Rs2 = Rs * Rs;
         int nsub = 0;
-        wave_sync();  // the previous sub-block's list is no longer read
-        for (int r = 0; r < kWaves; ++r) {
-            int nr = s_nstg[r];
-            for (int base = 0; base < nr; base += kWave) {
+        bool sub_direct = direct;
+        if (!direct) {
+            wave_sync();  // the previous sub-block's list is no longer read
+            for (int base = 0; base < nstg; base += kWave) {
                 int idx = base + lane;
                 bool hit = false;
-                if (idx < nr) {
-                    V p = spm[r * Q + idx];
-                    T hb_inv = svh[r * Q + idx].w;
+                if (idx < nstg) {
+                    V p = spm[idx];
+                    T hb_inv = svh[idx].w;
                     T d2 = pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez);
                     hit = d2 < Rs2 || d2 * hb_inv * hb_inv < T(4);
                 }
                 uint64_t m = __ballot(hit);
                 int pos = nsub + __popcll(m & lanemask_lt());
-                if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)(r * Q + idx);
+                if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)idx;
                 nsub += __popcll(m);
             }
+            if (nsub > kSubCap) sub_direct = true;
+            wave_sync();
         }
-        if (nsub > kSubCap) {
-            nsub = kSubCap;
-            if (lane == 0) s_ovf = 1;
-        }
-        wave_sync();
 
-        const T ha_inv = tv.w;
-        const T ha_inv2 = ha_inv * ha_inv;
-        const T ha_inv4 = ha_inv2 * ha_inv2;
-        const T Pa = tt.x, Ga = tt.y, ca = tt.z;
-        Acc<T> sx, sy, sz, su;
-        sx.zero();
-        sy.zero();
-        sz.zero();
-        su.zero();
-        T vs = alpha * ca;
-        for (int k = j; k < nsub; k += kGroup) {
-            int e = sub[w][k];
-            V p = spm[e];
-            T dx = tp.x - p.x, dy = tp.y - p.y, dz = tp.z - p.z;
-            T r2 = dx * dx + dy * dy + dz * dz;
-            V v = svh[e];
-            T hb_inv2 = v.w * v.w;
-            bool ina = r2 * ha_inv2 < T(4);
-            bool inb = r2 * hb_inv2 < T(4);
-            if ((ina || inb) && r2 > T(0)) {
-                V tb = sth[e];
-                T rinv = T(1) / sqrt(r2);
-                T r = r2 * rinv;
-                T Fa = ina ? m4_df<T>(r * ha_inv) * ha_inv4 : T(0);
-                T Fb = inb ? m4_df<T>(r * v.w) * (hb_inv2 * hb_inv2) : T(0);
-                T vdr = ((tv.x - v.x) * dx + (tv.y - v.y) * dy + (tv.z - v.z) * dz) * rinv;
-                T A = Pa, B = tb.x;
-                if (vdr < T(0)) {
-                    T vsa = alpha * ca - beta * vdr;
-                    T vsb = alpha * tb.z - beta * vdr;
-                    A = Pa - T(0.5) * Ga * vsa * vdr;
-                    B = tb.x - T(0.5) * tb.y * vsb * vdr;
-                    vs = vs > vsa ? vs : vsa;
+        FSum<T> S;
+        S.x.zero(); S.y.zero(); S.z.zero(); S.u.zero();
+        S.alpha = (T)a.alpha;
+        S.beta = (T)a.beta;
+        S.tx = tp.x; S.ty = tp.y; S.tz = tp.z;
+        S.tvx = tv.x; S.tvy = tv.y; S.tvz = tv.z;
+        S.ha_inv = tv.w;
+        S.ha_inv2 = tv.w * tv.w;
+        S.ha_inv4 = S.ha_inv2 * S.ha_inv2;
+        S.Pa = tt.x; S.Ga = tt.y; S.ca = tt.z;
+        S.vs = S.alpha * S.ca;
+        if (!sub_direct) {
+            for (int k = j; k < nsub; k += kGroup) {
+                int e = sub[w][k];
+                V p = spm[e];
+                S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, svh[e], sth[e]);
+            }
+        } else {
+            for (int ci = 0; ci < nc; ++ci) {
+                int cc = sA[ci];
+                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+                double sh[3];
+                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                T sx = (T)sh[0], sy = (T)sh[1], sz = (T)sh[2];
+                for (int k = j; k < bn; k += kGroup) {
+                    V p = a.pm[b0 + k];
+                    S.pair(tp.x - (p.x + sx), tp.y - (p.y + sy), tp.z - (p.z + sz), p.w,
+                           a.vh[b0 + k], a.th[b0 + k]);
                 }
-                T term = p.w * (A * Fa + B * Fb) * rinv;
-                sx.add(-term * dx);
-                sy.add(-term * dy);
-                sz.add(-term * dz);
-                su.add(p.w * A * vdr * Fa);
             }
         }
-        sx.reduce16();
-        sy.reduce16();
-        sz.reduce16();
-        su.reduce16();
-        vs = wmax16(vs);
+        S.x.reduce16();
+        S.y.reduce16();
+        S.z.reduce16();
+        S.u.reduce16();
+        T vs = wmax16(S.vs);
         if (valid && j == 0) {
             double sc = a.m0 / kPi;
             int64_t i = s0 + t;
-            a.ax[i] = (T)(sc * sx.value());
-            a.ay[i] = (T)(sc * sy.value());
-            a.az[i] = (T)(sc * sz.value());
-            a.dudt[i] = (T)(sc * su.value());
+            a.ax[i] = (T)(sc * S.x.value());
+            a.ay[i] = (T)(sc * S.y.value());
+            a.az[i] = (T)(sc * S.z.value());
+            a.dudt[i] = (T)(sc * S.u.value());
             if (a.vsig) a.vsig[i] = vs;
         }
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_ovf) atomicOr(&a.status[ST_OVERFLOW], 1);
-    (void)s_red;
 }
 
 }  // namespace

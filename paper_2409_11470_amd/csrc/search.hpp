@@ -8,11 +8,14 @@
 //  2. stage: the candidate cells' particles that can interact with the target
 //     cell are copied to LDS, with positions moved into the target cell's
 //     frame (FP64 cell-centre difference, minimum image, rounded once to the
-//     pair precision).  Wave w stages candidate cells w, w+4, ... into its own
-//     LDS region, so the order is fixed.
+//     pair precision).  Counted per candidate cell first, then written at the
+//     prefix offsets, so the staged order is the candidate order (fixed).
 //  3. sub-block lists: the 64 targets form 16 sub-blocks of 4; a wavefront
 //     serves one sub-block at a time with 16 lanes per target, and the staged
 //     candidates that can reach the sub-block are listed (u16 LDS indices).
+//  If the staged set or a sub-block list does not fit in LDS, that work reads
+//  the candidate cells straight from global memory instead (same arithmetic,
+//  slower), so no capacity limit changes a result.
 #pragma once
 
 #include "common.hpp"
@@ -21,7 +24,7 @@ namespace apr {
 
 constexpr int kSearchThreads = 256;
 constexpr int kWaves = kSearchThreads / kWave;
-constexpr int kCandCap = 512;    // candidate cells per target cell
+constexpr int kCandCap = 1024;   // candidate cells per target cell
 constexpr int kSubCap = 512;     // staged candidates per sub-block
 constexpr int kGroup = 16;       // lanes per target
 
@@ -102,6 +105,27 @@ __device__ inline int traverse(const Tree &t, const Geo &tg, double R, bool sym,
         wave_sync();
     }
     return nf;
+}
+
+// In-place exclusive prefix sum of cnt[0..n) by one wavefront; returns the total.
+__device__ inline int wave_excl_scan_lds(int32_t *cnt, int n)
+{
+    int lane = lane_id();
+    int carry = 0;
+    for (int base = 0; base < n; base += kWave) {
+        int i = base + lane;
+        int v = i < n ? cnt[i] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            int t = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += t;
+        }
+        if (i < n) cnt[i] = carry + incl - v;
+        carry += __shfl(incl, kWave - 1, kWave);
+    }
+    wave_sync();
+    return carry;
 }
 
 // Centre difference (candidate cell - target cell), minimum image, in FP64.
