@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the APR-SPH hot path on one MI355X.
+
+Metric: SPH pair interactions per second (density + force), FP32 form vs FP64
+form.  Workload: the 64^3 = 262144-particle periodic box (jittered lattice,
+left/right states rho/P = 1/1 and 0.125/0.1 carried by masses of levels 0 and
+3, adiabatic gamma = 5/3, artificial viscosity alpha = 1, beta = 2), stepped
+with the kick-drift-kick leapfrog at the fixed dt = 0.3 min(h / vsig) of t = 0.
+
+A step is one full pass of the library's step: kick, drift, cell build
+(Morton sort + cells + tree), density with its h-rho Newton iteration, EOS,
+forces, kick.  The box has no refinement zone, so its step contains no
+split/merge pass.  Interactions per step = sum_a |{b != a: r < 2 h_a}|
+(density) + sum_a |{b != a: r < 2 max(h_a, h_b)}| (force), counted with the
+library's exact neighbour export before and after the timed steps (mean).
+value = interactions per step * steps / wall time of the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SPH pair interactions/s (density+force), FP32 vs FP64 form, at stated error"
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
+PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
+# Algorithmic floating-point operations per pair (adds, multiplies, compares,
+# square roots and reciprocals each count one), from the formulas the kernels
+# evaluate once per pair:
+#   density: separation 3, r^2 5, support test 1, sqrt 1, q 1, kernel
+#            polynomial f and 3f + q f' 7, two mass-weighted sums 4      -> 22
+#   force:   separation 3, r^2 5, two support tests 2, 1/r 1, r 1, q_a, q_b 2,
+#            f'(q_a), f'(q_b) 8, h^-4 factors 2, velocity difference 3,
+#            v.rhat 6, viscosity terms 10, pair weight 5, acceleration 6,
+#            du/dt 4, signal-velocity max 1                              -> 59
+FLOP_DENSITY_PAIR = 22
+FLOP_FORCE_PAIR = 59
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_ctx(A, p, precision):
+    return A.Context(A.make_params(
+        precision=A.APR_FP32 if precision == "fp32" else A.APR_FP64, eos=int(p["eos"]),
+        periodic=int(p["periodic"]), box_lo=p["lo"], box_hi=p["hi"], m0=p["m0"],
+        hfact=p["hfact"], gamma=p["gamma"], cs0=p["cs0"], av_alpha=p["alpha"],
+        av_beta=p["beta"], tol_h=1e-6 if precision == "fp32" else 1e-12, max_iter=60))
+
+
+def count_interactions(A, ctx, ds):
+    offs0, _ = A.apr_neighbours(ctx, ds, ds["h"].contiguous(), 0)
+    offs1, _ = A.apr_neighbours(ctx, ds, ds["h"].contiguous(), 1)
+    return int(offs0[-1].item()), int(offs1[-1].item())
+
+
+def run_form(A, torch, st, p, precision, steps, warmup):
+    ctx = make_ctx(A, p, precision)
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_accel(ctx, ds)
+    dt = A.apr_timestep(ctx, ds, 0.3)
+    A.apr_sync_status(ctx)
+    for k in range(warmup):
+        A.apr_step(ctx, ds, [], [], dt, k)
+    A.apr_sync_status(ctx)
+    d0, f0 = count_interactions(A, ctx, ds)
+    torch.cuda.synchronize()
+    A.apr_profile_enable(ctx, True)
+    A.apr_profile_read(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        A.apr_step(ctx, ds, [], [], dt, warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = A.apr_profile_read(ctx, reset=True)
+    A.apr_profile_enable(ctx, False)
+    fails = A.apr_sync_status(ctx)
+    d1, f1 = count_interactions(A, ctx, ds)
+    n = ds.n
+    idens = 0.5 * (d0 + d1)
+    iforce = 0.5 * (f0 + f1)
+    wall = t1 - t0
+    per_step = idens + iforce
+    ms_d, cnt_d = prof[A.APR_PROF_DENSITY]
+    ms_f, cnt_f = prof[A.APR_PROF_FORCES]
+    ms_c, cnt_c = prof[A.APR_PROF_CELLS]
+    res = dict(n=n, dt=dt, wall_s=wall, ms_per_step=1e3 * wall / steps,
+               interactions_per_step=per_step, density_pairs=idens, force_pairs=iforce,
+               value=per_step * steps / wall, failures=fails,
+               density_ms=ms_d / max(cnt_d, 1), forces_ms=ms_f / max(cnt_f, 1),
+               cells_ms=ms_c / max(cnt_c, 1), launches=(cnt_d, cnt_f, cnt_c))
+    res["density_force_rate"] = per_step / (1e-3 * (res["density_ms"] + res["forces_ms"]))
+    ctx.close()
+    return res
+
+
+def cpu_baseline(st, p, seconds_hint=15.0):
+    """The FP64 oracle (brute force, OpenMP) on a bounded sample of the same
+    workload: the density (h-rho Newton) of every particle within reach of a
+    few balls of 48 targets, then the forces on the targets."""
+    import numpy as np
+    import oracle
+    n = st["x"].shape[0]
+    pos = np.stack([st["x"], st["y"], st["z"]], 1)
+    hs = 1.2 / 64
+    rng = np.random.default_rng(99)
+    tg, sh = [], []
+    nballs = 8
+    for c in rng.choice(n, nballs, replace=False):
+        d = pos - pos[c]
+        d -= np.round(d)
+        r = np.sqrt((d * d).sum(1))
+        order = np.argsort(r, kind="stable")[:48]
+        tg.append(order)
+        sh.append(np.nonzero(r < r[order[-1]] + 4.5 * hs)[0])
+    tg = np.unique(np.concatenate(tg))
+    sh = np.unique(np.concatenate(sh))
+    kw = dict(m0=p["m0"], periodic=True, lo=p["lo"], hi=p["hi"])
+    t0 = time.perf_counter()
+    o = oracle.density(st["x"], st["y"], st["z"], st["level"], st["h"][sh], tol=1e-12,
+                       max_iter=60, targets=sh, **kw)
+    h, rho, om = np.full(n, 1e-9), np.ones(n), np.ones(n)
+    h[sh], rho[sh], om[sh] = o["h"], o["rho"], o["omega"]
+    oracle.forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"], st["level"],
+                  h, rho, om, eos=int(p["eos"]), gamma=p["gamma"], alpha=p["alpha"],
+                  beta=p["beta"], targets=tg, **kw)
+    t1 = time.perf_counter()
+    nb = oracle.neighbours(st["x"], st["y"], st["z"], h, symmetric=True, periodic=True,
+                           lo=p["lo"], hi=p["hi"], targets=tg)
+    inter = float(np.sum(o["nneigh"] - 1)) + float(sum(len(a) for a in nb))
+    return dict(value=inter / (t1 - t0), unit="interactions/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample="FP64 oracle: h-rho Newton for %d particles (within reach of %d balls "
+                       "of 48 targets) over all %d sources, then forces on %d targets; %.1f s"
+                       % (sh.shape[0], nballs, n, tg.shape[0], t1 - t0),
+                seconds=t1 - t0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2409_11470_amd as A
+    import workloads as W
+    torch.cuda.set_device(0)
+    st, p = W.shock_box()
+    log("workload: %d particles" % st["x"].shape[0])
+    r32 = run_form(A, torch, st, p, "fp32", args.steps, args.warmup)
+    log("fp32: %.3e interactions/s, %.3f ms/step" % (r32["value"], r32["ms_per_step"]))
+    r64 = None
+    if not args.fp32_only:
+        r64 = run_form(A, torch, st, p, "fp64", args.steps, args.warmup)
+        log("fp64: %.3e interactions/s, %.3f ms/step" % (r64["value"], r64["ms_per_step"]))
+    # roofline of the dominant kernel of the FP32 form (plain VALU arithmetic)
+    n = r32["n"]
+    if r32["density_ms"] >= r32["forces_ms"]:
+        kern, ms = "k_density<float>", r32["density_ms"]
+        flops = FLOP_DENSITY_PAIR * (r32["density_pairs"] + n)
+    else:
+        kern, ms = "k_forces<float>", r32["forces_ms"]
+        flops = FLOP_FORCE_PAIR * r32["force_pairs"]
+    achieved = flops / (ms * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=kern,
+                flop_per_launch=flops, ms_per_launch=ms)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(st, p)
+        log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+        cpu.pop("seconds")
+    out = {
+        "metric": METRIC, "value": r32["value"], "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "periodic shock box, 64^3 = 262144 particles, jittered lattice, "
+                               "mixed mass (levels 0 and 3), adiabatic, KDK leapfrog",
+                   "n_particles": r32["n"], "precision_form": "fp32 (cell-relative, "
+                   "compensated sums; FP64 positions, leapfrog, Newton test)",
+                   "newton_tol": 1e-6},
+        "roofline": roof, "cpu_baseline": cpu,
+        "fp32_form": {k: r32[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms",
+                                           "cells_ms", "interactions_per_step",
+                                           "density_force_rate", "failures")},
+        "fp64_form": None if r64 is None else {
+            k: r64[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms", "cells_ms",
+                                "interactions_per_step", "density_force_rate", "failures")},
+    }
+    if r64 is not None:
+        out["fp64_form"]["newton_tol"] = 1e-12
+        out["fp32_over_fp64"] = r32["value"] / r64["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -216,6 +216,17 @@ int apr_timestep(apr_ctx *ctx, const apr_state *s, double C, double *dt);
  * particles that failed to converge (may be NULL).  Clears the flags. */
 int apr_sync_status(apr_ctx *ctx, int64_t *count);
 
+/* Kernel timing (diagnostics).  While enabled, HIP events on the context's
+ * stream bracket every launch of the timed kernels: index APR_PROF_DENSITY
+ * (h-rho Newton kernel), APR_PROF_FORCES (force kernel), APR_PROF_CELLS
+ * (whole cell build), APR_PROF_SPLITMERGE (whole split/merge pass).
+ * apr_profile_read synchronises, writes the summed milliseconds and launch
+ * counts per index (arrays of APR_PROF_N) and, if reset, clears them. */
+enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
+       APR_PROF_N = 4 };
+int apr_profile_enable(apr_ctx *ctx, int on);
+int apr_profile_read(apr_ctx *ctx, double *ms, int64_t *launches, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,8 @@ def lib():
         if not os.path.exists(_build.LIB):
             _build.build()
         L = C.CDLL(_build.LIB)
+        L.orc_num_threads.restype = C.c_int32
+        L.orc_num_threads.argtypes = []
         L.orc_m4_f.restype = C.c_double
         L.orc_m4_f.argtypes = [C.c_double]
         L.orc_m4_df.restype = C.c_double
@@ -94,6 +96,10 @@ def _f64(a):
 def _box(lo, hi):
     return _f64(np.asarray(lo, dtype=np.float64).reshape(3)), _f64(
         np.asarray(hi, dtype=np.float64).reshape(3))
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 # --------------------------------------------------------------------- kernel

@@ -20,11 +20,15 @@
  * takes them.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+
+/* threads the OpenMP loops below use */
+int32_t orc_num_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* M4 cubic spline (Monaghan & Lattanzio 1985), 3D, compact support 2h.      */

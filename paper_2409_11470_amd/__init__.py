@@ -8,9 +8,11 @@ no CPU fallback: if libapr.so is missing, importing the binding fails.
 from ._abi import (  # noqa: F401
     APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP,
     APR_ERR_OVERFLOW, APR_FP64, APR_FP32, APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL,
-    APR_EOS_ADIABATIC, APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM, AprError, lib, lib_path,
+    APR_EOS_ADIABATIC, APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM, APR_PROF_DENSITY,
+    APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, AprError, lib, lib_path,
     Params, Zone, Sink, CState, apr_default_params)
 from .api import (  # noqa: F401
     Context, DeviceState, apr_ctx_create, apr_ctx_destroy, apr_build_cells, apr_density,
     apr_forces, apr_neighbours, apr_split_merge, apr_step, apr_accel, apr_timestep,
-    apr_sync_status, make_params, make_zones, make_sinks)
+    apr_sync_status, apr_profile_enable, apr_profile_read, make_params, make_zones,
+    make_sinks)

@@ -260,3 +260,15 @@ def apr_sync_status(ctx, raise_noconverge=True):
     if rc != 0:
         raise AprError(rc, ctx.error())
     return cnt.value
+
+
+def apr_profile_enable(ctx, on=True):
+    ctx.check(lib().apr_profile_enable(ctx.ptr, int(bool(on))))
+
+
+def apr_profile_read(ctx, reset=True):
+    """{index: (total ms, launches)} for the timed kernels; synchronises."""
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int64 * 4)()
+    ctx.check(lib().apr_profile_read(ctx.ptr, ms, cnt, int(bool(reset))))
+    return {k: (ms[k], cnt[k]) for k in range(4)}

@@ -49,6 +49,31 @@ void *ws(apr_ctx *c, const char *name, size_t bytes)
     return b.p;
 }
 
+int prof_begin(apr_ctx *c, int idx)
+{
+    if (!c->prof) return -1;
+    apr_ctx::EvPair e;
+    if (!c->ev_free.empty()) {
+        e = c->ev_free.back();
+        c->ev_free.pop_back();
+    } else if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
+        return -1;
+    }
+    e.idx = idx;
+    if (hipEventRecord(e.a, c->stream) != hipSuccess) {
+        c->ev_free.push_back(e);
+        return -1;
+    }
+    c->ev_used.push_back(e);
+    return (int)c->ev_used.size() - 1;
+}
+
+void prof_end(apr_ctx *c, int token)
+{
+    if (token < 0) return;
+    (void)hipEventRecord(c->ev_used[token].b, c->stream);
+}
+
 }  // namespace apr
 
 using namespace apr;
@@ -143,6 +168,11 @@ int apr_ctx_destroy(apr_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->bufs)
         if (b.p) (void)hipFree(b.p);
+    for (auto *v : {&c->ev_used, &c->ev_free})
+        for (auto &e : *v) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
     if (c->d_status) (void)hipFree(c->d_status);
     if (c->h_status) (void)hipHostFree(c->h_status);
     delete c;
@@ -164,6 +194,8 @@ int apr_build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
     if (rc) return rc;
     return build_cells(c, s, perm);
 }
+
+
 
 int apr_density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh,
                 int32_t *iters)
@@ -288,6 +320,36 @@ int apr_timestep(apr_ctx *c, const apr_state *s, double C, double *dt)
     void *rho, *om, *a, *vs;
     step_buffers(c, s->capacity, &rho, &om, &a, &vs);
     return min_timestep(c, s, vs, C, dt);
+}
+
+int apr_profile_enable(apr_ctx *c, int on)
+{
+    if (!c) return APR_ERR_INVALID;
+    c->prof = on != 0;
+    return APR_OK;
+}
+
+int apr_profile_read(apr_ctx *c, double *ms, int64_t *launches, int reset)
+{
+    if (!c) return APR_ERR_INVALID;
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto &e : c->ev_used) {
+        float t = 0.0f;
+        APR_HIP(c, hipEventElapsedTime(&t, e.a, e.b));
+        c->prof_ms[e.idx] += t;
+        c->prof_cnt[e.idx] += 1;
+        c->ev_free.push_back(e);
+    }
+    c->ev_used.clear();
+    for (int k = 0; k < APR_PROF_N; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (launches) launches[k] = c->prof_cnt[k];
+        if (reset) {
+            c->prof_ms[k] = 0.0;
+            c->prof_cnt[k] = 0;
+        }
+    }
+    return APR_OK;
 }
 
 int apr_sync_status(apr_ctx *c, int64_t *count)

@@ -282,7 +282,17 @@ int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
     return refit_hmax_from_cells(c);
 }
 
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm);
+
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
+{
+    int tok = prof_begin(c, APR_PROF_CELLS);
+    int rc = build_cells_impl(c, s, perm);
+    prof_end(c, tok);
+    return rc;
+}
+
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
 {
     int64_t n = s->n;
     if (n <= 0) return fail(c, APR_ERR_INVALID, "empty state");

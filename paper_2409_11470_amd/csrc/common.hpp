@@ -66,6 +66,15 @@ struct apr_ctx {
     // derived values of the last density / force evaluation (workspace)
     int64_t dens_n = -1;           // n of the last apr_density (for the split cap)
     int64_t force_n = -1;          // n of the last force evaluation (for the timestep)
+    // kernel timing: pairs of events per index, summed at read time
+    bool prof = false;
+    struct EvPair {
+        int idx;
+        hipEvent_t a, b;
+    };
+    std::vector<EvPair> ev_used, ev_free;
+    double prof_ms[APR_PROF_N] = {};
+    int64_t prof_cnt[APR_PROF_N] = {};
 };
 
 namespace apr {
@@ -205,6 +214,10 @@ int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, dou
 // splitmerge.hip
 int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
                 int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare);
+
+// kernel timing: prof_begin returns a token for prof_end (-1 when disabled)
+int prof_begin(apr_ctx *c, int idx);
+void prof_end(apr_ctx *c, int token);
 
 // fill helpers (kernels, so that they can sit inside captured graphs)
 int fill_i32(apr_ctx *c, int32_t *p, int32_t v, int64_t n);

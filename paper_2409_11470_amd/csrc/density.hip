@@ -394,6 +394,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
     float *hmax_new = wsa<float>(c, "hmax_new", (size_t)cb);
     int32_t *st = c->d_status;
     Tree tr = make_tree(c);
+    int tok = prof_begin(c, APR_PROF_DENSITY);
     if (c->p.precision == APR_FP32) {
         DensArgs<float> a;
         a.tree = tr;
@@ -431,6 +432,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         hipLaunchKernelGGL(k_density<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
                            c->stream, a);
     }
+    prof_end(c, tok);
     APR_LAUNCHED(c);
     hipLaunchKernelGGL(k_set_cell_hmax, dim3((unsigned)ceil_div(cb, 256)), dim3(256), 0,
                        c->stream, cell_hdr(c), hmax_new, cell_level(c, 0), cb);

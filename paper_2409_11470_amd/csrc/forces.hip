@@ -315,6 +315,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         hipLaunchKernelGGL(k_eos<float>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
                            p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
                            (const float *)rho, (const float *)omega, vh, th);
+        int tok = prof_begin(c, APR_PROF_FORCES);
         ForceArgs<float> a;
         a.tree = tr;
         a.pm = wsa<float4>(c, "pm32", (size_t)n);
@@ -326,12 +327,14 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         a.status = c->d_status;
         hipLaunchKernelGGL(k_forces<float>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
                            c->stream, a);
+        prof_end(c, tok);
     } else {
         double4 *vh = wsa<double4>(c, "vh64", (size_t)n),
                 *th = wsa<double4>(c, "th64", (size_t)n);
         hipLaunchKernelGGL(k_eos<double>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
                            p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
                            (const double *)rho, (const double *)omega, vh, th);
+        int tok = prof_begin(c, APR_PROF_FORCES);
         ForceArgs<double> a;
         a.tree = tr;
         a.pm = wsa<double4>(c, "pm64", (size_t)n);
@@ -343,6 +346,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         a.status = c->d_status;
         hipLaunchKernelGGL(k_forces<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
                            c->stream, a);
+        prof_end(c, tok);
     }
     APR_LAUNCHED(c);
     c->force_n = n;
