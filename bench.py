@@ -74,6 +74,7 @@ def run_form(A, torch, st, p, precision, steps, warmup):
     torch.cuda.synchronize()
     A.apr_profile_enable(ctx, True)
     A.apr_profile_read(ctx, reset=True)
+    A.apr_counters(ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -82,6 +83,7 @@ def run_form(A, torch, st, p, precision, steps, warmup):
     t1 = time.perf_counter()
     prof = A.apr_profile_read(ctx, reset=True)
     A.apr_profile_enable(ctx, False)
+    counters = A.apr_counters(ctx, reset=True)
     fails = A.apr_sync_status(ctx)
     d1, f1 = count_interactions(A, ctx, ds)
     n = ds.n
@@ -96,7 +98,8 @@ def run_form(A, torch, st, p, precision, steps, warmup):
                interactions_per_step=per_step, density_pairs=idens, force_pairs=iforce,
                value=per_step * steps / wall, failures=fails,
                density_ms=ms_d / max(cnt_d, 1), forces_ms=ms_f / max(cnt_f, 1),
-               cells_ms=ms_c / max(cnt_c, 1), launches=(cnt_d, cnt_f, cnt_c))
+               cells_ms=ms_c / max(cnt_c, 1), launches=(cnt_d, cnt_f, cnt_c),
+               counters=counters)
     res["density_force_rate"] = per_step / (1e-3 * (res["density_ms"] + res["forces_ms"]))
     ctx.close()
     return res
@@ -198,10 +201,11 @@ def main():
         "roofline": roof, "cpu_baseline": cpu,
         "fp32_form": {k: r32[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms",
                                            "cells_ms", "interactions_per_step",
-                                           "density_force_rate", "failures")},
+                                           "density_force_rate", "failures", "counters")},
         "fp64_form": None if r64 is None else {
             k: r64[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms", "cells_ms",
-                                "interactions_per_step", "density_force_rate", "failures")},
+                                "interactions_per_step", "density_force_rate", "failures",
+                                "counters")},
     }
     if r64 is not None:
         out["fp64_form"]["newton_tol"] = 1e-12

@@ -225,6 +225,14 @@ int apr_sync_status(apr_ctx *ctx, int64_t *count);
 enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
        APR_PROF_N = 4 };
 int apr_profile_enable(apr_ctx *ctx, int on);
+/* Work counters since the last reset (diagnostics), written to c[0..7]:
+ * [0] h-rho solves that hit max_iter, [1] overflowed lists without fallback,
+ * [2] density cells whose candidates did not fit in one LDS window (staged
+ * window by window instead), [3] the same for forces, [4] sub-block lists
+ * that did not fit, [5] density searches repeated with a larger radius,
+ * [6] density Newton passes summed over cells, [7] windows staged by the
+ * density kernel summed over cells and passes.  Synchronises. */
+int apr_counters(apr_ctx *ctx, int64_t *c, int reset);
 int apr_profile_read(apr_ctx *ctx, double *ms, int64_t *launches, int reset);
 
 #ifdef __cplusplus

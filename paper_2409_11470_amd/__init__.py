@@ -14,5 +14,5 @@ from ._abi import (  # noqa: F401
 from .api import (  # noqa: F401
     Context, DeviceState, apr_ctx_create, apr_ctx_destroy, apr_build_cells, apr_density,
     apr_forces, apr_neighbours, apr_split_merge, apr_step, apr_accel, apr_timestep,
-    apr_sync_status, apr_profile_enable, apr_profile_read, make_params, make_zones,
+    apr_sync_status, apr_profile_enable, apr_profile_read, apr_counters, make_params, make_zones,
     make_sinks)

@@ -272,3 +272,15 @@ def apr_profile_read(ctx, reset=True):
     cnt = (C.c_int64 * 4)()
     ctx.check(lib().apr_profile_read(ctx.ptr, ms, cnt, int(bool(reset))))
     return {k: (ms[k], cnt[k]) for k in range(4)}
+
+
+COUNTER_NAMES = ("noconverge", "overflow", "density_multiwindow_cells",
+                 "force_multiwindow_cells", "subblock_direct", "density_restage",
+                 "density_passes", "density_windows")
+
+
+def apr_counters(ctx, reset=True):
+    """Work counters (see include/apr.h) as a dict; synchronises."""
+    c = (C.c_int64 * 8)()
+    ctx.check(lib().apr_counters(ctx.ptr, c, int(bool(reset))))
+    return {k: int(c[i]) for i, k in enumerate(COUNTER_NAMES)}

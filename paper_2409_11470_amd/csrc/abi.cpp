@@ -352,13 +352,29 @@ int apr_profile_read(apr_ctx *c, double *ms, int64_t *launches, int reset)
     return APR_OK;
 }
 
+int apr_counters(apr_ctx *c, int64_t *out, int reset)
+{
+    if (!c || !out) return APR_ERR_INVALID;
+    APR_HIP(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * ST_WORDS,
+                              hipMemcpyDeviceToHost, c->stream));
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 8; ++k) out[k] = k < ST_WORDS ? c->h_status[k] : 0;
+    if (reset) {
+        int rc = fill_i32(c, c->d_status, 0, ST_WORDS);
+        if (rc) return rc;
+        APR_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return APR_OK;
+}
+
 int apr_sync_status(apr_ctx *c, int64_t *count)
 {
     if (!c) return APR_ERR_INVALID;
     APR_HIP(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * ST_WORDS,
                               hipMemcpyDeviceToHost, c->stream));
     APR_HIP(c, hipStreamSynchronize(c->stream));
-    APR_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * ST_WORDS, c->stream));
+    // the flags are cleared; the work counters [ST_DENS_DIRECT..] are kept
+    APR_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * 2, c->stream));
     int32_t nc = c->h_status[ST_NOCONV], ov = c->h_status[ST_OVERFLOW];
     if (count) *count = nc;
     if (ov) return fail(c, APR_ERR_OVERFLOW, "an internal candidate list overflowed");

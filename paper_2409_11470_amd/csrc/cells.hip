@@ -44,30 +44,42 @@ __global__ void k_morton(const double *x, const double *y, const double *z, int6
     vals[i] = (uint32_t)i;
 }
 
-__global__ void k_seg_count(const uint32_t *keys, int64_t n, int segshift, uint32_t *segcount)
+// Sorted keys: a segment starts where the key prefix changes.  segfirst is
+// pre-filled with UINT32_MAX; each non-empty segment's first index is written
+// once (no atomics).
+__global__ void k_seg_first(const uint32_t *keys, int64_t n, int segshift, uint32_t *segfirst)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    atomicAdd(&segcount[keys[i] >> segshift], 1u);
+    uint32_t s = keys[i] >> segshift;
+    if (i == 0 || (keys[i - 1] >> segshift) != s) segfirst[s] = (uint32_t)i;
 }
 
-// One block: segment starts, cells per segment and their offsets, the header.
-__global__ __launch_bounds__(1024) void k_seg_scan(const uint32_t *segcount, int nseg,
+// One block: segment counts from the first indices, segment starts, cells per
+// segment and their offsets, the header.
+__global__ __launch_bounds__(1024) void k_seg_scan(const uint32_t *segfirst, int nseg,
                                                    int64_t n, uint32_t *segstart,
                                                    uint32_t *celloff, Hdr *hdr,
                                                    int32_t *cell_start, int nlev)
 {
     __shared__ uint32_t ps[4096], pc[4096];
-    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
-        ps[s] = segcount[s];
-        pc[s] = (segcount[s] + kCell - 1) / kCell;
-    }
+    for (int s = threadIdx.x; s < nseg; s += blockDim.x) ps[s] = segfirst[s];
     __syncthreads();
     if (threadIdx.x == 0) {
-        // nseg <= 4096: a serial pass is a few microseconds and keeps this simple
+        // nseg <= 4096: serial passes of a few microseconds keep this simple
+        uint32_t next = (uint32_t)n;
+        for (int s = nseg - 1; s >= 0; --s) {
+            uint32_t f = ps[s];
+            uint32_t cnt = 0;
+            if (f != 0xffffffffu) {
+                cnt = next - f;
+                next = f;
+            }
+            ps[s] = cnt;
+        }
         uint32_t a = 0, b = 0;
         for (int s = 0; s < nseg; ++s) {
-            uint32_t ca = ps[s], cb = pc[s];
+            uint32_t ca = ps[s], cb = (ca + kCell - 1) / kCell;
             ps[s] = a;
             pc[s] = b;
             a += ca;
@@ -356,9 +368,9 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     hipLaunchKernelGGL(k_scatter_back, dim3(g), dim3(256), 0, c->stream, pa);
     APR_LAUNCHED(c);
 
-    rc = fill_u32(c, segcount, 0u, nseg);
+    rc = fill_u32(c, segcount, 0xffffffffu, nseg);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
+    hipLaunchKernelGGL(k_seg_first, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
                        segcount);
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, c->stream, segcount, nseg, n,
                        segstart, celloff, hdr, cs, nlev);

@@ -21,7 +21,17 @@ constexpr int kNumXcd = 8;      // MI355X: workgroups go round-robin over 8 XCDs
 constexpr double kPi = 3.14159265358979323846;
 
 // Status words on the device (ctx->d_status).
-enum { ST_NOCONV = 0, ST_OVERFLOW = 1, ST_WORDS = 4 };
+enum {
+    ST_NOCONV = 0,        // h-rho solves that hit max_iter
+    ST_OVERFLOW = 1,      // a list that has no fallback overflowed
+    ST_DENS_DIRECT = 2,   // density: cells whose staged set did not fit in LDS
+    ST_FORCE_DIRECT = 3,  // forces: same
+    ST_SUB_DIRECT = 4,    // sub-block lists that did not fit
+    ST_RESTAGE = 5,       // density: searches repeated for a larger radius
+    ST_PASSES = 6,        // density: Newton passes summed over cells
+    ST_WINDOWS = 7,       // staged windows summed over cells and passes
+    ST_WORDS = 8
+};
 
 // A leaf cell or a tree node: centre in FP64 and conservative (rounded-up)
 // FP32 half extents and largest smoothing length.

@@ -33,12 +33,13 @@ template <class T>
 struct StageCap;
 template <>
 struct StageCap<float> {
-    static constexpr int value = 2560;
+    static constexpr int value = 1536;
 };
 template <>
 struct StageCap<double> {
-    static constexpr int value = 1280;
+    static constexpr int value = 768;
 };
+constexpr int kDTCap = 128;  // per-target list capacity (density)
 
 template <class T>
 struct DensArgs {
@@ -56,20 +57,18 @@ struct DensArgs {
     int32_t *status;
 };
 
-// f and 3f + q f' of the M4 kernel, branch-free in q.
+// f and 3f + q f' of the M4 kernel, branch-free in q (0 <= q < 2), from
+// t = 2 - q and u = max(1 - q, 0):  f = t^3/4 - u^3,  f' = -3/4 t^2 + 3 u^2.
 template <class T>
 __device__ inline void m4_fg(T q, T &f, T &g)
 {
-    T q2 = q * q;
     T t = T(2) - q;
-    T t2 = t * t;
-    T fi = T(1) - T(1.5) * q2 + T(0.75) * q2 * q;
-    T gi = T(3) - T(7.5) * q2 + T(4.5) * q2 * q;
-    T fo = T(0.25) * t2 * t;
-    T go = T(1.5) * t2 * (T(1) - q);
-    bool inner = q < T(1);
-    f = inner ? fi : fo;
-    g = inner ? gi : go;
+    T u = T(1) - q;
+    u = u > T(0) ? u : T(0);
+    T t2 = t * t, u2 = u * u;
+    f = T(0.25) * t2 * t - u2 * u;
+    T df = T(3) * u2 - T(0.75) * t2;
+    g = T(3) * f + q * df;
 }
 
 // Per-lane partial sums of one Newton evaluation.
@@ -90,14 +89,16 @@ struct DSum {
     {
         T r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < R2) {
-            T r = sqrt(r2);
+            T r = psqrt(r2);
             T f, g;
             m4_fg<T>(r * hinv, f, g);
             w.add(m * f);
             d.add(m * g);
             nn += 1;
-            if (r2 > T(0)) dmin = dmin < r ? dmin : r;
-            else nzero += 1;
+            bool zero = !(r2 > T(0));
+            nzero += zero ? 1 : 0;
+            T rr = zero ? T(3.0e38) : r;
+            dmin = dmin < rr ? dmin : rr;
         }
     }
     __device__ void reduce16()
@@ -110,6 +111,37 @@ struct DSum {
     }
 };
 
+// Stages the candidates with staged offset in [w0, w0 + STAGE): positions in
+// the target cell's frame.  sB holds each candidate cell's first offset.
+template <class T, int STAGE>
+__device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<T> *pm,
+                                    const int32_t *sA, const int32_t *sB, int nc, int total,
+                                    T R2, int w0, vec4_t<T> *stg)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
+    for (int ci = w; ci < nc; ci += kWaves) {
+        int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
+        if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
+        int cc = sA[ci];
+        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+        double sh[3];
+        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+        bool hit = false;
+        vec4_t<T> p;
+        if (lane < bn) {
+            p = pm[b0 + lane];
+            p.x = p.x + (T)sh[0];
+            p.y = p.y + (T)sh[1];
+            p.z = p.z + (T)sh[2];
+            hit = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez) < R2;
+        }
+        uint64_t m = __ballot(hit);
+        int off = o0 + __popcll(m & lanemask_lt()) - w0;
+        if (hit && off >= 0 && off < STAGE) stg[off] = p;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
 {
@@ -117,8 +149,9 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
     constexpr int STAGE = StageCap<T>::value;
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V stg[STAGE];
-    __shared__ uint16_t sub[kWaves][kSubCap];
-    __shared__ int s_ncand, s_nstg, s_direct, s_ovf;
+    __shared__ uint16_t tls[kCell][kDTCap];
+    __shared__ uint16_t sub[kWaves][STAGE];
+    __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
 
     const Tree &tr = a.tree;
@@ -127,232 +160,213 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
-    const int w = threadIdx.x / kWave, lane = lane_id(), grp = lane >> 4, j = lane & 15;
-    if (threadIdx.x == 0) s_ovf = 0;
+    const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
+    const int t = 16 * w + (lane >> 2);   // this lane's target (4 lanes each)
+    const bool valid = t < cnt;
 
-    // per lane: the target of its group in each of the wave's 4 sub-blocks
-    double hreg[4];
-    int itc[4];
-    bool done[4];
-    double hmy = 0.0;
-#pragma unroll
-    for (int sb = 0; sb < 4; ++sb) {
-        int t = 16 * w + 4 * sb + grp;
-        bool v = t < cnt;
-        hreg[sb] = v ? a.h[s0 + t] : 0.0;
-        itc[sb] = 0;
-        done[sb] = !v;
-        hmy = fmax(hmy, hreg[sb]);
-    }
+    double h = valid ? a.h[s0 + t] : 0.0;
+    double Rt = 0.0;
+    int itc = 0, tlen = 0;
+    bool done = !valid;
+    V tp;
+    if (valid) tp = a.pm[s0 + t];
+    else { tp.x = T(0); tp.y = T(0); tp.z = T(0); tp.w = T(0); }
+    uint16_t *mylist = tls[t < kCell ? t : 0];
+
+    double R;
     {
-        double m = hmy;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+        double m = wave_max64(h);
         if (lane == 0) s_red[w] = m;
-    }
-    __syncthreads();
-    double R = 0.0;
-    for (int k = 0; k < kWaves; ++k) R = fmax(R, s_red[k]);
-    R *= 2.0 * (double)kSigma;
-    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
-
-    // each new search follows at least one Newton step of a pending target,
-    // so max_iter + 1 rounds always finish every target
-    for (int round = 0; round < a.max_iter + 2; ++round) {
-        // ---- 1. candidate cells
-        if (w == 0) {
-            int ovf = 0;
-            int nc = traverse(tr, tg, R, false, sA, sB, &ovf);
-            if (lane == 0) {
-                s_ncand = nc;
-                if (ovf) s_ovf = 1;
-            }
-        }
         __syncthreads();
-        const int nc = s_ncand;
-        const T R2c = (T)(R * R);
-        // ---- 2. stage candidates within R of the target cell box: count, scan, write
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 1 && s_direct) break;
+        R = 0.0;
+        for (int k = 0; k < kWaves; ++k) R = fmax(R, s_red[k]);
+        R *= 2.0 * (double)kSigma;
+    }
+
+    // Every new search follows a Newton step that grew some h, and every
+    // pass is a Newton step for each pending target: max_iter bounds both.
+    bool search = true;
+    bool lists = false;    // per-target lists valid (single window only)
+    int nc = 0, total = 0, nwin = 1;
+    for (int pass = 0; pass <= a.max_iter; ++pass) {
+        if (search) {
+            // ---- candidate cells, their staged counts and offsets
+            __syncthreads();
+            if (w == 0) {
+                int o = 0;
+                int ncl = traverse(tr, tg, R, false, sA, sB, &o);
+                if (lane == 0) {
+                    s_ncand = ncl;
+                    if (o) atomicOr(&a.status[ST_OVERFLOW], 1);
+                }
+            }
+            __syncthreads();
+            nc = s_ncand;
+            const T R2c = (T)(R * R);
+            const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
             for (int ci = w; ci < nc; ci += kWaves) {
                 int cc = sA[ci];
                 int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
                 double sh[3];
                 cell_shift(tr.lev[0][cc], tg, tr.box, sh);
                 bool hit = false;
-                V p;
                 if (lane < bn) {
-                    p = a.pm[b0 + lane];
-                    p.x = p.x + (T)sh[0];
-                    p.y = p.y + (T)sh[1];
-                    p.z = p.z + (T)sh[2];
-                    hit = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez) < R2c;
+                    V p = a.pm[b0 + lane];
+                    hit = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0),
+                                       T(0), ex, ey, ez) < R2c;
                 }
                 uint64_t m = __ballot(hit);
-                if (pass == 0) {
-                    if (lane == 0) sB[ci] = __popcll(m);
-                } else if (hit) {
-                    stg[sB[ci] + __popcll(m & lanemask_lt())] = p;
+                if (lane == 0) sB[ci] = __popcll(m);
+            }
+            __syncthreads();
+            if (w == 0) {
+                int tot = wave_excl_scan_lds(sB, nc);
+                if (lane == 0) {
+                    s_total = tot;
+                    if (tot > STAGE) atomicAdd(&a.status[ST_DENS_DIRECT], 1);
+                    if (pass > 0) atomicAdd(&a.status[ST_RESTAGE], 1);
                 }
             }
             __syncthreads();
-            if (pass == 0) {
-                if (w == 0) {
-                    int tot = wave_excl_scan_lds(sB, nc);
-                    if (lane == 0) {
-                        s_nstg = tot;
-                        s_direct = tot > STAGE;
-                    }
-                }
+            total = s_total;
+            nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
+            lists = false;
+            search = false;
+            if (nwin == 1) {
+                stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, R2c, 0, stg);
                 __syncthreads();
             }
         }
-        const bool direct = s_direct;
-        const int nstg = s_nstg;
-
-        // ---- 3. per sub-block: candidate list, Newton
-        double needR = 0.0;
-        for (int sb = 0; sb < 4; ++sb) {
-            int t = 16 * w + 4 * sb + grp;
-            bool valid = t < cnt;
-            // the wave skips sub-blocks whose targets are all done
-            if (!__any(!done[sb])) continue;
-            V tp;
-            if (valid) tp = a.pm[s0 + t];
-            else { tp.x = T(0); tp.y = T(0); tp.z = T(0); tp.w = T(0); }
-            T bigT = T(3.0e38);
-            T lox = wmin_groups(valid ? tp.x : bigT), loy = wmin_groups(valid ? tp.y : bigT),
-              loz = wmin_groups(valid ? tp.z : bigT);
-            T hix = wmax_groups(valid ? tp.x : -bigT), hiy = wmax_groups(valid ? tp.y : -bigT),
-              hiz = wmax_groups(valid ? tp.z : -bigT);
-            T bcx = T(0.5) * (lox + hix), bcy = T(0.5) * (loy + hiy), bcz = T(0.5) * (loz + hiz);
-            T bex = T(0.5) * (hix - lox), bey = T(0.5) * (hiy - loy), bez = T(0.5) * (hiz - loz);
-            double h = hreg[sb];
-            double ma = valid ? a.m0 * (double)tp.w : 0.0;
-
-            bool need_list = true, sub_direct = direct;
-            double Rs = 0.0;
-            int nsub = 0;
-            while (true) {
-                if (need_list) {
-                    double hm = wmax_groups(done[sb] ? 0.0 : h);
-                    Rs = 2.0 * (double)kSigma * hm;
-                    if (Rs > R) {  // candidate set too small: search again
-                        needR = fmax(needR, Rs);
-                        break;
-                    }
-                    sub_direct = direct;
-                    if (!direct) {
-                        // list the staged candidates within Rs of the sub-block box
-                        T Rs2 = (T)(Rs * Rs);
-                        nsub = 0;
-                        wave_sync();  // the previous list is no longer read
-                        for (int base = 0; base < nstg; base += kWave) {
-                            int idx = base + lane;
-                            bool hit = false;
-                            if (idx < nstg) {
-                                V p = stg[idx];
-                                hit = pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez) < Rs2;
-                            }
-                            uint64_t m = __ballot(hit);
-                            int pos = nsub + __popcll(m & lanemask_lt());
-                            if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)idx;
-                            nsub += __popcll(m);
-                        }
-                        if (nsub > kSubCap) sub_direct = true;
-                        wave_sync();
-                    }
-                    need_list = false;
+        // ---- one Newton evaluation of every pending target, window by window
+        DSum<T> S;
+        S.zero();
+        const bool wave_busy = __any(!done);
+        for (int win = 0; win < nwin; ++win) {
+            int w0 = win * STAGE;
+            int nstg = min(STAGE, total - w0);
+            if (nwin > 1) {
+                __syncthreads();  // the previous window is no longer read
+                stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, (T)(R * R), w0, stg);
+                __syncthreads();
+            }
+            if (!wave_busy) continue;
+            if (!lists) {
+                // this target's candidates within 2 sigma h (with margin)
+                Rt = done ? 0.0 : 2.0 * (double)kSigma * h;
+                const T Rtl = (T)Rt;
+                build_lists16<T>(
+                    nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
+                    [&](int k) {
+                        V q;
+                        int tt = 16 * w + k;
+                        if (tt < cnt) q = a.pm[s0 + tt];
+                        else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
+                        return q;
+                    },
+                    [&](int k) { return __shfl(Rtl, 4 * k, kWave); },
+                    [&](T d2, T Rs2, int) { return d2 < Rs2; },
+                    [&](const V &q, T rk, int e) {
+                        V p = stg[e];
+                        T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                        return dx * dx + dy * dy + dz * dz < rk * rk;
+                    });
+                tlen = s_tlen[t < kCell ? t : 0];
+            }
+            if (done) continue;
+            T hf = (T)h;
+            T hinv = T(1) / hf;
+            T R2 = T(4) * hf * hf;
+            if (tlen <= kDTCap) {
+                for (int k = j; k < tlen; k += kLanes) {
+                    V p = stg[mylist[k]];
+                    S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
                 }
-                // one Newton evaluation for the 4 targets
-                T hf = (T)h;
-                T hinv = T(1) / hf;
-                T R2 = T(4) * hf * hf;
-                DSum<T> S;
-                S.zero();
-                if (!sub_direct) {
-                    for (int k = j; k < nsub; k += kGroup) {
-                        V p = stg[sub[w][k]];
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
-                    }
-                } else {
-                    // from global memory: every particle of every candidate cell
-                    for (int ci = 0; ci < nc; ++ci) {
-                        int cc = sA[ci];
-                        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                        double sh[3];
-                        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-                        T sx = (T)sh[0], sy = (T)sh[1], sz = (T)sh[2];
-                        for (int k = j; k < bn; k += kGroup) {
-                            V p = a.pm[b0 + k];
-                            S.pair(tp.x - (p.x + sx), tp.y - (p.y + sy), tp.z - (p.z + sz), p.w,
-                                   R2, hinv);
-                        }
-                    }
+            } else {
+                // own list overflowed: walk the whole window
+                for (int k = j; k < nstg; k += kLanes) {
+                    V p = stg[k];
+                    S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
                 }
-                S.reduce16();
-                // FP64 Newton step (all 16 lanes of a group agree)
-                double W = S.w.value(), D = S.d.value();
-                double hh = (double)hf;
-                double rhos = a.m0 * W / (kPi * hh * hh * hh);
-                double drho = -a.m0 * D / (kPi * hh * hh * hh * hh);
-                double q3 = a.hfact / hh;
-                double rhoh = ma * q3 * q3 * q3;
-                double F = rhos - rhoh, dF = drho + 3.0 * rhoh / hh;
-                double hn = dF > 0.0 ? hh - F / dF : a.hfact * cbrt(ma / rhos);
-                hn = fmin(fmax(hn, 0.5 * hh), 2.0 * hh);
-                bool conv = fabs(hn - hh) < a.tol * hh;
-                if (!done[sb]) {
-                    itc[sb] += 1;
-                    bool last = conv || itc[sb] >= a.max_iter;
-                    if (last) {
-                        done[sb] = true;
-                        if (j == 0) {
-                            int64_t i = s0 + t;
-                            a.h[i] = hh;
-                            a.rho[i] = (T)rhos;
-                            a.omega[i] = (T)(1.0 - D / (3.0 * W));
-                            if (a.nneigh) a.nneigh[i] = S.nn;
-                            if (a.iters) a.iters[i] = itc[sb];
-                            if (a.dnn)
-                                a.dnn[i] = S.nzero >= 2 ? T(0)
-                                           : (S.dmin >= T(3.0e38) ? T(__builtin_huge_val()) : S.dmin);
-                            if (!conv) atomicAdd(&a.status[ST_NOCONV], 1);
-                        }
-                        hreg[sb] = hh;
-                    } else {
-                        hreg[sb] = hn;
-                        h = hn;
-                    }
-                }
-                if (!__any(!done[sb])) break;
-                // a pending target's support now reaches past the listed radius?
-                bool grow = !done[sb] && 2.0 * h > Rs;
-                if (__any(grow)) need_list = true;
             }
         }
-        // ---- 4. search again with a larger radius if a sub-block needs it
+        lists = nwin == 1;
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.status[ST_PASSES], 1);
+            atomicAdd(&a.status[ST_WINDOWS], nwin);
+        }
+        // ---- FP64 Newton step of this lane's target (its 4 lanes agree)
+        double needR = 0.0;
+        bool pending = false;
+        S.w.template reduce<kLanes>();
+        S.d.template reduce<kLanes>();
+        int nn = sum4(S.nn), nzero = sum4(S.nzero);
+        T dmin = min4(S.dmin);
+        if (!done) {
+            double W = S.w.value(), D = S.d.value();
+            double hh = (double)(T)h;
+            double hi = 1.0 / hh, hi3 = hi * hi * hi;
+            double ma = a.m0 * (double)tp.w;
+            double rhos = (a.m0 / kPi) * W * hi3;
+            double drho = -(a.m0 / kPi) * D * hi3 * hi;
+            double rhoh = ma * (a.hfact * a.hfact * a.hfact) * hi3;
+            double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
+            double hn;
+            if (dF > 0.0) hn = hh - F / dF;
+            else hn = a.hfact * cbrt(ma / rhos);
+            hn = fmin(fmax(hn, 0.5 * hh), 2.0 * hh);
+            bool conv = fabs(hn - hh) < a.tol * hh;
+            itc += 1;
+            if (conv || itc >= a.max_iter) {
+                done = true;
+                h = hh;
+                if (j == 0) {
+                    int64_t i = s0 + t;
+                    a.h[i] = hh;
+                    a.rho[i] = (T)rhos;
+                    a.omega[i] = (T)(1.0 - D / (3.0 * W));
+                    if (a.nneigh) a.nneigh[i] = nn;
+                    if (a.iters) a.iters[i] = itc;
+                    if (a.dnn)
+                        a.dnn[i] = nzero >= 2 ? T(0)
+                                              : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
+                    if (!conv) atomicAdd(&a.status[ST_NOCONV], 1);
+                }
+            } else {
+                h = hn;
+                pending = true;
+                if (2.0 * hn > Rt) lists = false;   // own list too short now
+                if (2.0 * hn > R) needR = 2.0 * (double)kSigma * hn;
+            }
+        }
+        // ---- block-wide: anything pending?  a larger search radius needed?
         {
-            double m = needR;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+            double m = wave_max64(needR);
+            int pw = __any(pending) ? 1 : 0;
+            int lw = __any(!lists) ? 1 : 0;
             __syncthreads();
-            if (lane == 0) s_red[w] = m;
+            if (lane == 0) {
+                s_red[w] = m;
+                s_flag[w] = pw | (lw << 1);
+            }
             __syncthreads();
             double need = 0.0;
-            for (int k = 0; k < kWaves; ++k) need = fmax(need, s_red[k]);
-            if (need <= 0.0) break;
-            R = fmax(need, 1.25 * R);
+            int fl = 0;
+            for (int k = 0; k < kWaves; ++k) {
+                need = fmax(need, s_red[k]);
+                fl |= s_flag[k];
+            }
+            if (!(fl & 1)) break;
+            if (fl & 2) lists = false;
+            if (need > 0.0) {
+                R = fmax(need, 1.25 * R);
+                search = true;
+            }
         }
     }
 
     // ---- new h_max of the cell for the force search
     {
-        double m = 0.0;
-#pragma unroll
-        for (int sb = 0; sb < 4; ++sb) m = fmax(m, hreg[sb]);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+        double m = wave_max64(valid ? h : 0.0);
         __syncthreads();
         if (lane == 0) s_red[w] = m;
         __syncthreads();
@@ -360,7 +374,6 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
             double hm = 0.0;
             for (int k = 0; k < kWaves; ++k) hm = fmax(hm, s_red[k]);
             a.hmax_new[cell] = f_up(hm);
-            if (s_ovf) atomicOr(&a.status[ST_OVERFLOW], 1);
         }
     }
 }

@@ -23,11 +23,11 @@ template <class T>
 struct FStageCap;
 template <>
 struct FStageCap<float> {
-    static constexpr int value = 1024;
+    static constexpr int value = 640;
 };
 template <>
 struct FStageCap<double> {
-    static constexpr int value = 512;
+    static constexpr int value = 320;
 };
 
 // Per particle: vh = (vx, vy, vz, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0).
@@ -74,13 +74,14 @@ struct ForceArgs {
     int32_t *status;
 };
 
+// f'(q) of the M4 kernel, branch-free (0 <= q < 2): -3/4 (2-q)^2 + 3 max(1-q, 0)^2.
 template <class T>
 __device__ inline T m4_df(T q)
 {
     T t = T(2) - q;
-    T in = q * (T(-3) + T(2.25) * q);
-    T out = T(-0.75) * t * t;
-    return q < T(1) ? in : out;
+    T u = T(1) - q;
+    u = u > T(0) ? u : T(0);
+    return T(3) * u * u - T(0.75) * t * t;
 }
 
 // Per-lane partial sums of the force on one target.
@@ -97,7 +98,7 @@ struct FSum {
         bool ina = r2 * ha_inv2 < T(4);
         bool inb = r2 * hb_inv2 < T(4);
         if ((ina || inb) && r2 > T(0)) {
-            T rinv = T(1) / sqrt(r2);
+            T rinv = prsqrt(r2);
             T r = r2 * rinv;
             T Fa = ina ? m4_df<T>(r * ha_inv) * ha_inv4 : T(0);
             T Fb = inb ? m4_df<T>(r * v.w) * (hb_inv2 * hb_inv2) : T(0);
@@ -126,8 +127,9 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
     constexpr int STAGE = FStageCap<T>::value;
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V spm[STAGE], svh[STAGE], sth[STAGE];
-    __shared__ uint16_t sub[kWaves][kSubCap];
-    __shared__ int s_ncand, s_nstg, s_direct, s_ovf;
+    __shared__ uint16_t sub[kWaves][STAGE];
+    __shared__ uint16_t tls[kCell][kTCap];
+    __shared__ int s_ncand, s_total, s_tlen[kCell];
 
     const Tree &tr = a.tree;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -135,162 +137,164 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
-    const int w = threadIdx.x / kWave, lane = lane_id(), grp = lane >> 4, j = lane & 15;
+    const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
+    const int t = 16 * w + (lane >> 2);   // this lane's target (4 lanes each)
+    const bool valid = t < cnt;
+    uint16_t *mylist = tls[t < kCell ? t : 0];
     const double R = 2.0 * (double)tg.hmax;  // targets' own supports
+    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
+    const T R2c = (T)(R * R);
 
     if (w == 0) {
-        int ovf = 0;
-        int nc = traverse(tr, tg, R, true, sA, sB, &ovf);
+        int o = 0;
+        int ncl = traverse(tr, tg, R, true, sA, sB, &o);
         if (lane == 0) {
-            s_ncand = nc;
-            s_ovf = ovf;
+            s_ncand = ncl;
+            if (o) atomicOr(&a.status[ST_OVERFLOW], 1);
         }
     }
     __syncthreads();
     const int nc = s_ncand;
-    // stage candidates b within max(R, 2 h_b) of the target cell box: count, scan, write
-    {
-        const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
-        const T R2 = (T)(R * R);
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 1 && s_direct) break;
-            for (int ci = w; ci < nc; ci += kWaves) {
-                int cc = sA[ci];
-                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                double sh[3];
-                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-                bool hit = false;
-                V p, v;
-                if (lane < bn) {
-                    p = a.pm[b0 + lane];
-                    v = a.vh[b0 + lane];
-                    p.x = p.x + (T)sh[0];
-                    p.y = p.y + (T)sh[1];
-                    p.z = p.z + (T)sh[2];
-                    T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
-                    hit = d2 < R2 || d2 * v.w * v.w < T(4);
-                }
-                uint64_t m = __ballot(hit);
-                if (pass == 0) {
-                    if (lane == 0) sB[ci] = __popcll(m);
-                } else if (hit) {
-                    int pos = sB[ci] + __popcll(m & lanemask_lt());
-                    spm[pos] = p;
-                    svh[pos] = v;
-                    sth[pos] = a.th[b0 + lane];
-                }
-            }
-            __syncthreads();
-            if (pass == 0) {
-                if (w == 0) {
-                    int tot = wave_excl_scan_lds(sB, nc);
-                    if (lane == 0) {
-                        s_nstg = tot;
-                        s_direct = tot > STAGE;
-                    }
-                }
-                __syncthreads();
-            }
+    // candidates b within max(R, 2 h_b) of the target cell box: count per cell
+    for (int ci = w; ci < nc; ci += kWaves) {
+        int cc = sA[ci];
+        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+        double sh[3];
+        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+        bool hit = false;
+        if (lane < bn) {
+            V p = a.pm[b0 + lane];
+            T hb = a.vh[b0 + lane].w;
+            T d2 = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0), T(0),
+                                ex, ey, ez);
+            hit = d2 < R2c || d2 * hb * hb < T(4);
+        }
+        uint64_t m = __ballot(hit);
+        if (lane == 0) sB[ci] = __popcll(m);
+    }
+    __syncthreads();
+    if (w == 0) {
+        int tot = wave_excl_scan_lds(sB, nc);
+        if (lane == 0) {
+            s_total = tot;
+            if (tot > STAGE) atomicAdd(&a.status[ST_FORCE_DIRECT], 1);
         }
     }
-    const bool direct = s_direct;
-    const int nstg = s_nstg;
+    __syncthreads();
+    const int total = s_total;
+    const int nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
 
-    for (int sb = 0; sb < 4; ++sb) {
-        int t = 16 * w + 4 * sb + grp;
-        bool valid = t < cnt;
-        if (!__any(valid)) break;
-        V tp, tv, tt;
-        if (valid) {
-            tp = a.pm[s0 + t];
-            tv = a.vh[s0 + t];
-            tt = a.th[s0 + t];
-        } else {
-            tp.x = tp.y = tp.z = tp.w = T(0);
-            tv.x = tv.y = tv.z = tv.w = T(0);
-            tt.x = tt.y = tt.z = tt.w = T(0);
-        }
-        T bigT = T(3.0e38);
-        T lox = wmin_groups(valid ? tp.x : bigT), loy = wmin_groups(valid ? tp.y : bigT),
-          loz = wmin_groups(valid ? tp.z : bigT);
-        T hix = wmax_groups(valid ? tp.x : -bigT), hiy = wmax_groups(valid ? tp.y : -bigT),
-          hiz = wmax_groups(valid ? tp.z : -bigT);
-        T bcx = T(0.5) * (lox + hix), bcy = T(0.5) * (loy + hiy), bcz = T(0.5) * (loz + hiz);
-        T bex = T(0.5) * (hix - lox), bey = T(0.5) * (hiy - loy), bez = T(0.5) * (hiz - loz);
-        // largest target support in the sub-block
-        T hmin_inv = wmin_groups(valid ? tv.w : bigT);
-        T Rs = T(2) / hmin_inv;
-        T Rs2 = Rs * Rs;
-        int nsub = 0;
-        bool sub_direct = direct;
-        if (!direct) {
-            wave_sync();  // the previous sub-block's list is no longer read
-            for (int base = 0; base < nstg; base += kWave) {
-                int idx = base + lane;
-                bool hit = false;
-                if (idx < nstg) {
-                    V p = spm[idx];
-                    T hb_inv = svh[idx].w;
-                    T d2 = pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez);
-                    hit = d2 < Rs2 || d2 * hb_inv * hb_inv < T(4);
-                }
-                uint64_t m = __ballot(hit);
-                int pos = nsub + __popcll(m & lanemask_lt());
-                if (hit && pos < kSubCap) sub[w][pos] = (uint16_t)idx;
-                nsub += __popcll(m);
+    V tp, tv, tt;
+    if (valid) {
+        tp = a.pm[s0 + t];
+        tv = a.vh[s0 + t];
+        tt = a.th[s0 + t];
+    } else {
+        tp.x = tp.y = tp.z = tp.w = T(0);
+        tv.x = tv.y = tv.z = T(0);
+        tv.w = T(0);
+        tt.x = tt.y = tt.z = tt.w = T(0);
+    }
+    FSum<T> S;
+    S.x.zero(); S.y.zero(); S.z.zero(); S.u.zero();
+    S.alpha = (T)a.alpha;
+    S.beta = (T)a.beta;
+    S.tx = tp.x; S.ty = tp.y; S.tz = tp.z;
+    S.tvx = tv.x; S.tvy = tv.y; S.tvz = tv.z;
+    S.ha_inv = tv.w;
+    S.ha_inv2 = tv.w * tv.w;
+    S.ha_inv4 = S.ha_inv2 * S.ha_inv2;
+    S.Pa = tt.x; S.Ga = tt.y; S.ca = tt.z;
+    S.vs = S.alpha * S.ca;
+    const bool wave_busy = __any(valid);
+
+    for (int win = 0; win < nwin; ++win) {
+        const int w0 = win * STAGE;
+        const int nstg = min(STAGE, total - w0);
+        if (win > 0) __syncthreads();  // the previous window is no longer read
+        // stage the window
+        for (int ci = w; ci < nc; ci += kWaves) {
+            int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
+            if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
+            int cc = sA[ci];
+            int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+            double sh[3];
+            cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+            bool hit = false;
+            V p, v;
+            if (lane < bn) {
+                p = a.pm[b0 + lane];
+                v = a.vh[b0 + lane];
+                p.x = p.x + (T)sh[0];
+                p.y = p.y + (T)sh[1];
+                p.z = p.z + (T)sh[2];
+                T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
+                hit = d2 < R2c || d2 * v.w * v.w < T(4);
             }
-            if (nsub > kSubCap) sub_direct = true;
-            wave_sync();
+            uint64_t m = __ballot(hit);
+            int off = o0 + __popcll(m & lanemask_lt()) - w0;
+            if (hit && off >= 0 && off < STAGE) {
+                spm[off] = p;
+                svh[off] = v;
+                sth[off] = a.th[b0 + lane];
+            }
         }
-
-        FSum<T> S;
-        S.x.zero(); S.y.zero(); S.z.zero(); S.u.zero();
-        S.alpha = (T)a.alpha;
-        S.beta = (T)a.beta;
-        S.tx = tp.x; S.ty = tp.y; S.tz = tp.z;
-        S.tvx = tv.x; S.tvy = tv.y; S.tvz = tv.z;
-        S.ha_inv = tv.w;
-        S.ha_inv2 = tv.w * tv.w;
-        S.ha_inv4 = S.ha_inv2 * S.ha_inv2;
-        S.Pa = tt.x; S.Ga = tt.y; S.ca = tt.z;
-        S.vs = S.alpha * S.ca;
-        if (!sub_direct) {
-            for (int k = j; k < nsub; k += kGroup) {
-                int e = sub[w][k];
+        __syncthreads();
+        if (!wave_busy) continue;
+        // this target's own pairs: r^2 < 4 max(h_a, h_b)^2
+        const T Ra = valid ? T(2) / tv.w : T(0);
+        build_lists16<T>(
+            nstg, spm, sub[w], &tls[0][0], kTCap, s_tlen,
+            [&](int k) {
+                V q;
+                int tt = 16 * w + k;
+                if (tt < cnt) q = a.pm[s0 + tt];
+                else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
+                return q;
+            },
+            [&](int k) { return __shfl(Ra, 4 * k, kWave); },
+            [&](T d2, T Rs2, int e) {
+                T hb = svh[e].w;
+                return d2 < Rs2 || d2 * hb * hb < T(4);
+            },
+            [&](const V &q, T rk, int e) {
+                V p = spm[e];
+                T hb = svh[e].w;
+                T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                T r2 = dx * dx + dy * dy + dz * dz;
+                return r2 < rk * rk || r2 * hb * hb < T(4);
+            });
+        const int tlen = s_tlen[t < kCell ? t : 0];
+        if (!valid) continue;
+        if (tlen <= kTCap) {
+            for (int k = j; k < tlen; k += kLanes) {
+                int e = mylist[k];
                 V p = spm[e];
                 S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, svh[e], sth[e]);
             }
         } else {
-            for (int ci = 0; ci < nc; ++ci) {
-                int cc = sA[ci];
-                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                double sh[3];
-                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-                T sx = (T)sh[0], sy = (T)sh[1], sz = (T)sh[2];
-                for (int k = j; k < bn; k += kGroup) {
-                    V p = a.pm[b0 + k];
-                    S.pair(tp.x - (p.x + sx), tp.y - (p.y + sy), tp.z - (p.z + sz), p.w,
-                           a.vh[b0 + k], a.th[b0 + k]);
-                }
+            // own list overflowed: walk the whole window
+            for (int e = j; e < nstg; e += kLanes) {
+                V p = spm[e];
+                S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, svh[e], sth[e]);
             }
         }
-        S.x.reduce16();
-        S.y.reduce16();
-        S.z.reduce16();
-        S.u.reduce16();
-        T vs = wmax16(S.vs);
-        if (valid && j == 0) {
-            double sc = a.m0 / kPi;
-            int64_t i = s0 + t;
-            a.ax[i] = (T)(sc * S.x.value());
-            a.ay[i] = (T)(sc * S.y.value());
-            a.az[i] = (T)(sc * S.z.value());
-            a.dudt[i] = (T)(sc * S.u.value());
-            if (a.vsig) a.vsig[i] = vs;
-        }
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_ovf) atomicOr(&a.status[ST_OVERFLOW], 1);
+
+    S.x.template reduce<kLanes>();
+    S.y.template reduce<kLanes>();
+    S.z.template reduce<kLanes>();
+    S.u.template reduce<kLanes>();
+    T vs = max4(S.vs);
+    if (valid && j == 0) {
+        double sc = a.m0 / kPi;
+        int64_t i = s0 + t;
+        a.ax[i] = (T)(sc * S.x.value());
+        a.ay[i] = (T)(sc * S.y.value());
+        a.az[i] = (T)(sc * S.z.value());
+        a.dudt[i] = (T)(sc * S.u.value());
+        if (a.vsig) a.vsig[i] = vs;
+    }
 }
 
 }  // namespace

@@ -13,6 +13,9 @@
 //  3. sub-block lists: the 64 targets form 16 sub-blocks of 4; a wavefront
 //     serves one sub-block at a time with 16 lanes per target, and the staged
 //     candidates that can reach the sub-block are listed (u16 LDS indices).
+//  4. per-target lists: each target's 16 lanes keep, from its sub-block list,
+//     the candidates inside its own support (with margin); the pair loops walk
+//     only those.
 //  If the staged set or a sub-block list does not fit in LDS, that work reads
 //  the candidate cells straight from global memory instead (same arithmetic,
 //  slower), so no capacity limit changes a result.
@@ -26,7 +29,18 @@ constexpr int kSearchThreads = 256;
 constexpr int kWaves = kSearchThreads / kWave;
 constexpr int kCandCap = 1024;   // candidate cells per target cell
 constexpr int kSubCap = 512;     // staged candidates per sub-block
-constexpr int kGroup = 16;       // lanes per target
+constexpr int kGroup = 16;       // lanes per target (sub-block layout)
+constexpr int kLanes = 4;        // lanes per target (one target per lane group of 4)
+constexpr int kTCap = 192;       // per-target candidate list (u16 LDS indices)
+
+// Orders LDS traffic between the lanes of one wavefront (a compiler and
+// memory fence at wavefront scope; the wavefront runs in lockstep).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct Tree {
     const Hdr *hdr;
@@ -36,13 +50,26 @@ struct Tree {
     Box box;
 };
 
-// Orders LDS traffic between the lanes of one wavefront (a compiler and
-// memory fence at wavefront scope; the wavefront runs in lockstep).
-__device__ inline void wave_sync()
+// Appends the lanes' hits to a per-group (16-lane) list; len is group-uniform.
+__device__ inline void group_append(bool hit, uint16_t e, uint16_t *list, int &len)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int grp = lane_id() >> 4, j = lane_id() & 15;
+    uint64_t m = __ballot(hit);
+    uint32_t gm = (uint32_t)(m >> (16 * grp)) & 0xffffu;
+    int pos = len + __popc(gm & ((1u << j) - 1u));
+    if (hit && pos < kTCap) list[pos] = e;
+    len += __popc(gm);
+}
+
+// Appends the lanes' hits to a per-target (4-lane) list; len is group-uniform.
+__device__ inline void quad_append(bool hit, uint16_t e, uint16_t *list, int cap, int &len)
+{
+    int q = lane_id() >> 2, j = lane_id() & 3;
+    uint64_t m = __ballot(hit);
+    uint32_t gm = (uint32_t)(m >> (4 * q)) & 0xfu;
+    int pos = len + __popc(gm & ((1u << j) - 1u));
+    if (hit && pos < cap) list[pos] = e;
+    len += __popc(gm);
 }
 
 // Breadth-first traversal by one wavefront.  Keeps the nodes whose box lies
@@ -175,6 +202,52 @@ __device__ inline T wsum16(T v)
     return v;
 }
 
+// Reductions over the 4 lanes of a target.
+template <class T>
+__device__ inline T sum4(T v)
+{
+    v += __shfl_xor(v, 1, kLanes);
+    v += __shfl_xor(v, 2, kLanes);
+    return v;
+}
+template <class T>
+__device__ inline T min4(T v)
+{
+    T u = __shfl_xor(v, 1, kLanes);
+    v = v < u ? v : u;
+    u = __shfl_xor(v, 2, kLanes);
+    return v < u ? v : u;
+}
+template <class T>
+__device__ inline T max4(T v)
+{
+    T u = __shfl_xor(v, 1, kLanes);
+    v = v > u ? v : u;
+    u = __shfl_xor(v, 2, kLanes);
+    return v > u ? v : u;
+}
+// Max / min over the whole wavefront.
+template <class T>
+__device__ inline T wave_max64(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o, kWave);
+        v = v > u ? v : u;
+    }
+    return v;
+}
+template <class T>
+__device__ inline T wave_min64(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o, kWave);
+        v = v < u ? v : u;
+    }
+    return v;
+}
+
 // Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
 template <class T>
 __device__ inline T wmax_groups(T v)
@@ -193,6 +266,14 @@ __device__ inline T wmin_groups(T v)
     return v < u ? v : u;
 }
 
+// Square root and reciprocal square root in the pair precision: the FP32
+// form uses the hardware v_sqrt_f32 / v_rsq_f32 (about 1 ulp), the FP64 form
+// the correctly rounded library functions.
+__device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double psqrt(double x) { return sqrt(x); }
+__device__ inline float prsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double prsqrt(double x) { return 1.0 / sqrt(x); }
+
 // Compensated (Kahan) accumulation in the pair precision: the sum is s - c.
 template <class T>
 struct Acc {
@@ -209,12 +290,13 @@ struct Acc {
         c = (t - s) - y;
         s = t;
     }
-    // combine with the 15 other lanes of the group (TwoSum on the partials)
-    __device__ void reduce16()
+    // combine with the other lanes of a width-W group (TwoSum on the partials)
+    template <int W>
+    __device__ void reduce()
     {
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            T s2 = __shfl_xor(s, o, kGroup), c2 = __shfl_xor(c, o, kGroup);
+        for (int o = W / 2; o > 0; o >>= 1) {
+            T s2 = __shfl_xor(s, o, W), c2 = __shfl_xor(c, o, W);
             T t = s + s2;
             T bb = t - s;
             T err = (s - (t - bb)) + (s2 - bb);
@@ -222,7 +304,76 @@ struct Acc {
             s = t;
         }
     }
+    __device__ void reduce16() { reduce<kGroup>(); }
     __device__ double value() const { return (double)s - (double)c; }
 };
+
+// Per-target candidate lists for the 16 targets of a wavefront (targets
+// 16 w + k, k = 0..15), built with 16 lanes per target: for each sub-block of
+// 4 targets the wavefront lists the staged entries near the sub-block's box
+// (box_ok(d2, Rs2, e): d2 the squared distance of entry e to the box, Rs the
+// largest reach of the sub-block's targets), then each target's 16 lanes keep
+// the entries that accept(target position, reach, e).  pos(k) and reach(k)
+// give target slot k's position and reach (0: no list); every lane calls them.
+// sub is the wavefront's scratch list (room for nstg entries).  Writes
+// tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length above cap means the
+// list is incomplete and the caller must walk the staged set instead.
+template <class T, class Pos, class Reach, class BoxOk, class Accept>
+__device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *sub,
+                                     uint16_t *tls, int cap, int *tlen, Pos pos, Reach reach,
+                                     BoxOk box_ok, Accept accept)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, j = lane & 15;
+    for (int sb = 0; sb < 4; ++sb) {
+        const int k = 4 * sb + g;  // this lane's target slot in the wave
+        vec4_t<T> tp = pos(k);
+        T rk = reach(k);
+        T bigT = T(3.0e38);
+        bool act = rk > T(0);
+        T lox = wmin_groups(act ? tp.x : bigT), loy = wmin_groups(act ? tp.y : bigT),
+          loz = wmin_groups(act ? tp.z : bigT);
+        T hix = wmax_groups(act ? tp.x : -bigT), hiy = wmax_groups(act ? tp.y : -bigT),
+          hiz = wmax_groups(act ? tp.z : -bigT);
+        T Rs = wmax_groups(rk);
+        int len = 0;
+        if (Rs > T(0)) {
+            T Rs2 = Rs * Rs;
+            T bcx = T(0.5) * (lox + hix), bcy = T(0.5) * (loy + hiy), bcz = T(0.5) * (loz + hiz);
+            T bex = T(0.5) * (hix - lox), bey = T(0.5) * (hiy - loy), bez = T(0.5) * (hiz - loz);
+            int nsub = 0;
+            wave_sync();
+            for (int base = 0; base < nstg; base += kWave) {
+                int idx = base + lane;
+                bool hit = false;
+                if (idx < nstg) {
+                    vec4_t<T> p = stg[idx];
+                    hit = box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2,
+                                 idx);
+                }
+                uint64_t m = __ballot(hit);
+                if (hit) sub[nsub + __popcll(m & lanemask_lt())] = (uint16_t)idx;
+                nsub += __popcll(m);
+            }
+            wave_sync();
+            uint16_t *L = tls + (size_t)(16 * w + k) * cap;
+            for (int base = 0; base < nsub; base += kGroup) {
+                int k0 = base + j;
+                bool hit = false;
+                int e = 0;
+                if (k0 < nsub && act) {
+                    e = sub[k0];
+                    hit = accept(tp, rk, e);
+                }
+                uint64_t m = __ballot(hit);
+                uint32_t gm = (uint32_t)(m >> (16 * g)) & 0xffffu;
+                int p = len + __popc(gm & ((1u << j) - 1u));
+                if (hit && p < cap) L[p] = (uint16_t)e;
+                len += __popc(gm);
+            }
+        }
+        if (j == 0) tlen[16 * w + k] = len;
+    }
+    wave_sync();
+}
 
 }  // namespace apr
