@@ -542,11 +542,16 @@ static double wrap(double v, int periodic, double lo, double hi)
 /* that every leaf holds exactly two particles.                             */
 /* Readings: coordinates are quantised to 2^21 steps per axis over the box; */
 /* each node is cut on the axis of largest quantised extent (ties x<y<z) at */
-/* c = floor(mean quantised coordinate); the left side takes the k' smallest */
-/* particles in (coordinate, id) order, where k = #(coord < c) and k' = k if */
-/* k is even, k + 1 if k is odd and the left side is the smaller, k - 1 if   */
-/* k is odd otherwise, and 2 floor(n/4) if k = 0 (all equal to the mean).   */
-/* Both sides keep ascending id order.                                      */
+/* c = floor(mean quantised coordinate), left meaning coord < c.  If no     */
+/* coordinate lies below c the cut moves up one step (coord <= c); if then  */
+/* every coordinate is equal (all particles at one quantised point) the left */
+/* side is the first 2 floor(n/4) in id order.  With k the resulting left   */
+/* count, an odd k is made even by moving one particle across the cut      */
+/* towards balance: k + 1 (the smallest of the right side in (coordinate,  */
+/* id) order joins the left) if the left side is the smaller, else k - 1     */
+/* (the largest of the left side joins the right).  So the left side is    */
+/* always the k' smallest in (coordinate, id) order, and both sides keep    */
+/* ascending id order.                                                      */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const int64_t *qc[3]; /* quantised coordinates */
@@ -599,8 +604,14 @@ static void pair_tree(const tree_ctx *T, int64_t *idx, int64_t n, int64_t *pairs
     int64_t k = 0;
     for (int64_t i = 0; i < n; ++i)
         if (T->qc[ax][idx[i]] < c) k += 1;
+    if (k == 0) {
+        /* no coordinate below the cut: move it up one quantisation step */
+        c += 1;
+        for (int64_t i = 0; i < n; ++i)
+            if (T->qc[ax][idx[i]] < c) k += 1;
+    }
     int64_t kp;
-    if (k == 0) kp = 2 * (n / 4);
+    if (k == n) kp = 2 * (n / 4); /* all at one point: split by id */
     else if (k % 2 == 0) kp = k;
     else if (k < n - k) kp = k + 1;
     else kp = k - 1;

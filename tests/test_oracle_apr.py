@@ -221,3 +221,22 @@ def test_merge_uses_pair_centre_of_mass(orc):
     assert out["id"][0] == 2 and out["level"][0] == 0  # lower id kept, one level down
     assert out["x"][0] == (0.9 + 1.15) * 0.5 and out["vx"][0] == 2.0 and out["u"][0] == 1.5
     assert out["h"][0] == 0.1 * 1.2599210498948731647672106072782
+
+
+def test_pair_tree_degenerate_cuts(orc):
+    # quantised coordinates {5,5,5,5,5,5,5,9} (in steps): mean 5.5, floor 5, so
+    # nothing lies below the cut; it moves up one step to "<= 5", which holds 7
+    # (odd, larger side) -> the largest left particle (id 6) crosses over
+    step = 1.0 / 2097152.0
+    x = np.array([5, 5, 5, 5, 5, 5, 5, 9], float) * step + 0.25 * step
+    z = np.zeros(8)
+    ids = np.arange(8)
+    pr = orc.pair_tree(np.arange(8), x, z, z, ids, (0, 0, 0), (1, 1, 1))
+    got = sorted(map(tuple, np.sort(pr, 1).tolist()))
+    # left {0..5} -> split again at its mean (all equal -> by id): {0,1},{2,3},{4,5}
+    assert got == [(0, 1), (2, 3), (4, 5), (6, 7)]
+    # all particles at one point: split by id order only
+    xs = np.full(6, 0.5)
+    pr = orc.pair_tree(np.arange(6), xs, xs, xs, np.array([9, 3, 7, 1, 5, 11]), (0, 0, 0),
+                       (1, 1, 1))
+    assert sorted(map(tuple, np.sort(pr, 1).tolist())) == [(0, 5), (1, 3), (2, 4)]
