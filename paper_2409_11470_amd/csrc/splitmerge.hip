@@ -1,12 +1,760 @@
-// Split/merge pass (placeholder until the GPU pass lands).
+// One split/merge pass (paper Sec. 2.2 splitting, Sec. 2.3 merging, Sec. 2.5
+// order: split from the lowest level up, merge from the highest level down, a
+// particle changes level at most once per pass).
+//
+// Split: a per-particle zone test and one scan place the new children; the
+// child axis, offset and the exact-centre-of-mass coordinate pair are
+// computed in FP64 with no contraction, so positions match a plain FP64
+// evaluation except for the last-place differences of sin/cos.
+//
+// Merge, per level l: the level-l candidates are compacted, sorted by id
+// (stable radix sort), and paired by a k-d tree built level-synchronously over
+// all nodes at once: per tree level, integer atomics give each node's extent,
+// coordinate sum, count below the cut and the (coordinate, id)-extreme
+// particles near the cut (integer atomics are order-independent, so the tree
+// is deterministic), and a stable scan partitions every node.  The tree's
+// rules (quantised coordinates, cut at floor(mean), even counts) are those in
+// include/apr.h.  Finally the leaf pairs whose centre of mass leaves the
+// level's zone merge, and a stable compaction removes the dropped particles.
 #include "common.hpp"
 
 namespace apr {
 
-int split_merge(apr_ctx *c, apr_state *, const apr_zone *, int, int64_t, int, int64_t *,
-                int64_t *, int64_t *)
+namespace {
+
+constexpr int kMaxZones = 8;
+constexpr double kCbrtHalf = 0.79370052598409973737585281963615;  // 2^(-1/3)
+constexpr double kCbrtTwo = 1.2599210498948731647672106072782;    // 2^(1/3)
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ULL;
+constexpr double kQuant = 2097152.0;  // 2^21 steps per axis
+constexpr int kIdBits = 43;           // (coordinate, id) keys: 21 + 43 bits
+
+struct Zones {
+    int nz, bg, derefine;
+    double c[kMaxZones][3];
+    int nsh[kMaxZones];
+    double r[kMaxZones][8];
+    int ell[kMaxZones][8];
+};
+
+// Level of a point: innermost sphere of each zone (strict), combined by max
+// (or min when derefining); *which = first zone giving the combined level.
+__device__ int zone_level(const Zones &Z, double x, double y, double z, int *which)
 {
-    return fail(c, APR_ERR_INVALID, "split/merge pass not available in this build");
+#pragma clang fp contract(off)
+    int best = Z.bg, w = -1;
+    for (int k = 0; k < Z.nz; ++k) {
+        double dx = x - Z.c[k][0], dy = y - Z.c[k][1], dz = z - Z.c[k][2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        int lev = -1;
+        for (int s = 0; s < Z.nsh[k]; ++s) {
+            double rr = Z.r[k][s];
+            if (d2 < rr * rr) lev = Z.ell[k][s];
+        }
+        if (lev < 0) continue;
+        if (Z.derefine ? (lev < best) : (lev > best)) {
+            best = lev;
+            w = k;
+        } else if (lev == best && w < 0) {
+            w = k;
+        }
+    }
+    if (which) *which = w;
+    return best;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): k-th output from state s.
+__device__ inline uint64_t sm64(uint64_t s, uint64_t k)
+{
+    uint64_t z = s + k * kGamma;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint64_t stream_state(uint64_t seed, int64_t step, int64_t id)
+{
+    uint64_t a = sm64((uint64_t)step, 1);
+    uint64_t b = sm64((uint64_t)id ^ a, 1);
+    return sm64(seed ^ b, 1);
+}
+
+__device__ inline double u53(uint64_t v) { return (double)(v >> 11) * 0x1.0p-53; }
+
+// Split axis: tangential to zone `zone` (rotated about x - c by 2 pi U1), or
+// uniform on the sphere (cos theta = 2 U1 - 1, phi = 2 pi U2).
+__device__ void split_axis(const Zones &Z, int zone, int mode, uint64_t s, double x, double y,
+                           double z, double w[3])
+{
+#pragma clang fp contract(off)
+    const double pi = 3.14159265358979323846;
+    double U1 = u53(sm64(s, 1)), U2 = u53(sm64(s, 2));
+    if (mode == APR_SPLIT_TANGENTIAL && zone >= 0) {
+        double v[3] = {x - Z.c[zone][0], y - Z.c[zone][1], z - Z.c[zone][2]};
+        double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (vn > 0.0) {
+            int k = 0;
+            if (fabs(v[1]) < fabs(v[k])) k = 1;
+            if (fabs(v[2]) < fabs(v[k])) k = 2;
+            double e[3] = {0.0, 0.0, 0.0};
+            e[k] = 1.0;
+            double w0[3] = {v[1] * e[2] - v[2] * e[1], v[2] * e[0] - v[0] * e[2],
+                            v[0] * e[1] - v[1] * e[0]};
+            double wn = sqrt(w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2]);
+            w0[0] /= wn;
+            w0[1] /= wn;
+            w0[2] /= wn;
+            double vh[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+            double b[3] = {vh[1] * w0[2] - vh[2] * w0[1], vh[2] * w0[0] - vh[0] * w0[2],
+                           vh[0] * w0[1] - vh[1] * w0[0]};
+            double t = 2.0 * pi * U1;
+            double ct = cos(t), st = sin(t);
+            for (int i = 0; i < 3; ++i) w[i] = w0[i] * ct + b[i] * st;
+            return;
+        }
+    }
+    double cth = 2.0 * U1 - 1.0;
+    double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+    double ph = 2.0 * pi * U2;
+    w[0] = sth * cos(ph);
+    w[1] = sth * sin(ph);
+    w[2] = cth;
+}
+
+// Coordinates of the two children x +- d with x+ + x- = 2x exactly whenever
+// |d| <= |x|: round the child on the far side from zero, take the exact shift
+// d' = x_far - x, set the near child to x - d' (exact).
+__device__ void split_pair_coord(double x, double d, double *xp, double *xm)
+{
+#pragma clang fp contract(off)
+    if (x != 0.0 && fabs(d) <= fabs(x)) {
+        double sgn = x > 0.0 ? 1.0 : -1.0;
+        double far = x + sgn * fabs(d);
+        double dd = far - x;
+        double near = x - dd;
+        bool plus_is_far = (d * sgn) >= 0.0;
+        *xp = plus_is_far ? far : near;
+        *xm = plus_is_far ? near : far;
+    } else {
+        *xp = x + d;
+        *xm = x - d;
+    }
+}
+
+__device__ inline double wrap(double v, const Box &b, int k)
+{
+    if (!b.periodic) return v;
+    double hi = b.lo[k] + b.L[k];
+    if (v >= hi) return v - b.L[k];
+    if (v < b.lo[k]) return v + b.L[k];
+    return v;
+}
+
+struct SArr {
+    double *x, *y, *z, *vx, *vy, *vz, *u, *h, *ax, *ay, *az, *dudt;
+    int8_t *level;
+    int64_t *id;
+};
+
+__global__ void k_split_flags(int64_t n, SArr s, Zones Z, uint32_t *flag, int8_t *zone_of)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int w;
+    int lz = zone_level(Z, s.x[i], s.y[i], s.z[i], &w);
+    flag[i] = s.level[i] < lz ? 1u : 0u;
+    zone_of[i] = (int8_t)w;
+}
+
+template <class D>
+__global__ void k_split_apply(int64_t n, SArr s, Zones Z, Box b, const uint32_t *flag,
+                              const uint32_t *rank, const int8_t *zone_of, const D *dnn,
+                              double r_sep_factor, double nn_cap, int mode, uint64_t seed,
+                              int64_t step, int64_t next_id, uint8_t *changed)
+{
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    int64_t slot = n + rank[i];
+    uint64_t st = stream_state(seed, step, s.id[i]);
+    double w[3];
+    double px = s.x[i], py = s.y[i], pz = s.z[i];
+    split_axis(Z, zone_of[i], mode, st, px, py, pz, w);
+    double r = r_sep_factor * s.h[i];
+    if (nn_cap > 0.0 && dnn) {
+        double dn = (double)dnn[i];
+        if (isfinite(dn) && nn_cap * dn < r) r = nn_cap * dn;
+    }
+    double p[3] = {px, py, pz}, xp[3], xm[3];
+    for (int k = 0; k < 3; ++k) split_pair_coord(p[k], r * w[k], &xp[k], &xm[k]);
+    s.x[slot] = wrap(xm[0], b, 0);
+    s.y[slot] = wrap(xm[1], b, 1);
+    s.z[slot] = wrap(xm[2], b, 2);
+    s.x[i] = wrap(xp[0], b, 0);
+    s.y[i] = wrap(xp[1], b, 1);
+    s.z[i] = wrap(xp[2], b, 2);
+    s.vx[slot] = s.vx[i];
+    s.vy[slot] = s.vy[i];
+    s.vz[slot] = s.vz[i];
+    s.u[slot] = s.u[i];
+    if (s.ax) s.ax[slot] = s.ax[i];
+    if (s.ay) s.ay[slot] = s.ay[i];
+    if (s.az) s.az[slot] = s.az[i];
+    if (s.dudt) s.dudt[slot] = s.dudt[i];
+    double hc = s.h[i] * kCbrtHalf;
+    s.h[i] = hc;
+    s.h[slot] = hc;
+    int8_t lv = (int8_t)(s.level[i] + 1);
+    s.level[i] = lv;
+    s.level[slot] = lv;
+    s.id[slot] = next_id + (int64_t)rank[i];
+    changed[i] = 1;
+    changed[slot] = 1;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_max_level(int64_t n, const int8_t *level, int32_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, (int32_t)level[i]);
+}
+
+__global__ void k_cand_flags(int64_t n, const int8_t *level, const uint8_t *changed,
+                             const uint8_t *removed, int l, uint32_t *flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (level[i] == l && !changed[i] && !removed[i]) ? 1u : 0u;
+}
+
+__global__ void k_compact_idx(int64_t n, const uint32_t *flag, const uint32_t *pos,
+                              uint32_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) out[pos[i]] = (uint32_t)i;
+}
+
+__global__ void k_id_keys(int64_t m, const uint32_t *slot, const int64_t *id, int high,
+                          uint32_t *key)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    uint64_t v = (uint64_t)id[slot[i]];
+    key[i] = high ? (uint32_t)(v >> 32) : (uint32_t)v;
+}
+
+__device__ inline int32_t quantise(double v, double lo, double s)
+{
+    double f = floor((v - lo) * s);
+    if (f < 0.0) f = 0.0;
+    if (f > kQuant - 1.0) f = kQuant - 1.0;
+    return (int32_t)f;
+}
+
+// quantised coordinates, stored per particle slot
+__global__ void k_quant(int64_t m, const uint32_t *slot, SArr s, Box b, double s0, double s1,
+                        double s2, int32_t *qx, int32_t *qy, int32_t *qz)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    uint32_t p = slot[i];
+    qx[p] = quantise(s.x[p], b.lo[0], s0);
+    qy[p] = quantise(s.y[p], b.lo[1], s1);
+    qz[p] = quantise(s.z[p], b.lo[2], s2);
+}
+
+// ------------------------------------------------------------ pairing tree
+// Element arrays (position i in the tree order): es[i] particle slot, lo[i],
+// hi[i] the range of its node.  Node statistics live at the node's start.
+struct Node {
+    int32_t mn[3], mx[3];
+    unsigned long long sum;
+    uint32_t kc, keq;
+    unsigned long long amin_c, amax_c, amin_c1, amax_c1;
+    int32_t ax, cut, kp, all_eq;
+    unsigned long long moved;
+};
+
+struct TreeArgs {
+    int64_t m;
+    const uint32_t *es;
+    const int32_t *lo, *hi;
+    const int32_t *q[3];
+    const int64_t *id;
+    Node *node;
+};
+
+__device__ inline bool active(const TreeArgs &a, int64_t i) { return a.hi[i] - a.lo[i] > 2; }
+
+__global__ void k_tree_init(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
+    Node &nd = a.node[i];
+    for (int k = 0; k < 3; ++k) {
+        nd.mn[k] = INT32_MAX;
+        nd.mx[k] = INT32_MIN;
+    }
+    nd.sum = 0;
+    nd.kc = 0;
+    nd.keq = 0;
+    nd.amin_c = ~0ull;
+    nd.amax_c = 0;
+    nd.amin_c1 = ~0ull;
+    nd.amax_c1 = 0;
+    nd.moved = ~0ull;
+}
+
+__global__ void k_tree_minmax(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || !active(a, i)) return;
+    Node &nd = a.node[a.lo[i]];
+    uint32_t p = a.es[i];
+    for (int k = 0; k < 3; ++k) {
+        atomicMin(&nd.mn[k], a.q[k][p]);
+        atomicMax(&nd.mx[k], a.q[k][p]);
+    }
+}
+
+__global__ void k_tree_axis(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
+    Node &nd = a.node[i];
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+        if (nd.mx[k] - nd.mn[k] > nd.mx[ax] - nd.mn[ax]) ax = k;
+    nd.ax = ax;
+}
+
+__global__ void k_tree_sum(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || !active(a, i)) return;
+    Node &nd = a.node[a.lo[i]];
+    atomicAdd(&nd.sum, (unsigned long long)a.q[nd.ax][a.es[i]]);
+}
+
+__global__ void k_tree_count(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || !active(a, i)) return;
+    int32_t L = a.lo[i];
+    Node &nd = a.node[L];
+    int64_t n = a.hi[i] - L;
+    int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
+    uint32_t p = a.es[i];
+    int64_t v = a.q[nd.ax][p];
+    unsigned long long key =
+        ((unsigned long long)v << kIdBits) | ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
+    if (v < c) {
+        atomicAdd(&nd.kc, 1u);
+        atomicMax(&nd.amax_c, key);
+    } else {
+        atomicMin(&nd.amin_c, key);
+    }
+    if (v == c) atomicAdd(&nd.keq, 1u);
+    if (v <= c) atomicMax(&nd.amax_c1, key);
+    else atomicMin(&nd.amin_c1, key);
+}
+
+__global__ void k_tree_decide(TreeArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
+    Node &nd = a.node[i];
+    int64_t n = a.hi[i] - i;
+    int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
+    int64_t k = nd.kc;
+    unsigned long long amin = nd.amin_c, amax = nd.amax_c;
+    if (k == 0) {  // nothing below the cut: move it up one step
+        c += 1;
+        k = nd.keq;
+        amin = nd.amin_c1;
+        amax = nd.amax_c1;
+    }
+    nd.cut = (int32_t)c;
+    nd.all_eq = 0;
+    nd.moved = ~0ull;
+    if (k == n) {
+        nd.all_eq = 1;
+        nd.kp = (int32_t)(2 * (n / 4));
+    } else if (k % 2 == 0) {
+        nd.kp = (int32_t)k;
+    } else if (k < n - k) {
+        nd.kp = (int32_t)(k + 1);
+        nd.moved = amin;
+    } else {
+        nd.kp = (int32_t)(k - 1);
+        nd.moved = amax;
+    }
+}
+
+__global__ void k_tree_left(TreeArgs a, uint32_t *left)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    if (!active(a, i)) {
+        left[i] = 1u;  // leaves stay in place
+        return;
+    }
+    int32_t L = a.lo[i];
+    const Node &nd = a.node[L];
+    uint32_t p = a.es[i];
+    bool l;
+    if (nd.all_eq) {
+        l = (i - L) < nd.kp;
+    } else {
+        int64_t v = a.q[nd.ax][p];
+        l = v < nd.cut;
+        unsigned long long key = ((unsigned long long)v << kIdBits) |
+                                 ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
+        if (key == nd.moved) l = !l;
+    }
+    left[i] = l ? 1u : 0u;
+}
+
+__global__ void k_tree_partition(TreeArgs a, const uint32_t *left, const uint32_t *lscan,
+                                 uint32_t *es2, int32_t *lo2, int32_t *hi2, int32_t *more)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.m) return;
+    int32_t L = a.lo[i], H = a.hi[i];
+    if (H - L <= 2) {
+        es2[i] = a.es[i];
+        lo2[i] = L;
+        hi2[i] = H;
+        return;
+    }
+    int32_t kp = a.node[L].kp;
+    int64_t lr = (int64_t)lscan[i] - (int64_t)lscan[L];
+    int64_t pos;
+    int32_t nl, nh;
+    if (left[i]) {
+        pos = L + lr;
+        nl = L;
+        nh = L + kp;
+    } else {
+        pos = L + kp + (i - L - lr);
+        nl = L + kp;
+        nh = H;
+    }
+    es2[pos] = a.es[i];
+    lo2[pos] = nl;
+    hi2[pos] = nh;
+    if (nh - nl > 2) atomicOr(more, 1);
+}
+
+__global__ void k_tree_root(int64_t m, int32_t *lo, int32_t *hi)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    lo[i] = 0;
+    hi[i] = (int32_t)m;
+}
+
+__global__ void k_merge_pairs(int64_t npairs, const uint32_t *es, SArr s, Zones Z, int l,
+                              uint8_t *changed, uint8_t *removed, unsigned long long *count)
+{
+#pragma clang fp contract(off)
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    uint32_t p = es[2 * k], q = es[2 * k + 1];
+    double cx = (s.x[p] + s.x[q]) * 0.5;
+    double cy = (s.y[p] + s.y[q]) * 0.5;
+    double cz = (s.z[p] + s.z[q]) * 0.5;
+    if (!(zone_level(Z, cx, cy, cz, nullptr) < l)) return;
+    uint32_t keep = s.id[p] < s.id[q] ? p : q;
+    uint32_t gone = keep == p ? q : p;
+    s.x[keep] = cx;
+    s.y[keep] = cy;
+    s.z[keep] = cz;
+    s.vx[keep] = (s.vx[p] + s.vx[q]) * 0.5;
+    s.vy[keep] = (s.vy[p] + s.vy[q]) * 0.5;
+    s.vz[keep] = (s.vz[p] + s.vz[q]) * 0.5;
+    s.u[keep] = (s.u[p] + s.u[q]) * 0.5;
+    s.h[keep] = s.h[keep] * kCbrtTwo;
+    s.level[keep] = (int8_t)(l - 1);
+    changed[keep] = 1;
+    removed[gone] = 1;
+    atomicAdd(count, 1ull);
+}
+
+__global__ void k_keep_flags(int64_t n, const uint8_t *removed, uint32_t *flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = removed[i] ? 0u : 1u;
+}
+
+struct CompactArgs {
+    double *d[12], *dt[12];
+    int nd;
+    int8_t *lev, *levt;
+    int64_t *id, *idt;
+    const uint32_t *keep, *pos;
+    int64_t n;
+};
+
+__global__ void k_compact_gather(CompactArgs a)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n || !a.keep[i]) return;
+    uint32_t j = a.pos[i];
+    for (int k = 0; k < a.nd; ++k) a.dt[k][j] = a.d[k][i];
+    a.levt[j] = a.lev[i];
+    a.idt[j] = a.id[i];
+}
+
+__global__ void k_compact_back(CompactArgs a, int64_t m)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int k = 0; k < a.nd; ++k) a.d[k][i] = a.dt[k][i];
+    a.lev[i] = a.levt[i];
+    a.id[i] = a.idt[i];
+}
+
+unsigned grid(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 256); }
+
+}  // namespace
+
+int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
+                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare)
+{
+    const apr_params &P = c->p;
+    if (nzones > kMaxZones) return fail(c, APR_ERR_INVALID, "at most 8 zones");
+    bool do_split = flags == 0 || (flags & 1);
+    bool do_merge = flags == 0 || (flags & 2);
+    *n_split = 0;
+    *n_merged = 0;
+    *n_spare = 0;
+    Zones Z;
+    std::memset(&Z, 0, sizeof(Z));
+    Z.nz = nzones;
+    Z.bg = P.ell_background;
+    Z.derefine = P.derefine;
+    for (int k = 0; k < nzones; ++k) {
+        for (int d = 0; d < 3; ++d) Z.c[k][d] = zones[k].c[d];
+        Z.nsh[k] = zones[k].n;
+        for (int sh = 0; sh < zones[k].n; ++sh) {
+            Z.r[k][sh] = zones[k].r[sh];
+            Z.ell[k][sh] = zones[k].ell[sh];
+        }
+    }
+    if (s->next_id + s->n >= (int64_t)1 << kIdBits) return fail(c, APR_ERR_INVALID, "ids too large");
+    Box b = make_box(P);
+    SArr A = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->h,
+              s->ax, s->ay, s->az, s->dudt, s->level, s->id};
+    int64_t cap = s->capacity;
+    int64_t n = s->n;
+    int tok = prof_begin(c, APR_PROF_SPLITMERGE);
+
+    uint32_t *flag = wsa<uint32_t>(c, "sm_flag", (size_t)cap);
+    uint32_t *scan = wsa<uint32_t>(c, "sm_scan", (size_t)cap);
+    uint32_t *tot = wsa<uint32_t>(c, "sm_tot", 4);
+    int8_t *zone_of = wsa<int8_t>(c, "sm_zone", (size_t)cap);
+    uint8_t *changed = wsa<uint8_t>(c, "sm_changed", (size_t)cap);
+    uint8_t *removed = wsa<uint8_t>(c, "sm_removed", (size_t)cap);
+    int32_t *imax = wsa<int32_t>(c, "sm_imax", 4);
+    unsigned long long *mcount = wsa<unsigned long long>(c, "sm_mcount", 2);
+    if (!flag || !scan || !tot || !zone_of || !changed || !removed || !imax || !mcount)
+        return fail(c, APR_ERR_HIP, "split/merge workspace");
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid(cap)), dim3(256), 0, c->stream, changed, (uint8_t)0,
+                       cap);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid(cap)), dim3(256), 0, c->stream, removed, (uint8_t)0,
+                       cap);
+    APR_LAUNCHED(c);
+    uint32_t h32 = 0;
+
+    if (do_split) {
+        hipLaunchKernelGGL(k_split_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, A, Z, flag,
+                           zone_of);
+        APR_LAUNCHED(c);
+        int rc = exclusive_scan_u32(c, flag, scan, n, tot);
+        if (rc) return rc;
+        APR_HIP(c, hipMemcpyAsync(&h32, tot, 4, hipMemcpyDeviceToHost, c->stream));
+        APR_HIP(c, hipStreamSynchronize(c->stream));
+        int64_t ns = h32;
+        if (n + ns > cap) {
+            prof_end(c, tok);
+            *n_split = n + ns;
+            return fail(c, APR_ERR_CAPACITY, "splits need more capacity");
+        }
+        if (ns > 0) {
+            bool cap_nn = P.nn_cap > 0.0;
+            if (cap_nn && c->dens_n != n) {
+                prof_end(c, tok);
+                return fail(c, APR_ERR_INVALID,
+                            "nn_cap > 0 needs apr_density on the current state first");
+            }
+            if (P.precision == APR_FP32) {
+                const float *dnn = cap_nn ? wsa<float>(c, "dnn32", (size_t)cap) : nullptr;
+                hipLaunchKernelGGL(k_split_apply<float>, dim3(grid(n)), dim3(256), 0, c->stream,
+                                   n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
+                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);
+            } else {
+                const double *dnn = cap_nn ? wsa<double>(c, "dnn64", (size_t)cap) : nullptr;
+                hipLaunchKernelGGL(k_split_apply<double>, dim3(grid(n)), dim3(256), 0, c->stream,
+                                   n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
+                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);
+            }
+            APR_LAUNCHED(c);
+            n += ns;
+            s->next_id += ns;
+            s->n = n;
+        }
+        *n_split = ns;
+    }
+
+    if (do_merge && n > 1) {
+        APR_HIP(c, hipMemsetAsync(imax, 0, 4, c->stream));
+        APR_HIP(c, hipMemsetAsync(mcount, 0, 8, c->stream));
+        hipLaunchKernelGGL(k_max_level, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
+                           imax);
+        APR_LAUNCHED(c);
+        int32_t lmax = 0;
+        APR_HIP(c, hipMemcpyAsync(&lmax, imax, 4, hipMemcpyDeviceToHost, c->stream));
+        APR_HIP(c, hipStreamSynchronize(c->stream));
+        uint32_t *cand = wsa<uint32_t>(c, "sm_cand", (size_t)n);
+        uint32_t *keys = wsa<uint32_t>(c, "sm_keys", (size_t)n);
+        int32_t *q[3] = {wsa<int32_t>(c, "sm_qx", (size_t)n), wsa<int32_t>(c, "sm_qy", (size_t)n),
+                         wsa<int32_t>(c, "sm_qz", (size_t)n)};
+        uint32_t *es[2] = {wsa<uint32_t>(c, "sm_es0", (size_t)n),
+                           wsa<uint32_t>(c, "sm_es1", (size_t)n)};
+        int32_t *lo[2] = {wsa<int32_t>(c, "sm_lo0", (size_t)n), wsa<int32_t>(c, "sm_lo1", (size_t)n)};
+        int32_t *hi[2] = {wsa<int32_t>(c, "sm_hi0", (size_t)n), wsa<int32_t>(c, "sm_hi1", (size_t)n)};
+        Node *node = wsa<Node>(c, "sm_node", (size_t)n);
+        int32_t *more = imax + 1;
+        if (!cand || !keys || !q[2] || !es[1] || !lo[1] || !hi[1] || !node)
+            return fail(c, APR_ERR_HIP, "merge workspace");
+        double sc[3];
+        for (int k = 0; k < 3; ++k) sc[k] = kQuant / b.L[k];
+        bool high_ids = s->next_id > (int64_t)0xffffffffLL;
+        for (int l = lmax; l >= 1; --l) {
+            hipLaunchKernelGGL(k_cand_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
+                               changed, removed, l, flag);
+            APR_LAUNCHED(c);
+            int rc = exclusive_scan_u32(c, flag, scan, n, tot);
+            if (rc) return rc;
+            APR_HIP(c, hipMemcpyAsync(&h32, tot, 4, hipMemcpyDeviceToHost, c->stream));
+            APR_HIP(c, hipStreamSynchronize(c->stream));
+            int64_t nc = h32;
+            if (nc % 2) *n_spare += 1;
+            int64_t m = nc - (nc % 2);
+            if (m < 2) continue;
+            hipLaunchKernelGGL(k_compact_idx, dim3(grid(n)), dim3(256), 0, c->stream, n, flag,
+                               scan, cand);
+            // ascending id (stable LSD: low 32 bits, then high)
+            hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
+                               s->id, 0, keys);
+            APR_LAUNCHED(c);
+            rc = radix_sort_u32(c, keys, cand, nc, 32);
+            if (rc) return rc;
+            if (high_ids) {
+                hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
+                                   s->id, 1, keys);
+                APR_LAUNCHED(c);
+                rc = radix_sort_u32(c, keys, cand, nc, 32);
+                if (rc) return rc;
+            }
+            // the highest id (last) sits out when nc is odd; tree over the first m
+            hipLaunchKernelGGL(k_quant, dim3(grid(m)), dim3(256), 0, c->stream, m, cand, A, b,
+                               sc[0], sc[1], sc[2], q[0], q[1], q[2]);
+            APR_HIP(c, hipMemcpyAsync(es[0], cand, (size_t)m * 4, hipMemcpyDeviceToDevice,
+                                      c->stream));
+            hipLaunchKernelGGL(k_tree_root, dim3(grid(m)), dim3(256), 0, c->stream, m, lo[0],
+                               hi[0]);
+            APR_LAUNCHED(c);
+            int cur = 0;
+            for (int depth = 0; m > 2 && depth < 4096; ++depth) {
+                TreeArgs ta;
+                ta.m = m;
+                ta.es = es[cur];
+                ta.lo = lo[cur];
+                ta.hi = hi[cur];
+                for (int k = 0; k < 3; ++k) ta.q[k] = q[k];
+                ta.id = s->id;
+                ta.node = node;
+                unsigned g = grid(m);
+                hipLaunchKernelGGL(k_tree_init, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_minmax, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_axis, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_sum, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_decide, dim3(g), dim3(256), 0, c->stream, ta);
+                hipLaunchKernelGGL(k_tree_left, dim3(g), dim3(256), 0, c->stream, ta, flag);
+                APR_LAUNCHED(c);
+                rc = exclusive_scan_u32(c, flag, scan, m, nullptr);
+                if (rc) return rc;
+                APR_HIP(c, hipMemsetAsync(more, 0, 4, c->stream));
+                hipLaunchKernelGGL(k_tree_partition, dim3(g), dim3(256), 0, c->stream, ta, flag,
+                                   scan, es[1 - cur], lo[1 - cur], hi[1 - cur], more);
+                APR_LAUNCHED(c);
+                cur = 1 - cur;
+                int32_t hm = 0;
+                APR_HIP(c, hipMemcpyAsync(&hm, more, 4, hipMemcpyDeviceToHost, c->stream));
+                APR_HIP(c, hipStreamSynchronize(c->stream));
+                if (!hm) break;
+                if (depth == 4095) {
+                    prof_end(c, tok);
+                    return fail(c, APR_ERR_INVALID, "pairing tree deeper than 4096 levels");
+                }
+            }
+            hipLaunchKernelGGL(k_merge_pairs, dim3(grid(m / 2)), dim3(256), 0, c->stream, m / 2,
+                               es[cur], A, Z, l, changed, removed, mcount);
+            APR_LAUNCHED(c);
+        }
+        unsigned long long nm = 0;
+        APR_HIP(c, hipMemcpyAsync(&nm, mcount, 8, hipMemcpyDeviceToHost, c->stream));
+        APR_HIP(c, hipStreamSynchronize(c->stream));
+        *n_merged = (int64_t)nm;
+        if (nm > 0) {
+            // stable compaction of the survivors
+            hipLaunchKernelGGL(k_keep_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, removed,
+                               flag);
+            APR_LAUNCHED(c);
+            int rc = exclusive_scan_u32(c, flag, scan, n, tot);
+            if (rc) return rc;
+            CompactArgs ca;
+            std::memset(&ca, 0, sizeof(ca));
+            double *arrs[12] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->h,
+                                s->ax, s->ay, s->az, s->dudt};
+            static const char *tn[12] = {"pt0", "pt1", "pt2", "pt3", "pt4", "pt5",
+                                         "pt6", "pt7", "pt8", "pt9", "pt10", "pt11"};
+            for (int k = 0; k < 12; ++k) {
+                if (!arrs[k]) continue;
+                ca.d[ca.nd] = arrs[k];
+                ca.dt[ca.nd] = wsa<double>(c, tn[ca.nd], (size_t)n);
+                if (!ca.dt[ca.nd]) return fail(c, APR_ERR_HIP, "compaction workspace");
+                ca.nd += 1;
+            }
+            ca.lev = s->level;
+            ca.levt = wsa<int8_t>(c, "pt_lev", (size_t)n);
+            ca.id = s->id;
+            ca.idt = wsa<int64_t>(c, "pt_id", (size_t)n);
+            ca.keep = flag;
+            ca.pos = scan;
+            ca.n = n;
+            int64_t m = n - (int64_t)nm;
+            hipLaunchKernelGGL(k_compact_gather, dim3(grid(n)), dim3(256), 0, c->stream, ca);
+            hipLaunchKernelGGL(k_compact_back, dim3(grid(m)), dim3(256), 0, c->stream, ca, m);
+            APR_LAUNCHED(c);
+            n = m;
+            s->n = n;
+        }
+    }
+    prof_end(c, tok);
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    c->cells_n = -1;
+    c->dens_n = -1;
+    c->force_n = -1;
+    return APR_OK;
 }
 
 }  // namespace apr
