@@ -301,7 +301,7 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
         int64_t ns = 0, nm = 0, nsp = 0;
         rc = apr_split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp);
         if (rc) return rc;
-        if (ns + nm > 0) {
+        if (ns + nm > 0 || c->cells_n != s->n) {
             rc = build_cells(c, s, nullptr);
             if (rc) return rc;
         }

@@ -751,9 +751,11 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     }
     prof_end(c, tok);
     APR_HIP(c, hipStreamSynchronize(c->stream));
-    c->cells_n = -1;
-    c->dens_n = -1;
-    c->force_n = -1;
+    if (*n_split + *n_merged > 0) {  // the particle set changed: cells are stale
+        c->cells_n = -1;
+        c->dens_n = -1;
+        c->force_n = -1;
+    }
     return APR_OK;
 }
 
