@@ -151,6 +151,25 @@ int apr_density(apr_ctx *ctx, apr_state *s, void *rho, void *omega, int32_t *nne
 int apr_forces(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega, void *ax,
                void *ay, void *az, void *dudt, void *vsig);
 
+/* Vector-Jacobian product of the density and force sums (the adjoint; the
+ * paper has none, it serves to tune split offsets against the density error
+ * of Sec. 2.2 and 3.3).  Forward: rho, Omega at the h that solves
+ * rho_sum(h) = m (hfact/h)^3 (apr_density, whose h s->h holds), then
+ * apr_forces' a and du/dt.  Given cotangents rho_bar [n], h_bar [n],
+ * ax_bar, ay_bar, az_bar, dudt_bar [n] (each may be NULL: zero), writes
+ *   xbar, ybar, zbar [n] = dL/dx, dL/dy, dL/dz,   mbar [n] = dL/dm_a,
+ * L = sum_a rho_bar rho + h_bar h + abar . a + dudt_bar du/dt, with h
+ * implicit in (x, m) (implicit-function theorem on the h-rho relation: the
+ * density tangent is (d rho_sum at fixed h)/Omega) and m_a = m0 2^-level_a
+ * taken as a free per-particle variable.  Velocities, u and sink terms are
+ * held fixed.  Neighbours are searched again, not stored.  rho, omega,
+ * cotangents and outputs are of the context precision; the cells must be
+ * those of the forward (apr_build_cells, then apr_density).  Asynchronous. */
+int apr_vjp(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega,
+            const void *rho_bar, const void *h_bar, const void *ax_bar, const void *ay_bar,
+            const void *az_bar, const void *dudt_bar, void *xbar, void *ybar, void *zbar,
+            void *mbar);
+
 /* Neighbour lists for a given h (device, [n]), with the FP64 predicate
  * r_ab^2 < (2 h_a)^2 (mode 0) or r_ab^2 < (2 max(h_a, h_b))^2 (mode 1), b != a,
  * evaluated on absolute positions with the minimum-image convention and no
@@ -219,11 +238,12 @@ int apr_sync_status(apr_ctx *ctx, int64_t *count);
 /* Kernel timing (diagnostics).  While enabled, HIP events on the context's
  * stream bracket every launch of the timed kernels: index APR_PROF_DENSITY
  * (h-rho Newton kernel), APR_PROF_FORCES (force kernel), APR_PROF_CELLS
- * (whole cell build), APR_PROF_SPLITMERGE (whole split/merge pass).
+ * (whole cell build), APR_PROF_SPLITMERGE (whole split/merge pass),
+ * APR_PROF_VJP (the three kernels of apr_vjp).
  * apr_profile_read synchronises, writes the summed milliseconds and launch
  * counts per index (arrays of APR_PROF_N) and, if reset, clears them. */
 enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
-       APR_PROF_N = 4 };
+       APR_PROF_VJP = 4, APR_PROF_N = 5 };
 int apr_profile_enable(apr_ctx *ctx, int on);
 /* Work counters since the last reset (diagnostics), written to c[0..7]:
  * [0] h-rho solves that hit max_iter, [1] overflowed lists without fallback,

@@ -7,7 +7,8 @@ APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP, APR_
 APR_FP64, APR_FP32 = 0, 1
 APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL, APR_EOS_ADIABATIC = 0, 1, 2
 APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM = 0, 1
-APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_N = 0, 1, 2, 3, 4
+APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP, APR_PROF_N = (
+    0, 1, 2, 3, 4, 5)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -75,6 +76,7 @@ def lib():
     L.apr_build_cells.argtypes = [_vp, C.POINTER(CState), _vp]
     L.apr_density.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp]
     L.apr_forces.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.apr_vjp.argtypes = [_vp, C.POINTER(CState)] + [_vp] * 12
     L.apr_neighbours.argtypes = [_vp, C.POINTER(CState), _vp, C.c_int32, _vp, _vp, _vp,
                                  C.c_int64, _i64p]
     L.apr_split_merge.argtypes = [_vp, C.POINTER(CState), C.POINTER(Zone), C.c_int32, C.c_int64,
@@ -88,7 +90,7 @@ def lib():
     L.apr_counters.argtypes = [_vp, _i64p, C.c_int]
     L.apr_profile_read.argtypes = [_vp, C.POINTER(C.c_double), _i64p, C.c_int]
     for f in ("apr_ctx_create", "apr_ctx_destroy", "apr_ctx_set_stream", "apr_build_cells",
-              "apr_density", "apr_forces", "apr_neighbours", "apr_split_merge", "apr_step",
+              "apr_density", "apr_forces", "apr_vjp", "apr_neighbours", "apr_split_merge", "apr_step",
               "apr_accel", "apr_timestep", "apr_sync_status", "apr_profile_enable",
               "apr_profile_read", "apr_counters"):
         getattr(L, f).restype = C.c_int

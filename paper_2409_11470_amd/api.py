@@ -155,6 +155,13 @@ class DeviceState:
         self.n = int(cs.n)
         self.next_id = int(cs.next_id)
 
+    def clone(self):
+        """A copy of the first n particles (capacity n)."""
+        c = DeviceState.__new__(DeviceState)
+        c.capacity, c.n, c.next_id = max(1, self.n), self.n, self.next_id
+        c.t = {k: v[:c.capacity].clone() for k, v in self.t.items()}
+        return c
+
     def grow(self, capacity):
         if capacity <= self.capacity:
             return
@@ -189,6 +196,19 @@ def apr_forces(ctx, st, rho, omega, ax, ay, az, dudt, vsig=None):
     cs = st.cstate()
     ctx.check(lib().apr_forces(ctx.ptr, C.byref(cs), _ptr(rho), _ptr(omega), _ptr(ax), _ptr(ay),
                                _ptr(az), _ptr(dudt), _ptr(vsig)))
+
+
+def apr_vjp(ctx, st, rho, omega, rho_bar=None, h_bar=None, ax_bar=None, ay_bar=None,
+            az_bar=None, dudt_bar=None):
+    """Adjoint of apr_density + apr_forces on the current cells: returns
+    (xbar, ybar, zbar, mbar), device tensors of the context precision."""
+    n = st.n
+    out = [torch.empty(n, dtype=ctx.dtype, device=rho.device) for _ in range(4)]
+    cs = st.cstate()
+    ctx.check(lib().apr_vjp(ctx.ptr, C.byref(cs), _ptr(rho), _ptr(omega), _ptr(rho_bar),
+                            _ptr(h_bar), _ptr(ax_bar), _ptr(ay_bar), _ptr(az_bar),
+                            _ptr(dudt_bar), *[_ptr(t) for t in out]))
+    return tuple(out)
 
 
 def apr_neighbours(ctx, st, h, mode=0):

@@ -213,6 +213,17 @@ int apr_forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omeg
     return forces(c, s, rho, omega, ax, ay, az, dudt, vsig);
 }
 
+int apr_vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
+            const void *rho_bar, const void *h_bar, const void *ax_bar, const void *ay_bar,
+            const void *az_bar, const void *dudt_bar, void *xbar, void *ybar, void *zbar,
+            void *mbar)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    return vjp(c, s, rho, omega, rho_bar, h_bar, ax_bar, ay_bar, az_bar, dudt_bar, xbar, ybar,
+               zbar, mbar);
+}
+
 int apr_neighbours(apr_ctx *c, const apr_state *s, const double *h, int32_t mode,
                    int64_t *counts, int64_t *offsets, int64_t *list, int64_t cap,
                    int64_t *total)

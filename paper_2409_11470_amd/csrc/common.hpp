@@ -209,6 +209,14 @@ Geo *cell_level(apr_ctx *c, int lev);
 int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters);
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
            void *ay, void *az, void *dudt, void *vsig);
+// EOS pack of forces.hip: vh = (v, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0)
+// into the workspace buffers vh32/th32 (FP32) or vh64/th64 (FP64).
+int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega);
+
+// adjoint.hip
+int vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, const void *rho_bar,
+        const void *h_bar, const void *ax_bar, const void *ay_bar, const void *az_bar,
+        const void *dudt_bar, void *xbar, void *ybar, void *zbar, void *mbar);
 
 // neighbours.hip
 int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_t *counts,

@@ -299,6 +299,29 @@ __global__ __launch_bounds__(kSearchThreads) void k_forces(ForceArgs<T> a)
 
 }  // namespace
 
+int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
+{
+    int64_t n = s->n;
+    const apr_params &p = c->p;
+    unsigned g = (unsigned)ceil_div(n, 256);
+    if (p.precision == APR_FP32) {
+        float4 *vh = wsa<float4>(c, "vh32", (size_t)n), *th = wsa<float4>(c, "th32", (size_t)n);
+        if (!vh || !th) return fail(c, APR_ERR_HIP, "workspace");
+        hipLaunchKernelGGL(k_eos<float>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
+                           p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
+                           (const float *)rho, (const float *)omega, vh, th);
+    } else {
+        double4 *vh = wsa<double4>(c, "vh64", (size_t)n),
+                *th = wsa<double4>(c, "th64", (size_t)n);
+        if (!vh || !th) return fail(c, APR_ERR_HIP, "workspace");
+        hipLaunchKernelGGL(k_eos<double>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
+                           p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
+                           (const double *)rho, (const double *)omega, vh, th);
+    }
+    APR_LAUNCHED(c);
+    return APR_OK;
+}
+
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
            void *ay, void *az, void *dudt, void *vsig)
 {
@@ -312,19 +335,16 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     // the force search needs the supports of the h the state holds now
     int rc = cells_hmax_from(c, s->h, n);
     if (rc) return rc;
+    rc = eos_pack(c, s, rho, omega);
+    if (rc) return rc;
     Tree tr = make_tree(c);
-    unsigned g = (unsigned)ceil_div(n, 256);
     if (p.precision == APR_FP32) {
-        float4 *vh = wsa<float4>(c, "vh32", (size_t)n), *th = wsa<float4>(c, "th32", (size_t)n);
-        hipLaunchKernelGGL(k_eos<float>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
-                           p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
-                           (const float *)rho, (const float *)omega, vh, th);
         int tok = prof_begin(c, APR_PROF_FORCES);
         ForceArgs<float> a;
         a.tree = tr;
         a.pm = wsa<float4>(c, "pm32", (size_t)n);
-        a.vh = vh;
-        a.th = th;
+        a.vh = wsa<float4>(c, "vh32", (size_t)n);
+        a.th = wsa<float4>(c, "th32", (size_t)n);
         a.ax = (float *)ax; a.ay = (float *)ay; a.az = (float *)az;
         a.dudt = (float *)dudt; a.vsig = (float *)vsig;
         a.m0 = p.m0; a.alpha = p.av_alpha; a.beta = p.av_beta;
@@ -333,17 +353,12 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
                            c->stream, a);
         prof_end(c, tok);
     } else {
-        double4 *vh = wsa<double4>(c, "vh64", (size_t)n),
-                *th = wsa<double4>(c, "th64", (size_t)n);
-        hipLaunchKernelGGL(k_eos<double>, dim3(g), dim3(256), 0, c->stream, n, p.eos, p.cs0,
-                           p.q_cs, p.r_ref, p.gamma, s->x, s->y, s->vx, s->vy, s->vz, s->u, s->h,
-                           (const double *)rho, (const double *)omega, vh, th);
         int tok = prof_begin(c, APR_PROF_FORCES);
         ForceArgs<double> a;
         a.tree = tr;
         a.pm = wsa<double4>(c, "pm64", (size_t)n);
-        a.vh = vh;
-        a.th = th;
+        a.vh = wsa<double4>(c, "vh64", (size_t)n);
+        a.th = wsa<double4>(c, "th64", (size_t)n);
         a.ax = (double *)ax; a.ay = (double *)ay; a.az = (double *)az;
         a.dudt = (double *)dudt; a.vsig = (double *)vsig;
         a.m0 = p.m0; a.alpha = p.av_alpha; a.beta = p.av_beta;
