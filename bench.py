@@ -15,7 +15,15 @@ split/merge pass.  Interactions per step = sum_a |{b != a: r < 2 h_a}|
 library's exact neighbour export before and after the timed steps (mean).
 value = interactions per step * steps / wall time of the timed steps.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+The same run times the rest of the path on the other workloads ("legs"): the
+refined box (one split pass over 262144 particles, then density + forces +
+adjoint on the 362k-particle result, both forms), the 1M-particle planet disc
+stepped with its refinement zone (every step: cells, density, split/merge,
+forces, sink gravity, leapfrog) and the 8M-particle circumbinary disc (FP32
+density + forces + adjoint).
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-legs]
+       [--no-cpu-baseline] [--fp32-only]
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -47,18 +55,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_ctx(A, p, precision):
+def make_ctx(A, p, precision, seed=7):
+    """A context for a workload's parameter dict p in the given form."""
     return A.Context(A.make_params(
         precision=A.APR_FP32 if precision == "fp32" else A.APR_FP64, eos=int(p["eos"]),
         periodic=int(p["periodic"]), box_lo=p["lo"], box_hi=p["hi"], m0=p["m0"],
-        hfact=p["hfact"], gamma=p["gamma"], cs0=p["cs0"], av_alpha=p["alpha"],
-        av_beta=p["beta"], tol_h=1e-6 if precision == "fp32" else 1e-12, max_iter=60))
+        hfact=p["hfact"], gamma=p["gamma"], cs0=p["cs0"], q_cs=p.get("q_cs", 0.25),
+        r_ref=p.get("r_ref", 1.0), av_alpha=p["alpha"], av_beta=p["beta"],
+        tol_h=1e-6 if precision == "fp32" else 1e-12, max_iter=60,
+        r_sep_factor=p.get("r_sep_factor", 0.2), nn_cap=p.get("nn_cap", 0.0),
+        split_mode=int(p.get("split_mode", 0)), seed=seed, G=p.get("G", 1.0)))
 
 
 def count_interactions(A, ctx, ds):
-    offs0, _ = A.apr_neighbours(ctx, ds, ds["h"].contiguous(), 0)
-    offs1, _ = A.apr_neighbours(ctx, ds, ds["h"].contiguous(), 1)
-    return int(offs0[-1].item()), int(offs1[-1].item())
+    h = ds["h"].contiguous()
+    return (A.apr_neighbours(ctx, ds, h, 0, count_only=True),
+            A.apr_neighbours(ctx, ds, h, 1, count_only=True))
 
 
 def run_form(A, torch, st, p, precision, steps, warmup):
@@ -147,6 +159,123 @@ def cpu_baseline(st, p, seconds_hint=15.0):
                 seconds=t1 - t0)
 
 
+def _cot(torch, n, dt, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return [torch.randn(n, dtype=dt, device="cuda", generator=g) for _ in range(5)]
+
+
+def forward_adjoint(A, torch, ctx, ds, reps):
+    """Density + forces + adjoint (apr_vjp with seeded N(0,1) cotangents on rho,
+    a and du/dt) on the state's current cells, reps times; kernel times from
+    the library's stream events."""
+    n = ds.n
+    dt = ctx.dtype
+    rho = torch.empty(n, dtype=dt, device="cuda")
+    om = torch.empty_like(rho)
+    acc = [torch.empty_like(rho) for _ in range(4)]
+    rb, ab0, ab1, ab2, ub = _cot(torch, n, dt, 17)
+    A.apr_build_cells(ctx, ds)
+    A.apr_density(ctx, ds, rho, om)
+    A.apr_forces(ctx, ds, rho, om, *acc)
+    A.apr_vjp(ctx, ds, rho, om, rb, None, ab0, ab1, ab2, ub)
+    A.apr_sync_status(ctx)
+    A.apr_profile_enable(ctx, True)
+    A.apr_profile_read(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A.apr_density(ctx, ds, rho, om)
+        A.apr_forces(ctx, ds, rho, om, *acc)
+        A.apr_vjp(ctx, ds, rho, om, rb, None, ab0, ab1, ab2, ub)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = A.apr_profile_read(ctx, reset=True)
+    A.apr_profile_enable(ctx, False)
+    fails = A.apr_sync_status(ctx)
+    d, f = count_interactions(A, ctx, ds)
+    ms = {k: prof[i][0] / max(prof[i][1], 1) for k, i in
+          (("density_ms", A.APR_PROF_DENSITY), ("forces_ms", A.APR_PROF_FORCES),
+           ("vjp_ms", A.APR_PROF_VJP))}
+    inter = d + f
+    out = dict(n=n, interactions=inter, failures=fails, reps=reps,
+               wall_ms_per_rep=1e3 * wall / reps, **ms)
+    out["forward_rate"] = inter / (1e-3 * (ms["density_ms"] + ms["forces_ms"]))
+    out["adjoint_rate"] = inter / (1e-3 * ms["vjp_ms"])
+    out["forward_adjoint_rate"] = inter * reps / wall
+    return out
+
+
+def leg_refine_box(A, torch, W, reps):
+    """The refined box: one split pass over 262144 particles (about 1e5 split),
+    then forward + adjoint on the 362k-particle result in both forms."""
+    st, p = W.refine_box()
+    n = st["x"].shape[0]
+    times = []
+    for k in range(reps + 1):
+        ctx = make_ctx(A, p, "fp64")
+        ds = A.DeviceState.from_numpy(st, capacity=2 * n + 8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ns, nm, nsp = A.apr_split_merge(ctx, ds, p["zones"], 3, 1)
+        torch.cuda.synchronize()
+        if k > 0:
+            times.append(time.perf_counter() - t0)
+        ctx.close()
+    times.sort()
+    out = dict(workload="refined box: 64^3 periodic shock box, split sphere r = 0.45 at the "
+                        "centre (level 4), tangential split, r_sep = 0.2 h",
+               n_before=n, n_split=ns, split_pass_ms=1e3 * times[len(times) // 2],
+               split_particles_per_s=n / times[len(times) // 2])
+    for prec in ("fp32", "fp64"):
+        ctx = make_ctx(A, p, prec)
+        out[prec] = forward_adjoint(A, torch, ctx, ds.clone(), reps)
+        ctx.close()
+    return out
+
+
+def leg_circumbinary(A, torch, W, reps):
+    """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint."""
+    st, p = W.circumbinary_disc()
+    ctx = make_ctx(A, p, "fp32")
+    ds = A.DeviceState.from_numpy(st)
+    del st
+    out = dict(workload="circumbinary disc, 8.0M particles (levels 0, 1, 2), locally "
+                        "isothermal", fp32=forward_adjoint(A, torch, ctx, ds, reps))
+    ctx.close()
+    return out
+
+
+def leg_planet_disc(A, torch, W, steps):
+    """The 1M-particle planet disc stepped with its refinement zone: every step
+    runs kick, drift, cells, density, split/merge, cells and density again,
+    forces, sink gravity, kick."""
+    st, p = W.planet_disc()
+    ctx = make_ctx(A, p, "fp32", seed=3)
+    ds = A.DeviceState.from_numpy(st, capacity=st["x"].shape[0] * 5 // 4)
+    A.apr_accel(ctx, ds, p["sinks"])
+    dt = 2e-3
+    A.apr_step(ctx, ds, p["zones"], p["sinks"], dt, 0)
+    A.apr_sync_status(ctx)
+    n0 = ds.n
+    d0, f0 = count_interactions(A, ctx, ds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        A.apr_step(ctx, ds, p["zones"], p["sinks"], dt, 1 + k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fails = A.apr_sync_status(ctx)
+    d1, f1 = count_interactions(A, ctx, ds)
+    inter = 0.5 * (d0 + d1 + f0 + f1)
+    ctx.close()
+    return dict(workload="planet disc, 1M particles, refinement sphere r = 1 at (5, 0, 0), "
+                         "random split r_sep = 0.5 h, sink at the origin, dt = 2e-3",
+                form="fp32", steps=steps, n_first=n0, n_last=ds.n, failures=fails,
+                ms_per_step=1e3 * wall / steps, interactions_per_step=inter,
+                value=inter * steps / wall)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the disc and refined-box legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -183,6 +314,21 @@ def main():
     roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=achieved / PEAK_FP32_TFLOPS, traffic=None, kernel=kern,
                 flop_per_launch=flops, ms_per_launch=ms)
+    legs = None
+    if not args.no_legs:
+        legs = {}
+        legs["refine_box_split_adjoint"] = leg_refine_box(A, torch, W, 5)
+        log("refined box: split %.2f ms, fp32 adjoint %.3e interactions/s"
+            % (legs["refine_box_split_adjoint"]["split_pass_ms"],
+               legs["refine_box_split_adjoint"]["fp32"]["adjoint_rate"]))
+        legs["planet_disc_steps"] = leg_planet_disc(A, torch, W, 10)
+        log("planet disc: %.3e interactions/s, %.2f ms/step"
+            % (legs["planet_disc_steps"]["value"], legs["planet_disc_steps"]["ms_per_step"]))
+        torch.cuda.empty_cache()
+        legs["circumbinary_forward_adjoint"] = leg_circumbinary(A, torch, W, 3)
+        log("circumbinary: fp32 forward+adjoint %.3e interactions/s"
+            % legs["circumbinary_forward_adjoint"]["fp32"]["forward_adjoint_rate"])
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(st, p)
@@ -207,6 +353,7 @@ def main():
                                 "interactions_per_step", "density_force_rate", "failures",
                                 "counters")},
     }
+    out["legs"] = legs
     if r64 is not None:
         out["fp64_form"]["newton_tol"] = 1e-12
         out["fp32_over_fp64"] = r32["value"] / r64["value"]

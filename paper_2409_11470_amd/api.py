@@ -9,7 +9,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._abi import AprError, CState, Params, Sink, Zone, apr_default_params, lib
+from ._abi import (APR_PROF_N, AprError, CState, Params, Sink, Zone, apr_default_params,
+                   lib)
 
 _DFIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")
 
@@ -211,9 +212,10 @@ def apr_vjp(ctx, st, rho, omega, rho_bar=None, h_bar=None, ax_bar=None, ay_bar=N
     return tuple(out)
 
 
-def apr_neighbours(ctx, st, h, mode=0):
+def apr_neighbours(ctx, st, h, mode=0, count_only=False):
     """Neighbour slots per particle for the given h (device float64 [n]).
-    Returns (offsets [n+1], list) as device int64 tensors."""
+    Returns (offsets [n+1], list) as device int64 tensors, or only the total
+    number of pairs if count_only."""
     n = st.n
     dev = h.device
     counts = torch.zeros(n, dtype=torch.int64, device=dev)
@@ -222,6 +224,8 @@ def apr_neighbours(ctx, st, h, mode=0):
     cs = st.cstate()
     ctx.check(lib().apr_neighbours(ctx.ptr, C.byref(cs), _ptr(h), mode, _ptr(counts),
                                    _ptr(offs), None, 0, C.byref(total)))
+    if count_only:
+        return int(total.value)
     lst = torch.zeros(max(1, total.value), dtype=torch.int64, device=dev)
     ctx.check(lib().apr_neighbours(ctx.ptr, C.byref(cs), _ptr(h), mode, _ptr(counts),
                                    _ptr(offs), _ptr(lst), lst.numel(), C.byref(total)))
@@ -288,10 +292,10 @@ def apr_profile_enable(ctx, on=True):
 
 def apr_profile_read(ctx, reset=True):
     """{index: (total ms, launches)} for the timed kernels; synchronises."""
-    ms = (C.c_double * 4)()
-    cnt = (C.c_int64 * 4)()
+    ms = (C.c_double * APR_PROF_N)()
+    cnt = (C.c_int64 * APR_PROF_N)()
     ctx.check(lib().apr_profile_read(ctx.ptr, ms, cnt, int(bool(reset))))
-    return {k: (ms[k], cnt[k]) for k in range(4)}
+    return {k: (ms[k], cnt[k]) for k in range(APR_PROF_N)}
 
 
 COUNTER_NAMES = ("noconverge", "overflow", "density_multiwindow_cells",

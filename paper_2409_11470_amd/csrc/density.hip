@@ -153,6 +153,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
     __shared__ uint16_t sub[kWaves][STAGE];
     __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
+    __shared__ int s_more;
+    __shared__ Walk s_walk;
 
     const Tree &tr = a.tree;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -185,115 +187,129 @@ __global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
 
     // Every new search follows a Newton step that grew some h, and every
     // pass is a Newton step for each pending target: max_iter bounds both.
+    // A cell whose candidates span several chunks of the tree walk walks
+    // again in every pass (multi); otherwise the candidates of the last walk
+    // stay, and with a single window the staged set and the lists too.
     bool search = true;
-    bool lists = false;    // per-target lists valid (single window only)
+    bool multi = false;
+    bool lists = false;    // per-target lists valid (single chunk and window only)
     int nc = 0, total = 0, nwin = 1;
     for (int pass = 0; pass <= a.max_iter; ++pass) {
-        if (search) {
-            // ---- candidate cells, their staged counts and offsets
-            __syncthreads();
-            if (w == 0) {
-                int o = 0;
-                int ncl = traverse(tr, tg, R, false, sA, sB, &o);
-                if (lane == 0) {
-                    s_ncand = ncl;
-                    if (o) atomicOr(&a.status[ST_OVERFLOW], 1);
-                }
-            }
-            __syncthreads();
-            nc = s_ncand;
-            const T R2c = (T)(R * R);
-            const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
-            for (int ci = w; ci < nc; ci += kWaves) {
-                int cc = sA[ci];
-                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                double sh[3];
-                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-                bool hit = false;
-                if (lane < bn) {
-                    V p = a.pm[b0 + lane];
-                    hit = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0),
-                                       T(0), ex, ey, ez) < R2c;
-                }
-                uint64_t m = __ballot(hit);
-                if (lane == 0) sB[ci] = __popcll(m);
-            }
-            __syncthreads();
-            if (w == 0) {
-                int tot = wave_excl_scan_lds(sB, nc);
-                if (lane == 0) {
-                    s_total = tot;
-                    if (tot > STAGE) atomicAdd(&a.status[ST_DENS_DIRECT], 1);
-                    if (pass > 0) atomicAdd(&a.status[ST_RESTAGE], 1);
-                }
-            }
-            __syncthreads();
-            total = s_total;
-            nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
-            lists = false;
-            search = false;
-            if (nwin == 1) {
-                stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, R2c, 0, stg);
-                __syncthreads();
-            }
-        }
-        // ---- one Newton evaluation of every pending target, window by window
         DSum<T> S;
         S.zero();
         const bool wave_busy = __any(!done);
-        for (int win = 0; win < nwin; ++win) {
-            int w0 = win * STAGE;
-            int nstg = min(STAGE, total - w0);
-            if (nwin > 1) {
-                __syncthreads();  // the previous window is no longer read
-                stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, (T)(R * R), w0, stg);
+        const bool walking = search || multi;
+        if (walking) {
+            __syncthreads();
+            if (w == 0) walk_init(tr, tg, R, false, &s_walk);
+            if (search && pass > 0 && threadIdx.x == 0) atomicAdd(&a.status[ST_RESTAGE], 1);
+        }
+        for (int chunk = 0;; ++chunk) {
+            bool last = true;
+            if (walking) {
+                // ---- next chunk of candidate cells, staged counts and offsets
                 __syncthreads();
-            }
-            if (!wave_busy) continue;
-            if (!lists) {
-                // this target's candidates within 2 sigma h (with margin)
-                Rt = done ? 0.0 : 2.0 * (double)kSigma * h;
-                const T Rtl = (T)Rt;
-                build_lists16<T>(
-                    nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
-                    [&](int k) {
-                        V q;
-                        int tt = 16 * w + k;
-                        if (tt < cnt) q = a.pm[s0 + tt];
-                        else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
-                        return q;
-                    },
-                    [&](int k) { return __shfl(Rtl, 4 * k, kWave); },
-                    [&](T d2, T Rs2, int) { return d2 < Rs2; },
-                    [&](const V &q, T rk, int e) {
-                        V p = stg[e];
-                        T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                        return dx * dx + dy * dy + dz * dz < rk * rk;
-                    });
-                tlen = s_tlen[t < kCell ? t : 0];
-            }
-            if (done) continue;
-            T hf = (T)h;
-            T hinv = T(1) / hf;
-            T R2 = T(4) * hf * hf;
-            if (tlen <= kDTCap) {
-                for (int k = j; k < tlen; k += kLanes) {
-                    V p = stg[mylist[k]];
-                    S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                if (w == 0) {
+                    int ncl = walk_next(tr, tg, R, false, &s_walk, sA, kCandCap);
+                    if (lane == 0) {
+                        s_ncand = ncl;
+                        s_more = walk_done(tr, &s_walk) ? 0 : 1;
+                    }
                 }
-            } else {
-                // own list overflowed: walk the whole window
-                for (int k = j; k < nstg; k += kLanes) {
-                    V p = stg[k];
-                    S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                __syncthreads();
+                nc = s_ncand;
+                last = s_more == 0;
+                if (!last) multi = true;
+                const T R2c = (T)(R * R);
+                const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
+                for (int ci = w; ci < nc; ci += kWaves) {
+                    int cc = sA[ci];
+                    int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+                    double sh[3];
+                    cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                    bool hit = false;
+                    if (lane < bn) {
+                        V p = a.pm[b0 + lane];
+                        hit = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0),
+                                           T(0), T(0), ex, ey, ez) < R2c;
+                    }
+                    uint64_t m = __ballot(hit);
+                    if (lane == 0) sB[ci] = __popcll(m);
+                }
+                __syncthreads();
+                if (w == 0) {
+                    int tot = wave_excl_scan_lds(sB, nc);
+                    if (lane == 0) {
+                        s_total = tot;
+                        if (pass == 0 && chunk == 0 && (tot > STAGE || !last))
+                            atomicAdd(&a.status[ST_DENS_DIRECT], 1);
+                    }
+                }
+                __syncthreads();
+                total = s_total;
+                nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
+                lists = false;
+                if (nwin == 1) {
+                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, R2c, 0, stg);
+                    __syncthreads();
                 }
             }
+            // ---- this chunk's part of one Newton evaluation, window by window
+            for (int win = 0; win < nwin && total > 0; ++win) {
+                int w0 = win * STAGE;
+                int nstg = min(STAGE, total - w0);
+                if (nwin > 1) {
+                    __syncthreads();  // the previous window is no longer read
+                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, (T)(R * R), w0,
+                                           stg);
+                    __syncthreads();
+                }
+                if (!wave_busy) continue;
+                if (!lists) {
+                    // this target's candidates within 2 sigma h (with margin)
+                    Rt = done ? 0.0 : 2.0 * (double)kSigma * h;
+                    const T Rtl = (T)Rt;
+                    build_lists16<T>(
+                        nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
+                        [&](int k) {
+                            V q;
+                            int tt = 16 * w + k;
+                            if (tt < cnt) q = a.pm[s0 + tt];
+                            else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
+                            return q;
+                        },
+                        [&](int k) { return __shfl(Rtl, 4 * k, kWave); },
+                        [&](T d2, T Rs2, int) { return d2 < Rs2; },
+                        [&](const V &q, T rk, int e) {
+                            V p = stg[e];
+                            T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                            return dx * dx + dy * dy + dz * dz < rk * rk;
+                        });
+                    tlen = s_tlen[t < kCell ? t : 0];
+                }
+                if (done) continue;
+                T hf = (T)h;
+                T hinv = T(1) / hf;
+                T R2 = T(4) * hf * hf;
+                if (tlen <= kDTCap) {
+                    for (int k = j; k < tlen; k += kLanes) {
+                        V p = stg[mylist[k]];
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                    }
+                } else {
+                    // own list overflowed: walk the whole window
+                    for (int k = j; k < nstg; k += kLanes) {
+                        V p = stg[k];
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                    }
+                }
+            }
+            if (threadIdx.x == 0) atomicAdd(&a.status[ST_WINDOWS], nwin);
+            if (last) break;
         }
-        lists = nwin == 1;
-        if (threadIdx.x == 0) {
-            atomicAdd(&a.status[ST_PASSES], 1);
-            atomicAdd(&a.status[ST_WINDOWS], nwin);
-        }
+        search = false;
+        lists = !multi && nwin == 1;
+        if (threadIdx.x == 0) atomicAdd(&a.status[ST_PASSES], 1);
         // ---- FP64 Newton step of this lane's target (its 4 lanes agree)
         double needR = 0.0;
         bool pending = false;

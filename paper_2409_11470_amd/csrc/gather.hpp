@@ -1,8 +1,9 @@
 // Generic gather over the symmetric pair relation r_ab < 2 max(h_a, h_b),
 // b != a, r_ab > 0: one workgroup of 4 wavefronts per target cell, candidate
-// cells from the tree, LDS staging window by window, per-target lists built
-// with 16 lanes per target, pair loops with 4 lanes per target.  No atomics
-// on the sums: each target accumulates its own terms in a fixed order.
+// cells from the tree walk chunk by chunk, LDS staging window by window,
+// per-target lists built with 16 lanes per target, pair loops with 4 lanes
+// per target.  No atomics on the sums: each target accumulates its own terms
+// in a fixed order.
 //
 // OP supplies (T the pair precision, V = vec4_t<T>):
 //   static constexpr int NS;            staged vec4 arrays per particle:
@@ -31,7 +32,8 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
     __shared__ V stg[NS][STAGE];
     __shared__ uint16_t sub[kWaves][STAGE];
     __shared__ uint16_t tls[kCell][kTCap];
-    __shared__ int s_ncand, s_total, s_tlen[kCell];
+    __shared__ int s_ncand, s_total, s_more, s_tlen[kCell];
+    __shared__ Walk s_walk;
 
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
     if (cell >= tr.hdr->ncells) return;
@@ -46,45 +48,6 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
     const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
     const T R2c = (T)(R * R);
 
-    if (w == 0) {
-        int o = 0;
-        int ncl = traverse(tr, tg, R, true, sA, sB, &o);
-        if (lane == 0) {
-            s_ncand = ncl;
-            if (o) atomicOr(&status[ST_OVERFLOW], 1);
-        }
-    }
-    __syncthreads();
-    const int nc = s_ncand;
-    // count the candidates b within max(R, 2 h_b) of the target cell box
-    for (int ci = w; ci < nc; ci += kWaves) {
-        int cc = sA[ci];
-        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-        double sh[3];
-        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-        bool hit = false;
-        if (lane < bn) {
-            V p = op.load(0, b0 + lane);
-            T hb = op.load(1, b0 + lane).w;
-            T d2 = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0), T(0),
-                                ex, ey, ez);
-            hit = d2 < R2c || d2 * hb * hb < T(4);
-        }
-        uint64_t m = __ballot(hit);
-        if (lane == 0) sB[ci] = __popcll(m);
-    }
-    __syncthreads();
-    if (w == 0) {
-        int tot = wave_excl_scan_lds(sB, nc);
-        if (lane == 0) {
-            s_total = tot;
-            if (tot > STAGE && st_word >= 0) atomicAdd(&status[st_word], 1);
-        }
-    }
-    __syncthreads();
-    const int total = s_total;
-    const int nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
-
     V own[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -96,76 +59,122 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
     const bool wave_busy = __any(valid);
     const T ra = valid ? T(2) / own[1].w : T(0);
 
-    for (int win = 0; win < nwin; ++win) {
-        const int w0 = win * STAGE;
-        const int nstg = min(STAGE, total - w0);
-        if (win > 0) __syncthreads();  // the previous window is no longer read
+    if (w == 0) walk_init(tr, tg, R, true, &s_walk);
+    for (int chunk = 0;; ++chunk) {
+        // ---- next chunk of candidate cells
+        __syncthreads();  // the previous chunk is no longer read
+        if (w == 0) {
+            int ncl = walk_next(tr, tg, R, true, &s_walk, sA, kCandCap);
+            if (lane == 0) {
+                s_ncand = ncl;
+                s_more = walk_done(tr, &s_walk) ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        const int nc = s_ncand;
+        const bool more = s_more != 0;
+        // count the candidates b within max(R, 2 h_b) of the target cell box
         for (int ci = w; ci < nc; ci += kWaves) {
-            int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
-            if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
             int cc = sA[ci];
             int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
             double sh[3];
             cell_shift(tr.lev[0][cc], tg, tr.box, sh);
             bool hit = false;
-            V p, v;
             if (lane < bn) {
-                p = op.load(0, b0 + lane);
-                v = op.load(1, b0 + lane);
-                p.x = p.x + (T)sh[0];
-                p.y = p.y + (T)sh[1];
-                p.z = p.z + (T)sh[2];
-                T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
-                hit = d2 < R2c || d2 * v.w * v.w < T(4);
+                V p = op.load(0, b0 + lane);
+                T hb = op.load(1, b0 + lane).w;
+                T d2 = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0),
+                                    T(0), ex, ey, ez);
+                hit = d2 < R2c || d2 * hb * hb < T(4);
             }
             uint64_t m = __ballot(hit);
-            int off = o0 + __popcll(m & lanemask_lt()) - w0;
-            if (hit && off >= 0 && off < STAGE) {
-                stg[0][off] = p;
-                stg[1][off] = v;
-#pragma unroll
-                for (int k = 2; k < NS; ++k) stg[k][off] = op.load(k, b0 + lane);
+            if (lane == 0) sB[ci] = __popcll(m);
+        }
+        __syncthreads();
+        if (w == 0) {
+            int tot = wave_excl_scan_lds(sB, nc);
+            if (lane == 0) {
+                s_total = tot;
+                if ((tot > STAGE || more || chunk > 0) && st_word >= 0 && chunk == 0)
+                    atomicAdd(&status[st_word], 1);
             }
         }
         __syncthreads();
-        if (!wave_busy) continue;
-        build_lists16<T>(
-            nstg, stg[0], sub[w], &tls[0][0], kTCap, s_tlen,
-            [&](int k) {
-                V q;
-                int tt = 16 * w + k;
-                if (tt < cnt) q = op.load(0, s0 + tt);
-                else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
-                return q;
-            },
-            [&](int k) { return __shfl(ra, 4 * k, kWave); },
-            [&](T d2, T Rs2, int e) {
-                T hb = stg[1][e].w;
-                return d2 < Rs2 || d2 * hb * hb < T(4);
-            },
-            [&](const V &q, T rk, int e) {
-                V p = stg[0][e];
-                T hb = stg[1][e].w;
-                T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-                T r2 = dx * dx + dy * dy + dz * dz;
-                return r2 < rk * rk || r2 * hb * hb < T(4);
-            });
-        const int tlen = s_tlen[t < kCell ? t : 0];
-        if (!valid) continue;
-        const T ha_inv2 = own[1].w * own[1].w;
-        const bool ownlist = tlen <= kTCap;
-        const int len = ownlist ? tlen : nstg;
-        for (int k = j; k < len; k += kLanes) {
-            int e = ownlist ? mylist[k] : k;
-            V nb[NS];
+        const int total = s_total;
+        const int nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
+
+        for (int win = 0; win < nwin && total > 0; ++win) {
+            const int w0 = win * STAGE;
+            const int nstg = min(STAGE, total - w0);
+            if (win > 0) __syncthreads();  // the previous window is no longer read
+            for (int ci = w; ci < nc; ci += kWaves) {
+                int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
+                if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
+                int cc = sA[ci];
+                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
+                double sh[3];
+                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                bool hit = false;
+                V p, v;
+                if (lane < bn) {
+                    p = op.load(0, b0 + lane);
+                    v = op.load(1, b0 + lane);
+                    p.x = p.x + (T)sh[0];
+                    p.y = p.y + (T)sh[1];
+                    p.z = p.z + (T)sh[2];
+                    T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
+                    hit = d2 < R2c || d2 * v.w * v.w < T(4);
+                }
+                uint64_t m = __ballot(hit);
+                int off = o0 + __popcll(m & lanemask_lt()) - w0;
+                if (hit && off >= 0 && off < STAGE) {
+                    stg[0][off] = p;
+                    stg[1][off] = v;
 #pragma unroll
-            for (int a = 0; a < NS; ++a) nb[a] = stg[a][e];
-            T dx = own[0].x - nb[0].x, dy = own[0].y - nb[0].y, dz = own[0].z - nb[0].z;
-            T r2 = dx * dx + dy * dy + dz * dz;
-            T hb = nb[1].w;
-            if ((r2 * ha_inv2 < T(4) || r2 * hb * hb < T(4)) && r2 > T(0))
-                op.pair(acc, own, dx, dy, dz, r2, nb);
+                    for (int k = 2; k < NS; ++k) stg[k][off] = op.load(k, b0 + lane);
+                }
+            }
+            __syncthreads();
+            if (!wave_busy) continue;
+            build_lists16<T>(
+                nstg, stg[0], sub[w], &tls[0][0], kTCap, s_tlen,
+                [&](int k) {
+                    V q;
+                    int tt = 16 * w + k;
+                    if (tt < cnt) q = op.load(0, s0 + tt);
+                    else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
+                    return q;
+                },
+                [&](int k) { return __shfl(ra, 4 * k, kWave); },
+                [&](T d2, T Rs2, int e) {
+                    T hb = stg[1][e].w;
+                    return d2 < Rs2 || d2 * hb * hb < T(4);
+                },
+                [&](const V &q, T rk, int e) {
+                    V p = stg[0][e];
+                    T hb = stg[1][e].w;
+                    T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                    T r2 = dx * dx + dy * dy + dz * dz;
+                    return r2 < rk * rk || r2 * hb * hb < T(4);
+                });
+            const int tlen = s_tlen[t < kCell ? t : 0];
+            if (!valid) continue;
+            const T ha_inv2 = own[1].w * own[1].w;
+            const bool ownlist = tlen <= kTCap;
+            const int len = ownlist ? tlen : nstg;
+            for (int k = j; k < len; k += kLanes) {
+                int e = ownlist ? mylist[k] : k;
+                V nb[NS];
+#pragma unroll
+                for (int a = 0; a < NS; ++a) nb[a] = stg[a][e];
+                T dx = own[0].x - nb[0].x, dy = own[0].y - nb[0].y, dz = own[0].z - nb[0].z;
+                T r2 = dx * dx + dy * dy + dz * dz;
+                T hb = nb[1].w;
+                if ((r2 * ha_inv2 < T(4) || r2 * hb * hb < T(4)) && r2 > T(0))
+                    op.pair(acc, own, dx, dy, dz, r2, nb);
+            }
         }
+        if (!more) break;
     }
     op.finish(acc, s0 + t, own, valid && j == 0);
 }

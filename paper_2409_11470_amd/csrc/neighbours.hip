@@ -41,9 +41,10 @@ __device__ inline bool is_neighbour(double xa, double ya, double za, double ha, 
 __global__ __launch_bounds__(64) void k_neigh(Tree tr, const double *x, const double *y,
                                               const double *z, const double *h, int mode,
                                               int64_t *counts, const int64_t *offsets,
-                                              int64_t *list, int64_t cap, int32_t *status)
+                                              int64_t *list, int64_t cap)
 {
-    __shared__ int32_t sA[kCandCap], sB[kCandCap];
+    __shared__ int32_t sA[kCandCap];
+    __shared__ Walk s_walk;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
     if (cell >= tr.hdr->ncells) return;
     const Geo tg = tr.lev[0][cell];
@@ -51,25 +52,29 @@ __global__ __launch_bounds__(64) void k_neigh(Tree tr, const double *x, const do
     int32_t s0 = tr.cs[cell], s1 = tr.cs[cell + 1];
     int64_t a = s0 + lane;
     bool valid = a < s1;
-    int ovf = 0;
-    int nc = traverse(tr, tg, 2.0 * (double)tg.hmax, mode == 1, sA, sB, &ovf);
     double xa = valid ? x[a] : 0.0, ya = valid ? y[a] : 0.0, za = valid ? z[a] : 0.0;
     double ha = valid ? h[a] : 0.0;
     int64_t k = 0;
     int64_t off = (list && valid) ? offsets[a] : 0;
-    for (int ci = 0; ci < nc; ++ci) {
-        int cc = sA[ci];
-        int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
-        for (int32_t b = b0; b < b1; ++b) {
-            double xb = x[b], yb = y[b], zb = z[b], hb = h[b];
-            if (valid && b != a && is_neighbour(xa, ya, za, ha, xb, yb, zb, hb, tr.box, mode)) {
-                if (list && off + k < cap) list[off + k] = b;
-                k += 1;
+    const double R = 2.0 * (double)tg.hmax;
+    walk_init(tr, tg, R, mode == 1, &s_walk);
+    for (;;) {
+        int nc = walk_next(tr, tg, R, mode == 1, &s_walk, sA, kCandCap);
+        for (int ci = 0; ci < nc; ++ci) {
+            int cc = sA[ci];
+            int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
+            for (int32_t b = b0; b < b1; ++b) {
+                double xb = x[b], yb = y[b], zb = z[b], hb = h[b];
+                if (valid && b != a && is_neighbour(xa, ya, za, ha, xb, yb, zb, hb, tr.box, mode)) {
+                    if (list && off + k < cap) list[off + k] = b;
+                    k += 1;
+                }
             }
         }
+        wave_sync();  // sA is read before the next chunk is written
+        if (walk_done(tr, &s_walk)) break;
     }
     if (valid && !list) counts[a] = k;
-    if (ovf && lane == 0) atomicOr(&status[ST_OVERFLOW], 1);
 }
 
 }  // namespace
@@ -87,7 +92,7 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
     unsigned nb = (unsigned)c->cells_bound;
     if (!list) {
         hipLaunchKernelGGL(k_neigh, dim3(nb), dim3(64), 0, c->stream, tr, s->x, s->y, s->z, h,
-                           mode, counts, offsets, (int64_t *)nullptr, (int64_t)0, c->d_status);
+                           mode, counts, offsets, (int64_t *)nullptr, (int64_t)0);
         APR_LAUNCHED(c);
         int64_t *tot = wsa<int64_t>(c, "neigh_total", 1);
         rc = exclusive_scan_i64(c, counts, offsets, n, tot);
@@ -101,7 +106,7 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
         return APR_OK;
     }
     hipLaunchKernelGGL(k_neigh, dim3(nb), dim3(64), 0, c->stream, tr, s->x, s->y, s->z, h, mode,
-                       counts, offsets, list, cap, c->d_status);
+                       counts, offsets, list, cap);
     APR_LAUNCHED(c);
     return APR_OK;
 }

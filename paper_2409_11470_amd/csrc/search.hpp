@@ -2,9 +2,11 @@
 // adjoint kernels.
 //
 // Work unit: one workgroup of 4 wavefronts per target cell (<= 64 particles).
-//  1. traverse: wavefront 0 walks the 64-ary cell tree breadth-first; at each
-//     level one wavefront instruction tests the 64 children of a frontier
-//     node, and ballot + popcount append the hits in order (deterministic).
+//  1. walk: wavefront 0 walks the 64-ary cell tree depth-first; one wavefront
+//     instruction tests the 64 children of a node, and ballot + popcount
+//     append the hit cells in order (deterministic).  The walk pauses when the
+//     candidate buffer is full, the candidates so far are processed, and it
+//     resumes: the number of candidate cells is unbounded.
 //  2. stage: the candidate cells' particles that can interact with the target
 //     cell are copied to LDS, with positions moved into the target cell's
 //     frame (FP64 cell-centre difference, minimum image, rounded once to the
@@ -27,7 +29,7 @@ namespace apr {
 
 constexpr int kSearchThreads = 256;
 constexpr int kWaves = kSearchThreads / kWave;
-constexpr int kCandCap = 1024;   // candidate cells per target cell
+constexpr int kCandCap = 1024;   // candidate cells per chunk of the walk
 constexpr int kSubCap = 512;     // staged candidates per sub-block
 constexpr int kGroup = 16;       // lanes per target (sub-block layout)
 constexpr int kLanes = 4;        // lanes per target (one target per lane group of 4)
@@ -72,66 +74,85 @@ __device__ inline void quad_append(bool hit, uint16_t e, uint16_t *list, int cap
     len += __popc(gm);
 }
 
-// Breadth-first traversal by one wavefront.  Keeps the nodes whose box lies
+// Resumable depth-first walk of the cell tree by one wavefront, handing out
+// the candidate cells in chunks (in Morton order, the order of the cells), so
+// that no candidate capacity limits a search.  A node is kept if its box lies
 // within R of the target box (or, with sym, within max(R, 2 hmax_node)).
-// Returns the number of candidate cells written to A (<= kCandCap; sets
-// *overflow if more were found).
-__device__ inline int traverse(const Tree &t, const Geo &tg, double R, bool sym, int32_t *A,
-                               int32_t *B, int *overflow)
+// State per level: the hit mask of the 64 children of the node being
+// expanded there and the id of child 0.  Lives in LDS; wavefront-uniform.
+struct Walk {
+    uint64_t mask[kMaxLev + 1];
+    int32_t base[kMaxLev + 1];
+    int depth;  // level of the deepest pending mask; > nlev when finished
+};
+
+__device__ inline bool node_hit(const Geo &g, const Geo &tg, const Box &box, double R, bool sym)
+{
+    double r = sym ? fmax(R, 2.0 * (double)g.hmax) : R;
+    return gap2(tg, g, box) < r * r;
+}
+
+// Starts the walk: tests the top-level nodes (<= 64).
+__device__ inline void walk_init(const Tree &t, const Geo &tg, double R, bool sym, Walk *W)
+{
+    int lane = lane_id(), top = t.nlev;
+    bool hit = lane < t.hdr->nnode[top] && node_hit(t.lev[top][lane], tg, t.box, R, sym);
+    uint64_t m = __ballot(hit);
+    wave_sync();
+    if (lane == 0) {
+        W->mask[top] = m;
+        W->base[top] = 0;
+        W->depth = top;
+    }
+    wave_sync();
+}
+
+__device__ inline bool walk_done(const Tree &t, const Walk *W) { return W->depth > t.nlev; }
+
+// Appends the next candidate cells to A (room for cap >= 64), whole groups of
+// siblings at a time, and returns their number; 0 once the walk is finished.
+__device__ inline int walk_next(const Tree &t, const Geo &tg, double R, bool sym, Walk *W,
+                                int32_t *A, int cap)
 {
     int lane = lane_id();
-    int top = t.nlev;
-    int ntop = t.hdr->nnode[top];
-    double R2 = R * R;
-    int nf = 0;
-    // the top level (<= 64 nodes) is tested directly
-    {
-        bool in = lane < ntop;
-        bool hit = false;
-        if (in) {
-            Geo g = t.lev[top][lane];
-            double r = sym ? fmax(R, 2.0 * (double)g.hmax) : R;
-            hit = gap2(tg, g, t.box) < (sym ? r * r : R2);
+    int n = 0;
+    int d = W->depth;
+    while (d <= t.nlev) {
+        uint64_t m = W->mask[d];
+        if (m == 0) {
+            d += 1;
+            continue;
         }
-        uint64_t m = __ballot(hit);
-        if (hit) A[__popcll(m & lanemask_lt())] = lane;
-        nf = __popcll(m);
+        if (d == 0) {
+            int k = __popcll(m);
+            if (n + k > cap) break;  // the caller takes this chunk first
+            if ((m >> lane) & 1ull) A[n + __popcll(m & lanemask_lt())] = W->base[0] + lane;
+            n += k;
+            wave_sync();
+            if (lane == 0) W->mask[0] = 0;
+            wave_sync();
+            d = 1;
+            continue;
+        }
+        // expand the first pending node of level d
+        int slot = __ffsll((unsigned long long)m) - 1;
+        int32_t node = W->base[d] + slot;
+        int64_t ch = (int64_t)node * kFan + lane;
+        bool hit = ch < t.hdr->nnode[d - 1] && node_hit(t.lev[d - 1][ch], tg, t.box, R, sym);
+        uint64_t cm = __ballot(hit);
         wave_sync();
-    }
-    int32_t *cur = A, *nxt = B;
-    for (int lev = top; lev >= 1; --lev) {
-        int nchild = t.hdr->nnode[lev - 1];
-        const Geo *cg = t.lev[lev - 1];
-        int nn = 0;
-        for (int f = 0; f < nf; ++f) {
-            int64_t ch = (int64_t)cur[f] * kFan + lane;
-            bool hit = false;
-            if (ch < nchild) {
-                Geo g = cg[ch];
-                double r = sym ? fmax(R, 2.0 * (double)g.hmax) : R;
-                hit = gap2(tg, g, t.box) < r * r;
-            }
-            uint64_t m = __ballot(hit);
-            int pos = nn + __popcll(m & lanemask_lt());
-            if (hit && pos < kCandCap) nxt[pos] = (int32_t)ch;
-            nn += __popcll(m);
-        }
-        if (nn > kCandCap) {
-            *overflow = 1;
-            nn = kCandCap;
+        if (lane == 0) {
+            W->mask[d] = m & (m - 1);
+            W->mask[d - 1] = cm;
+            W->base[d - 1] = node * kFan;
         }
         wave_sync();
-        int32_t *tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        nf = nn;
+        d -= 1;
     }
-    // make sure the result sits in A
-    if (cur != A) {
-        for (int i = lane; i < nf; i += kWave) A[i] = cur[i];
-        wave_sync();
-    }
-    return nf;
+    wave_sync();
+    if (lane == 0) W->depth = d;
+    wave_sync();
+    return n;
 }
 
 // In-place exclusive prefix sum of cnt[0..n) by one wavefront; returns the total.

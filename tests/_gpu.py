@@ -2,6 +2,7 @@
 results back to particle ids; run the oracle on whole sets or sampled balls."""
 import numpy as np
 import torch
+from scipy.spatial import cKDTree
 
 import oracle
 import paper_2409_11470_amd as A
@@ -100,3 +101,73 @@ def sample_balls(st, p, nballs, ntarget, seed, hscale):
         tg.append(order)
         sh.append(np.nonzero(r < rb + 4.5 * hscale)[0])
     return np.unique(np.concatenate(tg)), np.unique(np.concatenate(sh))
+
+
+def oracle_balls(st, p, nballs, ntarget, seed, tol=1e-12, forces=True, safety=1.5,
+                 centres=None):
+    """The FP64 oracle, exact on sampled targets of a large set: the ntarget
+    particles nearest to each of nballs random particles (ball radius rb).
+    Every particle b gets the reach bound R_b = 2 safety h0_b (h0 the initial
+    h).  Solved set I: the b within rb + max(2 safety max h0(targets), R_b) of
+    the ball centre, which holds every neighbour of a target under the
+    symmetric criterion; sources: the union of the balls of radius R_b about
+    the b in I (selected with a k-d tree; centres, if given, replace the random
+    ball centres).  The
+    density is solved for I over the sources and the forces summed on the
+    targets over I.  Checked afterwards: every solved h <= safety h0, so each
+    bound held for the solved particles.
+    Returns (targets [global index], density dict, forces dict or None)."""
+    rng = np.random.default_rng(seed)
+    n = st["x"].shape[0]
+    pos = np.stack([st["x"], st["y"], st["z"]], 1)
+    reach = 2.0 * safety * st["h"]
+    lo = np.asarray(p.get("lo", (0, 0, 0)), float)
+    L = np.asarray(p.get("hi", (1, 1, 1)), float) - lo
+    per = bool(p.get("periodic", False))
+    T, I, S = [], [], []
+    if centres is None:
+        centres = rng.choice(n, nballs, replace=False)
+    for c in centres:
+        d = pos - pos[c]
+        if per:
+            d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(1))
+        order = np.argsort(r, kind="stable")[:ntarget]
+        rb = r[order[-1]]
+        inner = r - rb < np.maximum(reach[order].max(), reach)
+        rs = float(np.max(r[inner] + reach[inner]))
+        cand = np.nonzero(r < rs)[0]
+        box = L if per else None
+        tree = cKDTree(pos[cand] - lo if per else pos[cand], boxsize=box)
+        iin = np.nonzero(inner)[0]
+        hits = tree.query_ball_point(pos[iin] - lo if per else pos[iin], reach[iin])
+        T.append(order)
+        I.append(iin)
+        S.append(np.union1d(cand[np.unique(np.concatenate(hits))], iin))
+    Tg = np.unique(np.concatenate(T))
+    Sg = np.unique(np.concatenate(S))
+    Ig = np.unique(np.concatenate(I))
+    loc = np.full(n, -1, np.int64)
+    loc[Sg] = np.arange(Sg.shape[0])
+    sub = {k: st[k][Sg] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level")}
+    kw = dict(m0=p["m0"], hfact=p.get("hfact", 1.2), periodic=per, lo=tuple(lo),
+              hi=tuple(lo + L))
+    o = oracle.density(sub["x"], sub["y"], sub["z"], sub["level"], sub["h"][loc[Ig]], tol=tol,
+                       max_iter=60, targets=loc[Ig], **kw)
+    assert np.all(o["h"] <= safety * st["h"][Ig]), "a solved h exceeds its bound"
+    ti = np.searchsorted(Ig, Tg)
+    dens = {k: v[ti] for k, v in o.items() if isinstance(v, np.ndarray)}
+    dens["failures"] = o["failures"]
+    dens["sample"] = (Tg.size, Ig.size, Sg.size)
+    if not forces:
+        return Tg, dens, None
+    m = Sg.shape[0]
+    h, rho, om = np.full(m, 1e-12), np.ones(m), np.ones(m)
+    h[loc[Ig]], rho[loc[Ig]], om[loc[Ig]] = o["h"], o["rho"], o["omega"]
+    f = oracle.forces(sub["x"], sub["y"], sub["z"], sub["vx"], sub["vy"], sub["vz"], sub["u"],
+                      sub["level"], h, rho, om, eos=int(p.get("eos", 0)),
+                      cs0=p.get("cs0", 1.0), q_cs=p.get("q_cs", 0.25),
+                      r_ref=p.get("r_ref", 1.0), gamma=p.get("gamma", 5.0 / 3.0),
+                      alpha=p.get("alpha", 1.0), beta=p.get("beta", 2.0), targets=loc[Tg],
+                      **{k: v for k, v in kw.items() if k != "hfact"})
+    return Tg, dens, f

@@ -59,6 +59,25 @@ def test_struct_layout_matches_header(tmp_path):
             assert int(out["%s.%s" % (s, f)]) == getattr(cls, f).offset, (s, f)
 
 
+def test_constants_match_header(tmp_path):
+    # every APR_ constant of the binding has the header's value (array sizes
+    # such as APR_PROF_N size buffers the library writes into)
+    import paper_2409_11470_amd._abi as B
+    names = sorted(k for k in dir(B) if k.startswith("APR_") and isinstance(getattr(B, k), int))
+    src = open(HEADER).read()
+    assert all(n in src for n in names)
+    prog = tmp_path / "consts.c"
+    body = "".join('printf("%s %%ld\\n", (long)(%s));' % (n, n) for n in names)
+    prog.write_text('#include <stdio.h>\n#include "apr.h"\nint main(void){%sreturn 0;}' % body)
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for n in names:
+        assert int(out[n]) == getattr(B, n), n
+
+
 def test_default_params(L):
     import paper_2409_11470_amd as A
     p = A.apr_default_params()

@@ -1,0 +1,192 @@
+"""Parity at the full sizes of the disc and refinement workloads, in the launch
+configuration the benchmark uses: the 1M-particle planet disc, the 8M-particle
+circumbinary disc (three masses) and the refined box (262144 particles of
+which about 1e5 split).  Density and forces are compared on sampled targets
+the oracle solves exactly (ball samples with complete source sets); the split
+and merge passes are compared slot by slot; the adjoint's split-separation
+derivative against central differences of the oracle on a sampled loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2409_11470_amd as A
+import workloads as W
+from _gpu import gpu_density, gpu_forces, oracle_balls, params_for
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-5, "fp32": 1e-3}
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def _check(g, gf, tg, od, of, prec):
+    assert od["failures"] == 0 and g["failures"] == 0
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k][tg], od[k]) < TOL[prec], k
+    da = np.sqrt(sum((gf[k][tg] - of[k]) ** 2 for k in ("ax", "ay", "az")))
+    assert np.max(da / of["anorm"]) < TOL[prec]
+    assert np.max(np.abs(gf["dudt"][tg] - of["dudt"]) / np.maximum(of["unorm"], 1e-300)) \
+        < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_planet_disc_1M_sampled(prec):
+    st, p = W.planet_disc()
+    g, ctx, ds, (rho, om) = gpu_density(st, p, prec)
+    gf = gpu_forces(ctx, ds, rho, om)
+    tg, od, of = oracle_balls(st, p, 6, 48, seed=21)
+    _check(g, gf, tg, od, of, prec)
+
+
+@pytest.fixture(scope="module")
+def cb_disc():
+    return W.circumbinary_disc()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_circumbinary_8M_sampled(cb_disc, prec):
+    st, p = cb_disc
+    g, ctx, ds, (rho, om) = gpu_density(st, p, prec)
+    gf = gpu_forces(ctx, ds, rho, om)
+    del ctx, ds, rho, om
+    torch.cuda.empty_cache()
+    # two balls centred on particles of each level (0 outer disc, 1 and 2
+    # the refined rings about the binary)
+    rng = np.random.default_rng(22)
+    centres = np.concatenate([rng.choice(np.nonzero(st["level"] == l)[0], 2, replace=False)
+                              for l in (0, 1, 2)])
+    tg, od, of = oracle_balls(st, p, 6, 48, seed=22, centres=centres)
+    assert set(np.unique(st["level"][tg])) == {0, 1, 2}
+    _check(g, gf, tg, od, of, prec)
+
+
+def _orc_pass(st, p, zones, step, flags, seed=7):
+    return oracle.split_merge(st, zones, step=step, seed=seed,
+                              r_sep_factor=p.get("r_sep_factor", 0.2),
+                              nn_cap=p.get("nn_cap", 0.0), split_mode=int(p.get("split_mode", 0)),
+                              periodic=p.get("periodic", False), lo=p["lo"], hi=p["hi"],
+                              do_split=bool(flags in (0, 1)), do_merge=bool(flags in (0, 2)))
+
+
+def _gpu_pass(st, p, zones, step, flags, seed=7):
+    ctx = A.Context(params_for(p, "fp64", r_sep_factor=p.get("r_sep_factor", 0.2),
+                               nn_cap=p.get("nn_cap", 0.0),
+                               split_mode=int(p.get("split_mode", 0)), seed=seed))
+    ds = A.DeviceState.from_numpy(st, capacity=2 * st["x"].shape[0] + 8)
+    cnt = A.apr_split_merge(ctx, ds, zones, step, flags)
+    return ds.to_numpy(), cnt
+
+
+def _compare(g, o, cnt):
+    assert tuple(cnt) == (o["n_split"], o["n_merged"], o["n_spare"])
+    assert g["x"].shape[0] == o["x"].shape[0] and g["next_id"] == o["next_id"]
+    for k in ("id", "level", "h", "vx", "vy", "vz", "u"):
+        assert np.array_equal(g[k], o[k]), k
+    for k in ("x", "y", "z"):
+        scale = np.maximum(np.abs(o[k]), 1.0)
+        assert np.max(np.abs(g[k] - o[k]) / scale) < 8 * np.finfo(float).eps, k
+
+
+def test_refine_box_full_split():
+    st, p = W.refine_box()
+    g, cnt = _gpu_pass(st, p, p["zones"], 3, 1)
+    o = _orc_pass(st, p, p["zones"], 3, 1)
+    assert cnt[0] > 90000
+    _compare(g, o, cnt)
+
+
+def test_circumbinary_8M_merge(cb_disc):
+    # shrink both zones: level-2 pairs between r = 2.5 and 3, level-1 pairs
+    # between 3.5 and 4 merge; 1.4M level-2 and 0.7M level-1 candidates
+    st, p = cb_disc
+    zones = [dict(c=(0.0, 0.0, 0.0), r=(3.5, 2.5), ell=(1, 2))]
+    g, cnt = _gpu_pass(st, p, zones, 4, 2)
+    o = _orc_pass(st, p, zones, 4, 2)
+    assert cnt[1] > 100000
+    _compare(g, o, cnt)
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_refine_box_split_separation_gradient(prec):
+    """The refined box after its split pass (about 362k particles); loss over
+    64 sampled child pairs, L = sum (rho_c - rho_parent)^2, as a function of
+    the separation factor s (children at centre +- s h w).  The adjoint's dL/ds
+    (all particles in the forward) vs central differences of the oracle."""
+    st, p = W.refine_box()
+    n0 = st["x"].shape[0]
+    s1 = _orc_pass(st, p, p["zones"], 3, 1)
+    n1 = s1["x"].shape[0]
+    split = np.nonzero(s1["level"][:n0] > st["level"])[0]
+    pb_all = n0 + np.arange(n1 - n0)
+    X1 = np.stack([s1["x"], s1["y"], s1["z"]], 1)
+    dX = X1[split] - X1[pb_all]
+    dX -= np.round(dX)  # periodic unit box
+    e = dX / (2 * 0.2)
+    centre = X1[pb_all] + 0.5 * dX
+    rng = np.random.default_rng(31)
+    pick = rng.choice(split.size, 64, replace=False)
+    pa, pb = split[pick], pb_all[pick]
+    # the unsplit parents' densities (constants of the loss)
+    pd = oracle.density(st["x"], st["y"], st["z"], st["level"], st["h"][split[pick]],
+                        m0=p["m0"], tol=1e-14, max_iter=100, periodic=True, targets=split[pick])
+    rho_ref = pd["rho"]
+
+    def positions(s):
+        X = X1.copy()
+        X[split] = centre + s * e
+        X[pb_all] = centre - s * e
+        return X - np.floor(X)
+
+    # oracle: densities of the 128 sampled children over the sources near them
+    tg = np.concatenate([pa, pb])
+
+    def c_loss(s):
+        X = positions(s)
+        st2 = dict(s1, x=X[:, 0], y=X[:, 1], z=X[:, 2])
+        d = pos_density(st2, tg)
+        return float(np.sum((d[:64] - rho_ref) ** 2 + (d[64:] - rho_ref) ** 2))
+
+    def pos_density(st2, targets):
+        P = np.stack([st2["x"], st2["y"], st2["z"]], 1)
+        hm = 2.0 * float(np.max(st2["h"]))
+        src = np.zeros(P.shape[0], bool)
+        for t in targets:
+            d = P - P[t]
+            d -= np.round(d)
+            src |= (d * d).sum(1) < (2.2 * hm) ** 2
+        S = np.nonzero(src)[0]
+        loc = np.full(P.shape[0], -1)
+        loc[S] = np.arange(S.size)
+        o = oracle.density(P[S, 0], P[S, 1], P[S, 2], st2["level"][S], st2["h"][targets],
+                           m0=p["m0"], tol=1e-14, max_iter=100, periodic=True,
+                           targets=loc[targets])
+        assert o["failures"] == 0 and np.all(o["h"] < hm)
+        return o["rho"]
+
+    s0, eps = 0.2, 1e-6
+    fd = (c_loss(s0 + eps) - c_loss(s0 - eps)) / (2 * eps)
+
+    ctx = A.Context(params_for(p, prec))
+    ds = A.DeviceState.from_numpy(s1)
+    s = torch.tensor(s0, dtype=torch.float64, device="cuda", requires_grad=True)
+    cen = torch.tensor(centre, device="cuda")
+    et = torch.tensor(e, device="cuda")
+    ia = torch.as_tensor(split, device="cuda")
+    ib = torch.as_tensor(pb_all, device="cuda")
+    X = torch.tensor(X1, device="cuda")
+    X = X.index_put((ia,), cen + s * et).index_put((ib,), cen - s * et)
+    X = X - torch.floor(X).detach()
+    rho, *_ = A.apr_sums(ctx, ds, X[:, 0].contiguous(), X[:, 1].contiguous(),
+                         X[:, 2].contiguous())
+    ref = torch.tensor(rho_ref, device="cuda")
+    ta, tb = torch.as_tensor(pa, device="cuda"), torch.as_tensor(pb, device="cuda")
+    loss = ((rho.double()[ta] - ref) ** 2 + (rho.double()[tb] - ref) ** 2).sum()
+    loss.backward()
+    an = float(s.grad)
+    print(f"full-size r_sep gradient {prec}: {an:.10e} fd {fd:.10e}")
+    assert abs(an - fd) < (1e-4 if prec == "fp64" else 1e-3) * abs(fd), (an, fd)
