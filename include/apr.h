@@ -212,9 +212,11 @@ int apr_split_merge(apr_ctx *ctx, apr_state *s, const apr_zone *zones, int32_t n
 
 /* Kick-drift-kick leapfrog step of size dt on the state (the paper's host
  * code integrates; the scheme here is the standard KDK):
- *   v += dt/2 a, u += dt/2 du/dt;  x += dt v (wrapped if periodic);
- *   rebuild cells, density;  split/merge if nzones > 0 (then rebuild and
- *   density again);  hydro forces + sink gravity -> a, du/dt;
+ *   v += dt/2 a, u += dt/2 du/dt;  x += dt v (wrapped if periodic), and the
+ *   Newton guess h *= exp(dt div v / 3) from the last force pass;
+ *   split/merge if nzones > 0 (Sec. 2.6: refinement opens the step; the
+ *   nearest-neighbour cap uses the last density pass);
+ *   rebuild cells, density;  hydro forces + sink gravity -> a, du/dt;
  *   v += dt/2 a, u += dt/2 du/dt.
  * s->ax..dudt must hold the acceleration of the current positions on entry
  * (apr_accel computes it).  sinks are at their positions for the end of the

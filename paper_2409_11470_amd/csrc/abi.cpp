@@ -301,22 +301,16 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
     if (rc) return rc;
     rc = drift(c, s, dt);
     if (rc) return rc;
-    rc = build_cells(c, s, nullptr);
-    if (rc) return rc;
     if (nzones > 0) {
-        // density first: the split cap needs nearest-neighbour distances here
-        void *rho, *om, *a, *vs;
-        step_buffers(c, s->capacity, &rho, &om, &a, &vs);
-        rc = density(c, s, rho, om, nullptr, nullptr);
-        if (rc) return rc;
+        // the refinement pass opens the step (before this step's density); its
+        // nearest-neighbour cap uses the distances of the last density pass,
+        // still in the current particle order
         int64_t ns = 0, nm = 0, nsp = 0;
         rc = apr_split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp);
         if (rc) return rc;
-        if (ns + nm > 0 || c->cells_n != s->n) {
-            rc = build_cells(c, s, nullptr);
-            if (rc) return rc;
-        }
     }
+    rc = build_cells(c, s, nullptr);
+    if (rc) return rc;
     rc = accel_now(c, s, sinks, nsinks, false);
     if (rc) return rc;
     return kick(c, s, 0.5 * dt);

@@ -34,7 +34,7 @@ template <class T>
 struct VJPStage;
 template <>
 struct VJPStage<float> {
-    static constexpr int force = 512, dens = 1024;
+    static constexpr int force = 384, dens = 768;
 };
 template <>
 struct VJPStage<double> {

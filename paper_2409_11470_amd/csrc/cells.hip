@@ -298,6 +298,7 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm);
 
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
 {
+    c->divv_n = -1;  // the permutation below reorders the particles
     int tok = prof_begin(c, APR_PROF_CELLS);
     int rc = build_cells_impl(c, s, perm);
     prof_end(c, tok);

@@ -76,6 +76,8 @@ struct apr_ctx {
     // derived values of the last density / force evaluation (workspace)
     int64_t dens_n = -1;           // n of the last apr_density (for the split cap)
     int64_t force_n = -1;          // n of the last force evaluation (for the timestep)
+    int64_t divv_n = -1;           // velocity divergence of the last force evaluation is in the
+                                   // workspace "divv" in the current particle order (else -1)
     // kernel timing: pairs of events per index, summed at read time
     bool prof = false;
     struct EvPair {

@@ -33,13 +33,13 @@ template <class T>
 struct StageCap;
 template <>
 struct StageCap<float> {
-    static constexpr int value = 1536;
+    static constexpr int value = 1024;
 };
 template <>
 struct StageCap<double> {
     static constexpr int value = 768;
 };
-constexpr int kDTCap = 128;  // per-target list capacity (density)
+constexpr int kDTCap = 96;   // per-target list capacity (density)
 
 template <class T>
 struct DensArgs {
@@ -143,7 +143,7 @@ __device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<
 }
 
 template <class T>
-__global__ __launch_bounds__(kSearchThreads) void k_density(DensArgs<T> a)
+__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(DensArgs<T> a)
 {
     using V = vec4_t<T>;
     constexpr int STAGE = StageCap<T>::value;

@@ -23,7 +23,7 @@ template <class T>
 struct FStageCap;
 template <>
 struct FStageCap<float> {
-    static constexpr int value = 640;
+    static constexpr int value = 384;
 };
 template <>
 struct FStageCap<double> {
@@ -82,11 +82,12 @@ struct ForceOp {
     using V = vec4_t<T>;
     const V *pm, *vh, *th;
     T *ax, *ay, *az, *dudt, *vsig;
+    float *divv;
     double m0;
     T alpha, beta;
     __device__ V load(int k, int64_t i) const { return k == 0 ? pm[i] : (k == 1 ? vh[i] : th[i]); }
     struct Acc {
-        apr::Acc<T> x, y, z, u;
+        apr::Acc<T> x, y, z, u, dv;
         T vs, hi, hi2, hi4;
     };
     __device__ void init(Acc &A, const V *own) const
@@ -95,6 +96,7 @@ struct ForceOp {
         A.y.zero();
         A.z.zero();
         A.u.zero();
+        A.dv.zero();
         A.vs = alpha * own[2].z;
         A.hi = own[1].w;
         A.hi2 = A.hi * A.hi;
@@ -125,13 +127,15 @@ struct ForceOp {
         A.y.add(-term * dy);
         A.z.add(-term * dz);
         A.u.add(mb * Aa * vdr * Fa);
+        A.dv.add(mb * vdr * Fa);
     }
-    __device__ void finish(Acc &A, int64_t i, const V *, bool write) const
+    __device__ void finish(Acc &A, int64_t i, const V *own, bool write) const
     {
         A.x.template reduce<kLanes>();
         A.y.template reduce<kLanes>();
         A.z.template reduce<kLanes>();
         A.u.template reduce<kLanes>();
+        A.dv.template reduce<kLanes>();
         T vs = max4(A.vs);
         if (!write) return;
         double sc = m0 / kPi;
@@ -140,11 +144,13 @@ struct ForceOp {
         az[i] = (T)(sc * A.z.value());
         dudt[i] = (T)(sc * A.u.value());
         if (vsig) vsig[i] = vs;
+        // div v_a = -(1/(Omega_a rho_a)) sum_b m_b v_ab . grad_a W_ab(h_a)
+        divv[i] = (float)(-(double)own[2].y * sc * A.dv.value());
     }
 };
 
 template <class T>
-__global__ __launch_bounds__(kSearchThreads) void k_forces(Tree tr, ForceOp<T> op,
+__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree tr, ForceOp<T> op,
                                                            int32_t *status)
 {
     gather_pairs<T, ForceOp<T>, FStageCap<T>::value>(tr, op, status, ST_FORCE_DIRECT);
@@ -191,6 +197,8 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     rc = eos_pack(c, s, rho, omega);
     if (rc) return rc;
     Tree tr = make_tree(c);
+    float *divv = wsa<float>(c, "divv", (size_t)n);
+    if (!divv) return fail(c, APR_ERR_HIP, "workspace");
     int tok = prof_begin(c, APR_PROF_FORCES);
     if (p.precision == APR_FP32) {
         ForceOp<float> op;
@@ -199,6 +207,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         op.th = wsa<float4>(c, "th32", (size_t)n);
         op.ax = (float *)ax; op.ay = (float *)ay; op.az = (float *)az;
         op.dudt = (float *)dudt; op.vsig = (float *)vsig;
+        op.divv = divv;
         op.m0 = p.m0; op.alpha = (float)p.av_alpha; op.beta = (float)p.av_beta;
         hipLaunchKernelGGL(k_forces<float>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
                            c->stream, tr, op, c->d_status);
@@ -209,6 +218,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         op.th = wsa<double4>(c, "th64", (size_t)n);
         op.ax = (double *)ax; op.ay = (double *)ay; op.az = (double *)az;
         op.dudt = (double *)dudt; op.vsig = (double *)vsig;
+        op.divv = divv;
         op.m0 = p.m0; op.alpha = p.av_alpha; op.beta = p.av_beta;
         hipLaunchKernelGGL(k_forces<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
                            c->stream, tr, op, c->d_status);
@@ -216,6 +226,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     prof_end(c, tok);
     APR_LAUNCHED(c);
     c->force_n = n;
+    c->divv_n = n;
     return APR_OK;
 }
 

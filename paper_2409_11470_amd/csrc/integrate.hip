@@ -19,11 +19,20 @@ __global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, double *u,
     if (u && dudt) u[i] += dt * dudt[i];
 }
 
+// x += dt v (wrapped into a periodic box).  With divv (the velocity
+// divergence of the last force evaluation) the smoothing length is predicted
+// from the continuity equation, dh/dt = (h/3) div v, as the Newton guess of
+// the next density pass: h *= exp(dt div v / 3), the factor kept in [0.8, 1.25].
 __global__ void k_drift(int64_t n, double *x, double *y, double *z, const double *vx,
-                        const double *vy, const double *vz, double dt, Box b)
+                        const double *vy, const double *vz, double *h, const float *divv,
+                        double dt, Box b)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (divv) {
+        double f = exp(dt * (double)divv[i] / 3.0);
+        h[i] *= fmin(fmax(f, 0.8), 1.25);
+    }
     double *p[3] = {x, y, z};
     const double *v[3] = {vx, vy, vz};
 #pragma unroll
@@ -117,8 +126,9 @@ int kick(apr_ctx *c, apr_state *s, double dt)
 int drift(apr_ctx *c, apr_state *s, double dt)
 {
     int64_t n = s->n;
+    const float *divv = c->divv_n == n ? wsa<float>(c, "divv", (size_t)n) : nullptr;
     hipLaunchKernelGGL(k_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, n,
-                       s->x, s->y, s->z, s->vx, s->vy, s->vz, dt, make_box(c->p));
+                       s->x, s->y, s->z, s->vx, s->vy, s->vz, s->h, divv, dt, make_box(c->p));
     APR_LAUNCHED(c);
     c->cells_n = -1;
     return APR_OK;

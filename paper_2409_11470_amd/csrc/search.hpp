@@ -29,11 +29,16 @@ namespace apr {
 
 constexpr int kSearchThreads = 256;
 constexpr int kWaves = kSearchThreads / kWave;
-constexpr int kCandCap = 1024;   // candidate cells per chunk of the walk
+constexpr int kCandCap = 256;    // candidate cells per chunk of the walk
 constexpr int kSubCap = 512;     // staged candidates per sub-block
 constexpr int kGroup = 16;       // lanes per target (sub-block layout)
 constexpr int kLanes = 4;        // lanes per target (one target per lane group of 4)
-constexpr int kTCap = 192;       // per-target candidate list (u16 LDS indices)
+constexpr int kTCap = 128;       // per-target candidate list (u16 LDS indices)
+// Workgroups per CU the density and force kernels are compiled for: the FP32
+// kernels fit 4 (LDS <= 40 KB, <= 128 VGPRs) to hide the latency of the
+// candidate loads and LDS walks; the FP64 ones need more registers.
+template <class T>
+constexpr int kBlocksPerCU = sizeof(T) == 4 ? 4 : 2;
 
 // Orders LDS traffic between the lanes of one wavefront (a compiler and
 // memory fence at wavefront scope; the wavefront runs in lockstep).

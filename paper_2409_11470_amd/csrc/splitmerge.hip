@@ -218,10 +218,24 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
     if (i < n) p[i] = v;
 }
 
+// Combines a value over the 64 lanes of a wavefront (every lane gets the result).
+template <class T, class F>
+__device__ inline T wave_reduce(T v, F op)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = op(v, (T)__shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+__device__ inline int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+
 __global__ void k_max_level(int64_t n, const int8_t *level, int32_t *out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(out, (int32_t)level[i]);
+    int32_t v = i < n ? (int32_t)level[i] : 0;
+    v = wave_reduce(v, imax);
+    if (__lane_id() == 0) atomicMax(out, v);
 }
 
 __global__ void k_cand_flags(int64_t n, const int8_t *level, const uint8_t *changed,
@@ -310,12 +324,44 @@ __global__ void k_tree_init(TreeArgs a)
     nd.moved = ~0ull;
 }
 
+// True when every active lane of the wavefront works on the same node (the
+// rule at the upper levels of the tree): the wavefront then combines its
+// lanes first and one lane updates the node, instead of one atomic per
+// element on a single address.  *first receives that lane.
+__device__ inline bool wave_one_node(bool act, int32_t L, int *first)
+{
+    uint64_t m = __ballot(act);
+    if (m == 0) return false;
+    *first = __ffsll((unsigned long long)m) - 1;
+    int32_t L0 = __shfl(L, *first, 64);
+    return __all(!act || L == L0) != 0;
+}
+
 __global__ void k_tree_minmax(TreeArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || !active(a, i)) return;
-    Node &nd = a.node[a.lo[i]];
-    uint32_t p = a.es[i];
+    bool act = i < a.m && active(a, i);
+    int32_t L = act ? a.lo[i] : -1;
+    uint32_t p = act ? a.es[i] : 0u;
+    int first = 0;
+    if (wave_one_node(act, L, &first)) {
+        int32_t mn[3], mx[3];
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = act ? a.q[k][p] : 0;
+            mn[k] = wave_reduce(act ? v : INT32_MAX, imin);
+            mx[k] = wave_reduce(act ? v : INT32_MIN, imax);
+        }
+        if (__lane_id() == first) {
+            Node &nd = a.node[L];
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&nd.mn[k], mn[k]);
+                atomicMax(&nd.mx[k], mx[k]);
+            }
+        }
+        return;
+    }
+    if (!act) return;
+    Node &nd = a.node[L];
     for (int k = 0; k < 3; ++k) {
         atomicMin(&nd.mn[k], a.q[k][p]);
         atomicMax(&nd.mx[k], a.q[k][p]);
@@ -333,34 +379,81 @@ __global__ void k_tree_axis(TreeArgs a)
     nd.ax = ax;
 }
 
+__device__ inline unsigned long long umin64(unsigned long long a, unsigned long long b)
+{
+    return a < b ? a : b;
+}
+__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b)
+{
+    return a > b ? a : b;
+}
+__device__ inline unsigned long long uadd64(unsigned long long a, unsigned long long b)
+{
+    return a + b;
+}
+
 __global__ void k_tree_sum(TreeArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || !active(a, i)) return;
-    Node &nd = a.node[a.lo[i]];
-    atomicAdd(&nd.sum, (unsigned long long)a.q[nd.ax][a.es[i]]);
+    bool act = i < a.m && active(a, i);
+    int32_t L = act ? a.lo[i] : -1;
+    int first = 0;
+    unsigned long long v = act ? (unsigned long long)a.q[a.node[L].ax][a.es[i]] : 0ull;
+    if (wave_one_node(act, L, &first)) {
+        v = wave_reduce(v, uadd64);
+        if (__lane_id() == first) atomicAdd(&a.node[L].sum, v);
+        return;
+    }
+    if (act) atomicAdd(&a.node[L].sum, v);
 }
 
 __global__ void k_tree_count(TreeArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || !active(a, i)) return;
-    int32_t L = a.lo[i];
+    bool act = i < a.m && active(a, i);
+    int32_t L = act ? a.lo[i] : -1;
+    int first = 0;
+    bool lt = false, eq = false;
+    unsigned long long key = 0;
+    if (act) {
+        Node &nd = a.node[L];
+        int64_t n = a.hi[i] - L;
+        int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
+        uint32_t p = a.es[i];
+        int64_t v = a.q[nd.ax][p];
+        key = ((unsigned long long)v << kIdBits) |
+              ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
+        lt = v < c;
+        eq = v == c;
+    }
+    if (wave_one_node(act, L, &first)) {
+        uint32_t kc = (uint32_t)__popcll(__ballot(act && lt));
+        uint32_t keq = (uint32_t)__popcll(__ballot(act && eq));
+        unsigned long long amax_c = wave_reduce((act && lt) ? key : 0ull, umax64);
+        unsigned long long amin_c = wave_reduce((act && !lt) ? key : ~0ull, umin64);
+        unsigned long long amax_c1 = wave_reduce((act && (lt || eq)) ? key : 0ull, umax64);
+        unsigned long long amin_c1 = wave_reduce((act && !(lt || eq)) ? key : ~0ull, umin64);
+        if (__lane_id() == first) {
+            Node &nd = a.node[L];
+            if (kc) atomicAdd(&nd.kc, kc);
+            if (keq) atomicAdd(&nd.keq, keq);
+            atomicMax(&nd.amax_c, amax_c);
+            atomicMin(&nd.amin_c, amin_c);
+            atomicMax(&nd.amax_c1, amax_c1);
+            atomicMin(&nd.amin_c1, amin_c1);
+        }
+        return;
+    }
+    if (!act) return;
     Node &nd = a.node[L];
-    int64_t n = a.hi[i] - L;
-    int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
-    uint32_t p = a.es[i];
-    int64_t v = a.q[nd.ax][p];
-    unsigned long long key =
-        ((unsigned long long)v << kIdBits) | ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
-    if (v < c) {
+    if (lt) {
         atomicAdd(&nd.kc, 1u);
         atomicMax(&nd.amax_c, key);
     } else {
         atomicMin(&nd.amin_c, key);
     }
-    if (v == c) atomicAdd(&nd.keq, 1u);
-    if (v <= c) atomicMax(&nd.amax_c1, key);
+    if (eq) atomicAdd(&nd.keq, 1u);
+    if (lt || eq) atomicMax(&nd.amax_c1, key);
     else atomicMin(&nd.amin_c1, key);
 }
 
@@ -753,6 +846,7 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     APR_HIP(c, hipStreamSynchronize(c->stream));
     if (*n_split + *n_merged > 0) {  // the particle set changed: cells are stale
         c->cells_n = -1;
+        c->divv_n = -1;
         c->dens_n = -1;
         c->force_n = -1;
     }
