@@ -111,15 +111,15 @@ struct DSum {
     }
 };
 
-// Stages the candidates with staged offset in [w0, w0 + STAGE): positions in
-// the target cell's frame.  sB holds each candidate cell's first offset.
+// Stages the candidates with staged offset in [w0, w0 + STAGE) that are within
+// reach of some wavefront's targets: positions in the target cell's frame.
+// sB holds each candidate cell's first offset.
 template <class T, int STAGE>
 __device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<T> *pm,
                                     const int32_t *sA, const int32_t *sB, int nc, int total,
-                                    T R2, int w0, vec4_t<T> *stg)
+                                    const WaveBoxes<T> &B, int w0, vec4_t<T> *stg)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
     for (int ci = w; ci < nc; ci += kWaves) {
         int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
         if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
@@ -134,7 +134,7 @@ __device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<
             p.x = p.x + (T)sh[0];
             p.y = p.y + (T)sh[1];
             p.z = p.z + (T)sh[2];
-            hit = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez) < R2;
+            hit = wave_reach<T, false>(B, p.x, p.y, p.z, T(0));
         }
         uint64_t m = __ballot(hit);
         int off = o0 + __popcll(m & lanemask_lt()) - w0;
@@ -155,6 +155,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     __shared__ double s_red[kWaves];
     __shared__ int s_more;
     __shared__ Walk s_walk;
+    __shared__ WaveBoxes<T> s_wb;
 
     const Tree &tr = a.tree;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -175,14 +176,21 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     else { tp.x = T(0); tp.y = T(0); tp.z = T(0); tp.w = T(0); }
     uint16_t *mylist = tls[t < kCell ? t : 0];
 
-    double R;
+    // staged reach of each wavefront's targets (2 sigma of its largest h) and
+    // of the whole cell (the tree walk's radius)
+    double R, Rw[kWaves];
     {
+        wave_box<T>(&s_wb, valid, tp.x, tp.y, tp.z);
         double m = wave_max64(h);
         if (lane == 0) s_red[w] = m;
         __syncthreads();
         R = 0.0;
-        for (int k = 0; k < kWaves; ++k) R = fmax(R, s_red[k]);
-        R *= 2.0 * (double)kSigma;
+        for (int k = 0; k < kWaves; ++k) {
+            Rw[k] = 2.0 * (double)kSigma * s_red[k];
+            R = fmax(R, Rw[k]);
+        }
+        if (threadIdx.x == 0)
+            for (int k = 0; k < kWaves; ++k) s_wb.R2[k] = 16 * k < cnt ? (T)(Rw[k] * Rw[k]) : T(-1);
     }
 
     // Every new search follows a Newton step that grew some h, and every
@@ -220,8 +228,6 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 nc = s_ncand;
                 last = s_more == 0;
                 if (!last) multi = true;
-                const T R2c = (T)(R * R);
-                const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
                 for (int ci = w; ci < nc; ci += kWaves) {
                     int cc = sA[ci];
                     int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
@@ -230,8 +236,8 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                     bool hit = false;
                     if (lane < bn) {
                         V p = a.pm[b0 + lane];
-                        hit = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0),
-                                           T(0), T(0), ex, ey, ez) < R2c;
+                        hit = wave_reach<T, false>(s_wb, p.x + (T)sh[0], p.y + (T)sh[1],
+                                                   p.z + (T)sh[2], T(0));
                     }
                     uint64_t m = __ballot(hit);
                     if (lane == 0) sB[ci] = __popcll(m);
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
                 lists = false;
                 if (nwin == 1) {
-                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, R2c, 0, stg);
+                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, s_wb, 0, stg);
                     __syncthreads();
                 }
             }
@@ -260,8 +266,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 int nstg = min(STAGE, total - w0);
                 if (nwin > 1) {
                     __syncthreads();  // the previous window is no longer read
-                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, (T)(R * R), w0,
-                                           stg);
+                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, s_wb, w0, stg);
                     __syncthreads();
                 }
                 if (!wave_busy) continue;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 h = hn;
                 pending = true;
                 if (2.0 * hn > Rt) lists = false;   // own list too short now
-                if (2.0 * hn > R) needR = 2.0 * (double)kSigma * hn;
+                if (2.0 * hn > Rw[w]) needR = 2.0 * (double)kSigma * hn;
             }
         }
         // ---- block-wide: anything pending?  a larger search radius needed?
@@ -374,7 +379,15 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
             if (!(fl & 1)) break;
             if (fl & 2) lists = false;
             if (need > 0.0) {
-                R = fmax(need, 1.25 * R);
+                // a wavefront's reach no longer covers some 2h: widen it
+                for (int k = 0; k < kWaves; ++k) {
+                    if (s_red[k] > 0.0) Rw[k] = fmax(s_red[k], 1.25 * Rw[k]);
+                    R = fmax(R, Rw[k]);
+                }
+                __syncthreads();  // every thread has read s_red and the old reach
+                if (threadIdx.x == 0)
+                    for (int k = 0; k < kWaves; ++k)
+                        if (16 * k < cnt) s_wb.R2[k] = (T)(Rw[k] * Rw[k]);
                 search = true;
             }
         }

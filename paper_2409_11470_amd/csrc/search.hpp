@@ -274,6 +274,61 @@ __device__ inline T wave_min64(T v)
     return v;
 }
 
+// The targets of each wavefront (16 of a cell's 64) as a box [lo, hi] in the
+// cell frame with its own reach R: a candidate is staged only if it lies
+// within reach of some wavefront's box.  For cells of mixed h this is much
+// tighter than one radius (from the largest h) around the whole cell.
+template <class T>
+struct WaveBoxes {
+    T lo[kWaves][3], hi[kWaves][3];
+    T R2[kWaves];   // < 0: the wavefront has no target
+};
+
+// Every thread calls it; (x, y, z) is this lane's target position, valid if
+// the lane has a target.  Writes the wavefront's box (not R2) to B.
+template <class T>
+__device__ inline void wave_box(WaveBoxes<T> *B, bool valid, T x, T y, T z)
+{
+    const T big = T(3.0e38);
+    T lx = wave_min64(valid ? x : big), ly = wave_min64(valid ? y : big),
+      lz = wave_min64(valid ? z : big);
+    T hx = wave_max64(valid ? x : -big), hy = wave_max64(valid ? y : -big),
+      hz = wave_max64(valid ? z : -big);
+    if (lane_id() == 0) {
+        int w = threadIdx.x / kWave;
+        B->lo[w][0] = lx; B->lo[w][1] = ly; B->lo[w][2] = lz;
+        B->hi[w][0] = hx; B->hi[w][1] = hy; B->hi[w][2] = hz;
+    }
+}
+
+// Squared distance of a point to the box [lo, hi].
+template <class T>
+__device__ inline T pt_lohi_d2(T x, T y, T z, const T *lo, const T *hi)
+{
+    T gx = fmax(fmax(lo[0] - x, x - hi[0]), T(0));
+    T gy = fmax(fmax(lo[1] - y, y - hi[1]), T(0));
+    T gz = fmax(fmax(lo[2] - z, z - hi[2]), T(0));
+    return gx * gx + gy * gy + gz * gz;
+}
+
+// Within reach of some wavefront's targets: d2_w < R2_w or, with SYM, within
+// the candidate's own support, d2_w / h_b^2 < 4 (hb2 = 1/h_b^2).
+// The wavefront loop is kept rolled so that the boxes are read from LDS at
+// each test (broadcast reads) instead of living in registers across the
+// staging loops (28 values).
+template <class T, bool SYM>
+__device__ inline bool wave_reach(const WaveBoxes<T> &B, T x, T y, T z, T hb2)
+{
+    bool hit = false;
+#pragma unroll 1
+    for (int k = 0; k < kWaves; ++k) {
+        T r2 = B.R2[k];
+        T d2 = pt_lohi_d2<T>(x, y, z, B.lo[k], B.hi[k]);
+        hit = hit || (r2 >= T(0) && (d2 < r2 || (SYM && d2 * hb2 < T(4))));
+    }
+    return hit;
+}
+
 // Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
 template <class T>
 __device__ inline T wmax_groups(T v)
