@@ -2,10 +2,13 @@
 // particle state -> leaf cells of at most 64 consecutive particles -> a
 // 64-ary tree of bounding boxes over the cells.
 //
-// Cells never cross a Morton prefix boundary at the segment level (2 for
-// periodic boxes, so a cell spans at most a quarter of the box per axis;
-// 3 otherwise), which keeps them compact where the Morton curve jumps.
-// All counts stay on the device (Hdr); kernels are sized by upper bounds.
+// Cells are cut from the leaves of the octree that the sorted keys define:
+// a leaf is the largest Morton cube holding at most kLeafCap particles (and
+// no larger than a segment: level 2 for periodic boxes, so a cell spans at
+// most a quarter of the box per axis; 3 otherwise), and each leaf is cut
+// into runs of 64.  Cubes keep the cells compact where the Morton curve
+// jumps, e.g. across the thin layers of a disc.  The cell count is read back
+// once per build so that the search kernels are launched on exact grids.
 #include "common.hpp"
 
 namespace apr {
@@ -44,72 +47,95 @@ __global__ void k_morton(const double *x, const double *y, const double *z, int6
     vals[i] = (uint32_t)i;
 }
 
-// Sorted keys: a segment starts where the key prefix changes.  segfirst is
-// pre-filled with UINT32_MAX; each non-empty segment's first index is written
-// once (no atomics).
-__global__ void k_seg_first(const uint32_t *keys, int64_t n, int segshift, uint32_t *segfirst)
+constexpr int kLeafCap = 256;  // particles of an octree leaf before it is split
+
+// Number of leading Morton levels (bit triplets) two 30-bit keys share, 0..10.
+__device__ inline int common_levels(uint32_t a, uint32_t b)
+{
+    uint32_t x = a ^ b;
+    return x == 0 ? 10 : (__clz(x) - 2) / 3;
+}
+
+// Leaf starts.  i starts a leaf iff i = 0, or it starts a segment, or the
+// cube shared by particles i-1 and i (level d = common_levels) holds more
+// than kLeafCap particles: then the cube is split and i and i-1 fall into
+// different children.  That cube holds more than C = kLeafCap particles iff
+// some window of C + 1 consecutive particles around i-1, i lies inside it,
+// i.e. iff g(j) = common_levels(key_j, key_{j+C}) >= d for some j in
+// [i - C, i - 1] (the keys are sorted).  One block of C threads per C
+// particles: the window maximum is the suffix maximum of g over the previous
+// C positions and the prefix maximum over this block's.  Equal keys never
+// start a leaf (a leaf of more than C equal keys is cut into runs of 64 like
+// any other).
+__global__ __launch_bounds__(kLeafCap) void k_leaf_flags(const uint32_t *keys, int64_t n,
+                                                        int seglev, uint32_t *flag)
+{
+    __shared__ int gp[kLeafCap], gc[kLeafCap];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kLeafCap;
+    const int64_t i = base + t;
+    auto g = [&](int64_t j) -> int {
+        return (j >= 0 && j + kLeafCap < n) ? common_levels(keys[j], keys[j + kLeafCap]) : -1;
+    };
+    gp[t] = g(base - kLeafCap + t);
+    gc[t] = g(base + t);
+    __syncthreads();
+    // suffix maximum of gp, prefix maximum of gc (Hillis-Steele, in place)
+    for (int o = 1; o < kLeafCap; o <<= 1) {
+        int a = t + o < kLeafCap ? gp[t + o] : -1;
+        int b = t >= o ? gc[t - o] : -1;
+        __syncthreads();
+        gp[t] = max(gp[t], a);
+        gc[t] = max(gc[t], b);
+        __syncthreads();
+    }
+    if (i >= n) return;
+    int win = max(gp[t], t > 0 ? gc[t - 1] : -1);
+    uint32_t f = 1;
+    if (i > 0) {
+        int d = common_levels(keys[i - 1], keys[i]);
+        f = (d < seglev || (d < 10 && win >= d)) ? 1u : 0u;
+    }
+    flag[i] = f;
+}
+
+// Leaf index -> first particle; lstart[nleaves] = n.
+__global__ void k_leaf_start(const uint32_t *flag, const uint32_t *lidx, int64_t n,
+                             uint32_t *lstart)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t s = keys[i] >> segshift;
-    if (i == 0 || (keys[i - 1] >> segshift) != s) segfirst[s] = (uint32_t)i;
+    if (flag[i]) lstart[lidx[i]] = (uint32_t)i;
+    if (i == n - 1) lstart[lidx[i] + flag[i]] = (uint32_t)n;
 }
 
-// One block: segment counts from the first indices, segment starts, cells per
-// segment and their offsets, the header.
-__global__ __launch_bounds__(1024) void k_seg_scan(const uint32_t *segfirst, int nseg,
-                                                   int64_t n, uint32_t *segstart,
-                                                   uint32_t *celloff, Hdr *hdr,
-                                                   int32_t *cell_start, int nlev)
+// A cell starts every 64 particles from the start of each leaf.
+__global__ void k_cell_flags(const uint32_t *flag, const uint32_t *lidx, const uint32_t *lstart,
+                             int64_t n, uint32_t *cflag)
 {
-    __shared__ uint32_t ps[4096], pc[4096];
-    for (int s = threadIdx.x; s < nseg; s += blockDim.x) ps[s] = segfirst[s];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // nseg <= 4096: serial passes of a few microseconds keep this simple
-        uint32_t next = (uint32_t)n;
-        for (int s = nseg - 1; s >= 0; --s) {
-            uint32_t f = ps[s];
-            uint32_t cnt = 0;
-            if (f != 0xffffffffu) {
-                cnt = next - f;
-                next = f;
-            }
-            ps[s] = cnt;
-        }
-        uint32_t a = 0, b = 0;
-        for (int s = 0; s < nseg; ++s) {
-            uint32_t ca = ps[s], cb = (ca + kCell - 1) / kCell;
-            ps[s] = a;
-            pc[s] = b;
-            a += ca;
-            b += cb;
-        }
-        hdr->ncells = (int32_t)b;
-        int64_t m = b;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t leaf = lidx[i] + flag[i] - 1;
+    cflag[i] = ((uint32_t)i - lstart[leaf]) % kCell == 0 ? 1u : 0u;
+}
+
+// Cell starts and the header (counts per tree level; nlev from the host).
+__global__ void k_cell_start(const uint32_t *cflag, const uint32_t *cidx, int64_t n,
+                             int32_t *cell_start, Hdr *hdr, int nlev)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cflag[i]) cell_start[cidx[i]] = (int32_t)i;
+    if (i == n - 1) {
+        int64_t m = (int64_t)cidx[i] + cflag[i];
+        cell_start[m] = (int32_t)n;
+        hdr->ncells = (int32_t)m;
         hdr->nnode[0] = (int32_t)m;
         for (int k = 1; k <= kMaxLev; ++k) {
             m = k <= nlev ? (m + kFan - 1) / kFan : 0;
             hdr->nnode[k] = (int32_t)m;
         }
-        cell_start[b] = (int32_t)n;
     }
-    __syncthreads();
-    for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
-        segstart[s] = ps[s];
-        celloff[s] = pc[s];
-    }
-}
-
-__global__ void k_cell_start(const uint32_t *keys, int64_t n, int segshift,
-                             const uint32_t *segstart, const uint32_t *celloff,
-                             int32_t *cell_start)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t s = keys[i] >> segshift;
-    int64_t r = i - (int64_t)segstart[s];
-    if (r % kCell == 0) cell_start[celloff[s] + r / kCell] = (int32_t)i;
 }
 
 struct PermArgs {
@@ -312,30 +338,17 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     if (n >= (int64_t)1 << 31) return fail(c, APR_ERR_INVALID, "too many particles");
     Box b = make_box(c->p);
     int seglev = c->p.periodic ? 2 : 3;
-    int segshift = kKeyBits - 3 * seglev;
-    int nseg = 1 << (3 * seglev);
-    // bounds: every segment adds at most one partial cell
-    int64_t cb = ceil_div(n, kCell) + nseg;
-    c->cells_bound = cb;
-    int nlev = 0;
-    int64_t m = cb;
-    c->nnode_bound[0] = cb;
-    while (m > kFan) {
-        m = ceil_div(m, kFan);
-        nlev += 1;
-        c->nnode_bound[nlev] = m;
-    }
-    if (nlev > kMaxLev) return fail(c, APR_ERR_INVALID, "too many cells");
-    c->nlev = nlev;
 
     uint32_t *keys = wsa<uint32_t>(c, "mkeys", (size_t)n);
     uint32_t *vals = wsa<uint32_t>(c, "mvals", (size_t)n);
-    uint32_t *segcount = wsa<uint32_t>(c, "segcount", (size_t)nseg);
-    uint32_t *segstart = wsa<uint32_t>(c, "segstart", (size_t)nseg);
-    uint32_t *celloff = wsa<uint32_t>(c, "celloff", (size_t)nseg);
+    uint32_t *lflag = wsa<uint32_t>(c, "leaf_flag", (size_t)n);
+    uint32_t *lidx = wsa<uint32_t>(c, "leaf_idx", (size_t)n);
+    uint32_t *lstart = wsa<uint32_t>(c, "leaf_start", (size_t)n + 1);
+    uint32_t *cflag = wsa<uint32_t>(c, "cell_flag", (size_t)n);
+    uint32_t *cidx = wsa<uint32_t>(c, "cell_idx", (size_t)n);
+    uint32_t *tot = wsa<uint32_t>(c, "cell_total", 2);
     Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
-    int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)cb + 1);
-    if (!keys || !vals || !segcount || !segstart || !celloff || !hdr || !cs)
+    if (!keys || !vals || !lflag || !lidx || !lstart || !cflag || !cidx || !tot || !hdr)
         return fail(c, APR_ERR_HIP, "cell workspace");
     unsigned g = (unsigned)ceil_div(n, 256);
     hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, c->stream, s->x, s->y, s->z, n, b, keys,
@@ -369,14 +382,39 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     hipLaunchKernelGGL(k_scatter_back, dim3(g), dim3(256), 0, c->stream, pa);
     APR_LAUNCHED(c);
 
-    rc = fill_u32(c, segcount, 0xffffffffu, nseg);
+    // octree leaves, then cells of <= 64 within each leaf
+    hipLaunchKernelGGL(k_leaf_flags, dim3((unsigned)ceil_div(n, kLeafCap)), dim3(kLeafCap), 0,
+                       c->stream, keys, n, seglev, lflag);
+    APR_LAUNCHED(c);
+    rc = exclusive_scan_u32(c, lflag, lidx, n, nullptr);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_seg_first, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
-                       segcount);
-    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, c->stream, segcount, nseg, n,
-                       segstart, celloff, hdr, cs, nlev);
-    hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, c->stream, keys, n, segshift,
-                       segstart, celloff, cs);
+    hipLaunchKernelGGL(k_leaf_start, dim3(g), dim3(256), 0, c->stream, lflag, lidx, n, lstart);
+    hipLaunchKernelGGL(k_cell_flags, dim3(g), dim3(256), 0, c->stream, lflag, lidx, lstart, n,
+                       cflag);
+    APR_LAUNCHED(c);
+    rc = exclusive_scan_u32(c, cflag, cidx, n, tot);
+    if (rc) return rc;
+    // the cell count sizes every search launch: read it back once per build
+    uint32_t ncell_h = 0;
+    APR_HIP(c, hipMemcpyAsync(&ncell_h, tot, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    int64_t cb = (int64_t)ncell_h;
+    if (cb < 1 || cb > n) return fail(c, APR_ERR_HIP, "cell count out of range");
+    c->cells_bound = cb;
+    int nlev = 0;
+    int64_t m = cb;
+    c->nnode_bound[0] = cb;
+    while (m > kFan) {
+        m = ceil_div(m, kFan);
+        nlev += 1;
+        c->nnode_bound[nlev] = m;
+    }
+    if (nlev > kMaxLev) return fail(c, APR_ERR_INVALID, "too many cells");
+    c->nlev = nlev;
+    int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)cb + 1);
+    if (!cs) return fail(c, APR_ERR_HIP, "cell workspace");
+    hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, c->stream, cflag, cidx, n, cs, hdr,
+                       nlev);
     APR_LAUNCHED(c);
 
     Geo *cells = cell_level(c, 0);
