@@ -170,6 +170,13 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     double h = valid ? a.h[s0 + t] : 0.0;
     double Rt = 0.0;
     int itc = 0, tlen = 0;
+    // results of this lane's target, stored once after the iteration (no global
+    // writes inside the loop: every barrier waits for outstanding ones)
+    T out_rho = T(0), out_om = T(0), out_dnn = T(0);
+    int out_nn = 0;
+    bool noconv = false;
+    // work counters of the block (thread 0), added once at the end
+    int c_restage = 0, c_direct = 0, c_windows = 0, c_passes = 0;
     bool done = !valid;
     V tp;
     if (valid) tp = a.pm[s0 + t];
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         if (walking) {
             __syncthreads();
             if (w == 0) walk_init(tr, tg, R, false, &s_walk);
-            if (search && pass > 0 && threadIdx.x == 0) atomicAdd(&a.status[ST_RESTAGE], 1);
+            if (search && pass > 0) c_restage += 1;
         }
         for (int chunk = 0;; ++chunk) {
             bool last = true;
@@ -247,8 +254,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                     int tot = wave_excl_scan_lds(sB, nc);
                     if (lane == 0) {
                         s_total = tot;
-                        if (pass == 0 && chunk == 0 && (tot > STAGE || !last))
-                            atomicAdd(&a.status[ST_DENS_DIRECT], 1);
+                        if (pass == 0 && chunk == 0 && (tot > STAGE || !last)) c_direct = 1;
                     }
                 }
                 __syncthreads();
@@ -309,12 +315,12 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                     }
                 }
             }
-            if (threadIdx.x == 0) atomicAdd(&a.status[ST_WINDOWS], nwin);
+            c_windows += nwin;
             if (last) break;
         }
         search = false;
         lists = !multi && nwin == 1;
-        if (threadIdx.x == 0) atomicAdd(&a.status[ST_PASSES], 1);
+        c_passes += 1;
         // ---- FP64 Newton step of this lane's target (its 4 lanes agree)
         double needR = 0.0;
         bool pending = false;
@@ -340,18 +346,11 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
             if (conv || itc >= a.max_iter) {
                 done = true;
                 h = hh;
-                if (j == 0) {
-                    int64_t i = s0 + t;
-                    a.h[i] = hh;
-                    a.rho[i] = (T)rhos;
-                    a.omega[i] = (T)(1.0 - D / (3.0 * W));
-                    if (a.nneigh) a.nneigh[i] = nn;
-                    if (a.iters) a.iters[i] = itc;
-                    if (a.dnn)
-                        a.dnn[i] = nzero >= 2 ? T(0)
-                                              : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
-                    if (!conv) atomicAdd(&a.status[ST_NOCONV], 1);
-                }
+                out_rho = (T)rhos;
+                out_om = (T)(1.0 - D / (3.0 * W));
+                out_nn = nn;
+                out_dnn = nzero >= 2 ? T(0) : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
+                noconv = !conv;
             } else {
                 h = hn;
                 pending = true;
@@ -393,6 +392,23 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         }
     }
 
+    // ---- results and counters
+    if (valid && j == 0) {
+        int64_t i = s0 + t;
+        a.h[i] = h;
+        a.rho[i] = out_rho;
+        a.omega[i] = out_om;
+        if (a.nneigh) a.nneigh[i] = out_nn;
+        if (a.iters) a.iters[i] = itc;
+        if (a.dnn) a.dnn[i] = out_dnn;
+        if (noconv) atomicAdd(&a.status[ST_NOCONV], 1);
+    }
+    if (threadIdx.x == 0) {
+        if (c_restage) atomicAdd(&a.status[ST_RESTAGE], c_restage);
+        if (c_direct) atomicAdd(&a.status[ST_DENS_DIRECT], c_direct);
+        atomicAdd(&a.status[ST_WINDOWS], c_windows);
+        atomicAdd(&a.status[ST_PASSES], c_passes);
+    }
     // ---- new h_max of the cell for the force search
     {
         double m = wave_max64(valid ? h : 0.0);

@@ -59,6 +59,7 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
     const bool wave_busy = __any(valid);
     const T ra = valid ? T(2) / own[1].w : T(0);
 
+    bool multiwin = false;  // counted once at the end (no global atomics in the loop)
     if (w == 0) walk_init(tr, tg, R, true, &s_walk);
     for (int chunk = 0;; ++chunk) {
         // ---- next chunk of candidate cells
@@ -93,11 +94,8 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
         __syncthreads();
         if (w == 0) {
             int tot = wave_excl_scan_lds(sB, nc);
-            if (lane == 0) {
-                s_total = tot;
-                if ((tot > STAGE || more || chunk > 0) && st_word >= 0 && chunk == 0)
-                    atomicAdd(&status[st_word], 1);
-            }
+            if (lane == 0) s_total = tot;
+            if (chunk == 0 && (tot > STAGE || more)) multiwin = true;
         }
         __syncthreads();
         const int total = s_total;
@@ -177,6 +175,7 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
         if (!more) break;
     }
     op.finish(acc, s0 + t, own, valid && j == 0);
+    if (threadIdx.x == 0 && multiwin && st_word >= 0) atomicAdd(&status[st_word], 1);
 }
 
 }  // namespace apr
