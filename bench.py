@@ -131,13 +131,17 @@ def run_form(A, torch, st, p, precision, steps, warmup):
     ms_d, cnt_d = prof[A.APR_PROF_DENSITY]
     ms_f, cnt_f = prof[A.APR_PROF_FORCES]
     ms_c, cnt_c = prof[A.APR_PROF_CELLS]
+    ms_p, cnt_p = prof[A.APR_PROF_CAND]
     res = dict(n=n, dt=dt, wall_s=wall, ms_per_step=1e3 * wall / steps,
                interactions_per_step=per_step, density_pairs=idens, force_pairs=iforce,
                value=per_step * steps / wall, failures=fails,
                density_ms=ms_d / max(cnt_d, 1), forces_ms=ms_f / max(cnt_f, 1),
                cells_ms=ms_c / max(cnt_c, 1), launches=(cnt_d, cnt_f, cnt_c),
+               cand_ms_per_step=ms_p / max(steps, 1),
                counters=counters)
-    res["density_force_rate"] = per_step / (1e-3 * (res["density_ms"] + res["forces_ms"]))
+    # density + forces pass: both kernels and the candidate walks ahead of them
+    res["density_force_rate"] = per_step / (1e-3 * (res["density_ms"] + res["forces_ms"] +
+                                                    res["cand_ms_per_step"]))
     ctx.close()
     return res
 
@@ -222,11 +226,14 @@ def forward_adjoint(A, torch, ctx, ds, reps):
     ms = {k: prof[i][0] / max(prof[i][1], 1) for k, i in
           (("density_ms", A.APR_PROF_DENSITY), ("forces_ms", A.APR_PROF_FORCES),
            ("vjp_ms", A.APR_PROF_VJP))}
+    ms["cand_ms_per_rep"] = prof[A.APR_PROF_CAND][0] / reps
     inter = d + f
     out = dict(n=n, interactions=inter, failures=fails, reps=reps,
                wall_ms_per_rep=1e3 * wall / reps, **ms)
-    out["forward_rate"] = inter / (1e-3 * (ms["density_ms"] + ms["forces_ms"]))
-    out["adjoint_rate"] = inter / (1e-3 * ms["vjp_ms"])
+    # each of density, forces and the adjoint has one candidate walk ahead of it
+    cw = ms["cand_ms_per_rep"] / 3.0
+    out["forward_rate"] = inter / (1e-3 * (ms["density_ms"] + ms["forces_ms"] + 2 * cw))
+    out["adjoint_rate"] = inter / (1e-3 * (ms["vjp_ms"] + cw))
     out["forward_adjoint_rate"] = inter * reps / wall
     return out
 
@@ -377,11 +384,11 @@ def main():
                    "newton_tol": 1e-6},
         "roofline": roof, "cpu_baseline": cpu,
         "fp32_form": {k: r32[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms",
-                                           "cells_ms", "interactions_per_step",
+                                           "cells_ms", "cand_ms_per_step", "interactions_per_step",
                                            "density_force_rate", "failures", "counters")},
         "fp64_form": None if r64 is None else {
             k: r64[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms", "cells_ms",
-                                "interactions_per_step", "density_force_rate", "failures",
+                                "cand_ms_per_step", "interactions_per_step", "density_force_rate", "failures",
                                 "counters")},
     }
     out["legs"] = legs

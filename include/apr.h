@@ -241,11 +241,12 @@ int apr_sync_status(apr_ctx *ctx, int64_t *count);
  * stream bracket every launch of the timed kernels: index APR_PROF_DENSITY
  * (h-rho Newton kernel), APR_PROF_FORCES (force kernel), APR_PROF_CELLS
  * (whole cell build), APR_PROF_SPLITMERGE (whole split/merge pass),
- * APR_PROF_VJP (the three kernels of apr_vjp).
+ * APR_PROF_VJP (the three kernels of apr_vjp), APR_PROF_CAND (the candidate-cell
+ * walks ahead of the density, force and adjoint kernels).
  * apr_profile_read synchronises, writes the summed milliseconds and launch
  * counts per index (arrays of APR_PROF_N) and, if reset, clears them. */
 enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
-       APR_PROF_VJP = 4, APR_PROF_N = 5 };
+       APR_PROF_VJP = 4, APR_PROF_CAND = 5, APR_PROF_N = 6 };
 int apr_profile_enable(apr_ctx *ctx, int on);
 /* Work counters since the last reset (diagnostics), written to c[0..7]:
  * [0] h-rho solves that hit max_iter, [1] overflowed lists without fallback,

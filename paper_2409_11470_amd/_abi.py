@@ -7,8 +7,8 @@ APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP, APR_
 APR_FP64, APR_FP32 = 0, 1
 APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL, APR_EOS_ADIABATIC = 0, 1, 2
 APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM = 0, 1
-APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP, APR_PROF_N = (
-    0, 1, 2, 3, 4, 5)
+(APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP,
+ APR_PROF_CAND, APR_PROF_N) = (0, 1, 2, 3, 4, 5, 6)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 

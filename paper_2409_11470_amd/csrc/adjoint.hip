@@ -193,16 +193,16 @@ struct DensVJP {
 
 template <class T>
 __global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<T> op,
-                                                              int32_t *status)
+                                                              CandList pre, int32_t *status)
 {
-    gather_pairs<T, ForceVJP<T>, VJPStage<T>::force>(tr, op, status, -1);
+    gather_pairs<T, ForceVJP<T>, VJPStage<T>::force>(tr, op, pre, status, -1);
 }
 
 template <class T>
 __global__ __launch_bounds__(kSearchThreads) void k_vjp_dens(Tree tr, DensVJP<T> op,
-                                                             int32_t *status)
+                                                             CandList pre, int32_t *status)
 {
-    gather_pairs<T, DensVJP<T>, VJPStage<T>::dens>(tr, op, status, -1);
+    gather_pairs<T, DensVJP<T>, VJPStage<T>::dens>(tr, op, pre, status, -1);
 }
 
 template <class T>
@@ -324,6 +324,9 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     const V *vh = (const V *)ws(c, f32 ? "vh32" : "vh64", n * sizeof(V) + 256);
     const V *th = (const V *)ws(c, f32 ? "th32" : "th64", n * sizeof(V) + 256);
     Tree tr = make_tree(c);
+    CandList pre;
+    rc = cand_pre(c, tr, true, 2.0, &pre);
+    if (rc) return rc;
     unsigned g = (unsigned)ceil_div(n, 256);
     static const char *fn[9] = {"vf0", "vf1", "vf2", "vf3", "vf4", "vf5", "vf6", "vf7", "vf8"};
     T *fout[9];
@@ -346,7 +349,7 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
         op.beta = (T)p.av_beta;
         for (int k = 0; k < 9; ++k) op.out[k] = fout[k];
         hipLaunchKernelGGL(k_vjp_force<T>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, c->d_status);
+                           c->stream, tr, op, pre, c->d_status);
         APR_LAUNCHED(c);
     }
     FPtrs<T> fp;
@@ -386,7 +389,7 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     dop.xbar[2] = (T *)zbar;
     dop.mbar = (T *)mbar;
     hipLaunchKernelGGL(k_vjp_dens<T>, dim3((unsigned)cb), dim3(kSearchThreads), 0, c->stream,
-                       tr, dop, c->d_status);
+                       tr, dop, pre, c->d_status);
     APR_LAUNCHED(c);
     return APR_OK;
 }

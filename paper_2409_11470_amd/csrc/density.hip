@@ -52,6 +52,7 @@ struct DensArgs {
     int32_t *iters;
     T *dnn;
     float *hmax_new;      // per cell
+    CandList pre;         // candidate cells walked ahead (radius 2 sigma hmax)
     double m0, hfact, tol;
     int max_iter;
     int32_t *status;
@@ -214,7 +215,12 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         S.zero();
         const bool wave_busy = __any(!done);
         const bool walking = search || multi;
-        if (walking) {
+        // the first search can take the candidates walked ahead of this kernel
+        int pre_n = -1;
+        if (pass == 0 && a.pre.ncand && R <= a.pre.rfac * (double)tg.hmax)
+            pre_n = a.pre.ncand[cell];
+        const bool use_pre = walking && pre_n >= 0;
+        if (walking && !use_pre) {
             __syncthreads();
             if (w == 0) walk_init(tr, tg, R, false, &s_walk);
             if (search && pass > 0) c_restage += 1;
@@ -224,7 +230,14 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
             if (walking) {
                 // ---- next chunk of candidate cells, staged counts and offsets
                 __syncthreads();
-                if (w == 0) {
+                if (use_pre) {
+                    for (int k = threadIdx.x; k < pre_n; k += kSearchThreads)
+                        sA[k] = a.pre.cand[cell * kCandCap + k];
+                    if (threadIdx.x == 0) {
+                        s_ncand = pre_n;
+                        s_more = 0;
+                    }
+                } else if (w == 0) {
                     int ncl = walk_next(tr, tg, R, false, &s_walk, sA, kCandCap);
                     if (lane == 0) {
                         s_ncand = ncl;
@@ -452,6 +465,9 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
     float *hmax_new = wsa<float>(c, "hmax_new", (size_t)cb);
     int32_t *st = c->d_status;
     Tree tr = make_tree(c);
+    CandList pre;
+    int rc0 = cand_pre(c, tr, false, 2.0 * (double)kSigma, &pre);
+    if (rc0) return rc0;
     int tok = prof_begin(c, APR_PROF_DENSITY);
     if (c->p.precision == APR_FP32) {
         DensArgs<float> a;
@@ -464,6 +480,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.iters = iters;
         a.dnn = wsa<float>(c, "dnn32", (size_t)s->capacity);
         a.hmax_new = hmax_new;
+        a.pre = pre;
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;
@@ -482,6 +499,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.iters = iters;
         a.dnn = wsa<double>(c, "dnn64", (size_t)s->capacity);
         a.hmax_new = hmax_new;
+        a.pre = pre;
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;

@@ -151,9 +151,9 @@ struct ForceOp {
 
 template <class T>
 __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree tr, ForceOp<T> op,
-                                                           int32_t *status)
+                                                           CandList pre, int32_t *status)
 {
-    gather_pairs<T, ForceOp<T>, FStageCap<T>::value>(tr, op, status, ST_FORCE_DIRECT);
+    gather_pairs<T, ForceOp<T>, FStageCap<T>::value>(tr, op, pre, status, ST_FORCE_DIRECT);
 }
 
 }  // namespace
@@ -199,6 +199,9 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     Tree tr = make_tree(c);
     float *divv = wsa<float>(c, "divv", (size_t)n);
     if (!divv) return fail(c, APR_ERR_HIP, "workspace");
+    CandList pre;
+    rc = cand_pre(c, tr, true, 2.0, &pre);
+    if (rc) return rc;
     int tok = prof_begin(c, APR_PROF_FORCES);
     if (p.precision == APR_FP32) {
         ForceOp<float> op;
@@ -210,7 +213,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         op.divv = divv;
         op.m0 = p.m0; op.alpha = (float)p.av_alpha; op.beta = (float)p.av_beta;
         hipLaunchKernelGGL(k_forces<float>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, c->d_status);
+                           c->stream, tr, op, pre, c->d_status);
     } else {
         ForceOp<double> op;
         op.pm = wsa<double4>(c, "pm64", (size_t)n);
@@ -221,7 +224,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
         op.divv = divv;
         op.m0 = p.m0; op.alpha = p.av_alpha; op.beta = p.av_beta;
         hipLaunchKernelGGL(k_forces<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, c->d_status);
+                           c->stream, tr, op, pre, c->d_status);
     }
     prof_end(c, tok);
     APR_LAUNCHED(c);

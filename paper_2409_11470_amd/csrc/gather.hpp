@@ -24,7 +24,8 @@
 namespace apr {
 
 template <class T, class OP, int STAGE>
-__device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int st_word)
+__device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, int32_t *status,
+                             int st_word)
 {
     using V = vec4_t<T>;
     constexpr int NS = OP::NS;
@@ -60,11 +61,20 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, int32_t *status, int 
     const T ra = valid ? T(2) / own[1].w : T(0);
 
     bool multiwin = false;  // counted once at the end (no global atomics in the loop)
-    if (w == 0) walk_init(tr, tg, R, true, &s_walk);
+    // candidates walked ahead of this kernel (same radius), else walk here
+    const int pre_n = (pre.ncand && pre.rfac == 2.0) ? pre.ncand[cell] : -1;
+    if (pre_n < 0 && w == 0) walk_init(tr, tg, R, true, &s_walk);
     for (int chunk = 0;; ++chunk) {
         // ---- next chunk of candidate cells
         __syncthreads();  // the previous chunk is no longer read
-        if (w == 0) {
+        if (pre_n >= 0) {
+            for (int k = threadIdx.x; k < pre_n; k += kSearchThreads)
+                sA[k] = pre.cand[cell * kCandCap + k];
+            if (threadIdx.x == 0) {
+                s_ncand = pre_n;
+                s_more = 0;
+            }
+        } else if (w == 0) {
             int ncl = walk_next(tr, tg, R, true, &s_walk, sA, kCandCap);
             if (lane == 0) {
                 s_ncand = ncl;

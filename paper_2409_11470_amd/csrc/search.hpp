@@ -160,6 +160,16 @@ __device__ inline int walk_next(const Tree &t, const Geo &tg, double R, bool sym
     return n;
 }
 
+// Candidate cells of every cell from a walk ahead of the search kernel (see
+// candidates.hip): cand[cell * kCandCap + k], k < ncand[cell]; ncand -1 means
+// "walk yourself".  The walk used radius rfac * hmax of the cell.
+struct CandList {
+    const int32_t *cand = nullptr;
+    const int32_t *ncand = nullptr;
+    double rfac = 0.0;
+};
+int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out);
+
 // In-place exclusive prefix sum of cnt[0..n) by one wavefront; returns the total.
 __device__ inline int wave_excl_scan_lds(int32_t *cnt, int n)
 {
