@@ -56,84 +56,251 @@ __device__ inline int common_levels(uint32_t a, uint32_t b)
     return x == 0 ? 10 : (__clz(x) - 2) / 3;
 }
 
+__device__ inline int32_t wave_reduce_max(int32_t v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ inline int32_t wave_reduce_sum(int32_t v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
 // Leaf starts.  i starts a leaf iff i = 0, or it starts a segment, or the
 // cube shared by particles i-1 and i (level d = common_levels) holds more
 // than kLeafCap particles: then the cube is split and i and i-1 fall into
 // different children.  That cube holds more than C = kLeafCap particles iff
 // some window of C + 1 consecutive particles around i-1, i lies inside it,
 // i.e. iff g(j) = common_levels(key_j, key_{j+C}) >= d for some j in
-// [i - C, i - 1] (the keys are sorted).  One block of C threads per C
-// particles: the window maximum is the suffix maximum of g over the previous
-// C positions and the prefix maximum over this block's.  Equal keys never
-// start a leaf (a leaf of more than C equal keys is cut into runs of 64 like
-// any other).
-__global__ __launch_bounds__(kLeafCap) void k_leaf_flags(const uint32_t *keys, int64_t n,
-                                                        int seglev, uint32_t *flag)
+// [i - C, i - 1] (the keys are sorted).  Equal keys never start a leaf (a
+// leaf of more than C equal keys is cut into runs of 64 like any other).
+//
+// Tiles of kTile particles per workgroup of 1024 threads.  The window
+// maximum comes from prefix and suffix maxima over aligned segments of C
+// positions (a window of C spans at most two of them).
+constexpr int kTileThreads = 1024;
+constexpr int kTileItems = 4;
+constexpr int kTile = kTileThreads * kTileItems;
+
+__global__ __launch_bounds__(kTileThreads) void k_leaf_flags(const uint32_t *keys, int64_t n,
+                                                             int seglev, uint32_t *flag,
+                                                             int32_t *blast)
 {
-    __shared__ int gp[kLeafCap], gc[kLeafCap];
+    constexpr int P = kTile + kLeafCap;  // position p <-> particle base - C + p
+    constexpr int S = (P + kTileThreads - 1) / kTileThreads;
+    __shared__ int8_t pre[P], suf[P];
+    __shared__ int32_t red[kTileThreads / kWave];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kLeafCap;
-    const int64_t i = base + t;
-    auto g = [&](int64_t j) -> int {
-        return (j >= 0 && j + kLeafCap < n) ? common_levels(keys[j], keys[j + kLeafCap]) : -1;
-    };
-    gp[t] = g(base - kLeafCap + t);
-    gc[t] = g(base + t);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int p = t; p < P; p += kTileThreads) {
+        int64_t j = base - kLeafCap + p;
+        int8_t g = (j >= 0 && j + kLeafCap < n)
+                       ? (int8_t)common_levels(keys[j], keys[j + kLeafCap])
+                       : (int8_t)-1;
+        pre[p] = g;
+        suf[p] = g;
+    }
     __syncthreads();
-    // suffix maximum of gp, prefix maximum of gc (Hillis-Steele, in place)
     for (int o = 1; o < kLeafCap; o <<= 1) {
-        int a = t + o < kLeafCap ? gp[t + o] : -1;
-        int b = t >= o ? gc[t - o] : -1;
+        int8_t a[S], b[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            int p = t + k * kTileThreads;
+            int r = p & (kLeafCap - 1);
+            a[k] = (p < P && r >= o) ? pre[p - o] : (int8_t)-1;
+            b[k] = (p < P && r + o < kLeafCap) ? suf[p + o] : (int8_t)-1;
+        }
         __syncthreads();
-        gp[t] = max(gp[t], a);
-        gc[t] = max(gc[t], b);
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            int p = t + k * kTileThreads;
+            if (p < P) {
+                pre[p] = a[k] > pre[p] ? a[k] : pre[p];
+                suf[p] = b[k] > suf[p] ? b[k] : suf[p];
+            }
+        }
         __syncthreads();
     }
-    if (i >= n) return;
-    int win = max(gp[t], t > 0 ? gc[t - 1] : -1);
-    uint32_t f = 1;
-    if (i > 0) {
-        int d = common_levels(keys[i - 1], keys[i]);
-        f = (d < seglev || (d < 10 && win >= d)) ? 1u : 0u;
+    int32_t last = -1;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        int q = t + k * kTileThreads;
+        int64_t i = base + q;
+        if (i >= n) continue;
+        // window [i - C, i - 1] = positions [q, q + C - 1]
+        int win = suf[q];
+        if (q & (kLeafCap - 1)) win = max(win, (int)pre[q + kLeafCap - 1]);
+        uint32_t f = 1;
+        if (i > 0) {
+            int d = common_levels(keys[i - 1], keys[i]);
+            f = (d < seglev || (d < 10 && win >= d)) ? 1u : 0u;
+        }
+        flag[i] = f;
+        if (f) last = (int32_t)i;
     }
-    flag[i] = f;
+    last = wave_reduce_max(last);
+    if (lane_id() == 0) red[t / kWave] = last;
+    __syncthreads();
+    if (t == 0) {
+        int32_t m = -1;
+        for (int w = 0; w < kTileThreads / kWave; ++w) m = max(m, red[w]);
+        blast[blockIdx.x] = m;
+    }
 }
 
-// Leaf index -> first particle; lstart[nleaves] = n.
-__global__ void k_leaf_start(const uint32_t *flag, const uint32_t *lidx, int64_t n,
-                             uint32_t *lstart)
+// One workgroup: exclusive scan of v[0..nb) in place, with operator max
+// (identity -1) or +; the total goes to *total when given.
+template <bool MAX>
+__global__ __launch_bounds__(kTileThreads) void k_scan_blocks(int32_t *v, int64_t nb,
+                                                              int32_t *total)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (flag[i]) lstart[lidx[i]] = (uint32_t)i;
-    if (i == n - 1) lstart[lidx[i] + flag[i]] = (uint32_t)n;
+    __shared__ int32_t red[kTileThreads / kWave + 1];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int32_t id = MAX ? -1 : 0;
+    auto op = [](int32_t a, int32_t b) { return MAX ? max(a, b) : a + b; };
+    int64_t per = (nb + kTileThreads - 1) / kTileThreads;
+    int64_t b0 = (int64_t)t * per, b1 = min(b0 + per, nb);
+    int32_t s = id;
+    for (int64_t k = b0; k < b1; ++k) s = op(s, v[k]);
+    // exclusive scan of the thread sums
+    int32_t incl = s;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl = op(incl, u);
+    }
+    if (lane == kWave - 1) red[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+        int32_t acc = id;
+        for (int k = 0; k < kTileThreads / kWave; ++k) {
+            int32_t x = red[k];
+            red[k] = acc;
+            acc = op(acc, x);
+        }
+        red[kTileThreads / kWave] = acc;
+    }
+    __syncthreads();
+    int32_t ex = op(red[w], __shfl_up(incl, 1, kWave));
+    if (lane == 0) ex = red[w];
+    for (int64_t k = b0; k < b1; ++k) {
+        int32_t x = v[k];
+        v[k] = ex;
+        ex = op(ex, x);
+    }
+    if (t == 0 && total) *total = red[kTileThreads / kWave];
 }
 
-// A cell starts every 64 particles from the start of each leaf.
-__global__ void k_cell_flags(const uint32_t *flag, const uint32_t *lidx, const uint32_t *lstart,
-                             int64_t n, uint32_t *cflag)
+// Cell starts inside leaves: every 64 particles from the leaf's first.  The
+// leaf start of i is the largest leaf start <= i: an inclusive max-scan, the
+// earlier tiles' part from carry[].  Writes cflag and the tile's cell count.
+__global__ __launch_bounds__(kTileThreads) void k_cell_flags(const uint32_t *flag,
+                                                             const int32_t *carry, int64_t n,
+                                                             uint32_t *cflag, int32_t *bsum)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t leaf = lidx[i] + flag[i] - 1;
-    cflag[i] = ((uint32_t)i - lstart[leaf]) % kCell == 0 ? 1u : 0u;
+    __shared__ int32_t red[kTileThreads / kWave + 1];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)t * kTileItems;
+    int32_t m[kTileItems];
+    int32_t run = -1;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        int64_t i = i0 + k;
+        if (i < n && flag[i]) run = (int32_t)i;
+        m[k] = run;
+    }
+    // exclusive max-scan of the threads' last starts
+    int32_t incl = run;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl = max(incl, u);
+    }
+    if (lane == kWave - 1) red[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+        int32_t acc = carry[blockIdx.x];
+        for (int k = 0; k < kTileThreads / kWave; ++k) {
+            int32_t x = red[k];
+            red[k] = acc;
+            acc = max(acc, x);
+        }
+    }
+    __syncthreads();
+    int32_t prev = __shfl_up(incl, 1, kWave);
+    int32_t before = lane > 0 ? max(red[w], prev) : red[w];
+    int32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        int64_t i = i0 + k;
+        if (i >= n) break;
+        int32_t ls = max(before, m[k]);
+        uint32_t cf = (i - ls) % kCell == 0 ? 1u : 0u;
+        cflag[i] = cf;
+        cnt += (int32_t)cf;
+    }
+    cnt = wave_reduce_sum(cnt);
+    __syncthreads();
+    if (lane == 0) red[w] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int32_t s = 0;
+        for (int k = 0; k < kTileThreads / kWave; ++k) s += red[k];
+        bsum[blockIdx.x] = s;
+    }
 }
 
 // Cell starts and the header (counts per tree level; nlev from the host).
-__global__ void k_cell_start(const uint32_t *cflag, const uint32_t *cidx, int64_t n,
-                             int32_t *cell_start, Hdr *hdr, int nlev)
+__global__ __launch_bounds__(kTileThreads) void k_cell_start(const uint32_t *cflag,
+                                                             const int32_t *boff, int64_t n,
+                                                             int32_t *cell_start, Hdr *hdr,
+                                                             int nlev)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (cflag[i]) cell_start[cidx[i]] = (int32_t)i;
-    if (i == n - 1) {
-        int64_t m = (int64_t)cidx[i] + cflag[i];
-        cell_start[m] = (int32_t)n;
-        hdr->ncells = (int32_t)m;
-        hdr->nnode[0] = (int32_t)m;
-        for (int k = 1; k <= kMaxLev; ++k) {
-            m = k <= nlev ? (m + kFan - 1) / kFan : 0;
-            hdr->nnode[k] = (int32_t)m;
+    __shared__ int32_t red[kTileThreads / kWave + 1];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    const int64_t i0 = (int64_t)blockIdx.x * kTile + (int64_t)t * kTileItems;
+    uint32_t cf[kTileItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        int64_t i = i0 + k;
+        cf[k] = i < n ? cflag[i] : 0u;
+        s += (int32_t)cf[k];
+    }
+    int32_t incl = s;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) red[w] = incl;
+    __syncthreads();
+    if (t == 0) {
+        int32_t acc = boff[blockIdx.x];
+        for (int k = 0; k < kTileThreads / kWave; ++k) {
+            int32_t x = red[k];
+            red[k] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    int32_t idx = red[w] + incl - s;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        int64_t i = i0 + k;
+        if (i >= n) break;
+        if (cf[k]) cell_start[idx] = (int32_t)i;
+        idx += (int32_t)cf[k];
+        if (i == n - 1) {
+            int64_t m = idx;
+            cell_start[m] = (int32_t)n;
+            hdr->ncells = (int32_t)m;
+            hdr->nnode[0] = (int32_t)m;
+            for (int l = 1; l <= kMaxLev; ++l) {
+                m = l <= nlev ? (m + kFan - 1) / kFan : 0;
+                hdr->nnode[l] = (int32_t)m;
+            }
         }
     }
 }
@@ -342,13 +509,12 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     uint32_t *keys = wsa<uint32_t>(c, "mkeys", (size_t)n);
     uint32_t *vals = wsa<uint32_t>(c, "mvals", (size_t)n);
     uint32_t *lflag = wsa<uint32_t>(c, "leaf_flag", (size_t)n);
-    uint32_t *lidx = wsa<uint32_t>(c, "leaf_idx", (size_t)n);
-    uint32_t *lstart = wsa<uint32_t>(c, "leaf_start", (size_t)n + 1);
     uint32_t *cflag = wsa<uint32_t>(c, "cell_flag", (size_t)n);
-    uint32_t *cidx = wsa<uint32_t>(c, "cell_idx", (size_t)n);
-    uint32_t *tot = wsa<uint32_t>(c, "cell_total", 2);
+    int32_t *blast = wsa<int32_t>(c, "tile_last", (size_t)ceil_div(n, kTile));
+    int32_t *bsum = wsa<int32_t>(c, "tile_cells", (size_t)ceil_div(n, kTile));
+    int32_t *tot = wsa<int32_t>(c, "cell_total", 2);
     Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
-    if (!keys || !vals || !lflag || !lidx || !lstart || !cflag || !cidx || !tot || !hdr)
+    if (!keys || !vals || !lflag || !cflag || !blast || !bsum || !tot || !hdr)
         return fail(c, APR_ERR_HIP, "cell workspace");
     unsigned g = (unsigned)ceil_div(n, 256);
     hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, c->stream, s->x, s->y, s->z, n, b, keys,
@@ -383,20 +549,20 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     APR_LAUNCHED(c);
 
     // octree leaves, then cells of <= 64 within each leaf
-    hipLaunchKernelGGL(k_leaf_flags, dim3((unsigned)ceil_div(n, kLeafCap)), dim3(kLeafCap), 0,
-                       c->stream, keys, n, seglev, lflag);
+    int64_t nt = ceil_div(n, kTile);
+    unsigned gt = (unsigned)nt;
+    hipLaunchKernelGGL(k_leaf_flags, dim3(gt), dim3(kTileThreads), 0, c->stream, keys, n, seglev,
+                       lflag, blast);
+    hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(kTileThreads), 0, c->stream, blast, nt,
+                       (int32_t *)nullptr);
+    hipLaunchKernelGGL(k_cell_flags, dim3(gt), dim3(kTileThreads), 0, c->stream, lflag, blast, n,
+                       cflag, bsum);
+    hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(kTileThreads), 0, c->stream, bsum, nt,
+                       tot);
     APR_LAUNCHED(c);
-    rc = exclusive_scan_u32(c, lflag, lidx, n, nullptr);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_leaf_start, dim3(g), dim3(256), 0, c->stream, lflag, lidx, n, lstart);
-    hipLaunchKernelGGL(k_cell_flags, dim3(g), dim3(256), 0, c->stream, lflag, lidx, lstart, n,
-                       cflag);
-    APR_LAUNCHED(c);
-    rc = exclusive_scan_u32(c, cflag, cidx, n, tot);
-    if (rc) return rc;
     // the cell count sizes every search launch: read it back once per build
-    uint32_t ncell_h = 0;
-    APR_HIP(c, hipMemcpyAsync(&ncell_h, tot, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    int32_t ncell_h = 0;
+    APR_HIP(c, hipMemcpyAsync(&ncell_h, tot, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     APR_HIP(c, hipStreamSynchronize(c->stream));
     int64_t cb = (int64_t)ncell_h;
     if (cb < 1 || cb > n) return fail(c, APR_ERR_HIP, "cell count out of range");
@@ -413,8 +579,8 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     c->nlev = nlev;
     int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)cb + 1);
     if (!cs) return fail(c, APR_ERR_HIP, "cell workspace");
-    hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, c->stream, cflag, cidx, n, cs, hdr,
-                       nlev);
+    hipLaunchKernelGGL(k_cell_start, dim3(gt), dim3(kTileThreads), 0, c->stream, cflag, bsum, n,
+                       cs, hdr, nlev);
     APR_LAUNCHED(c);
 
     Geo *cells = cell_level(c, 0);

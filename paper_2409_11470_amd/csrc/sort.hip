@@ -131,9 +131,11 @@ int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const ch
 }
 
 // ------------------------------------------------------------------ radix sort
-constexpr int kRadixBits = 8;
+// 10-bit digits: the 30-bit Morton keys take three passes.
+constexpr int kRadixBits = 10;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
+constexpr int kBinsPerThread = kBins / kSortThreads;
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // items per block
 
@@ -142,7 +144,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
                                                              int64_t nblocks)
 {
     __shared__ uint32_t h[kBins];
-    h[threadIdx.x] = 0;  // kSortThreads == kBins
+#pragma unroll
+    for (int k = 0; k < kBinsPerThread; ++k) h[threadIdx.x + k * kSortThreads] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortRounds; ++r) {
@@ -150,7 +153,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kBins - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kBinsPerThread; ++k) {
+        int b = threadIdx.x + k * kSortThreads;
+        hist[(int64_t)b * nblocks + blockIdx.x] = h[b];
+    }
 }
 
 // Stable scatter: in each round of 256 consecutive items, an item's rank among
@@ -163,8 +170,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     constexpr int nw = kSortThreads / kWave;
     __shared__ uint32_t run[kBins];
     __shared__ uint32_t wc[nw][kBins];
-    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    for (int w = 0; w < nw; ++w) wc[w][threadIdx.x] = 0;
+#pragma unroll
+    for (int k = 0; k < kBinsPerThread; ++k) {
+        int b = threadIdx.x + k * kSortThreads;
+        run[b] = offs[(int64_t)b * nblocks + blockIdx.x];
+        for (int w = 0; w < nw; ++w) wc[w][b] = 0;
+    }
     __syncthreads();
     int w = threadIdx.x / kWave;
     int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -192,12 +203,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             vout[pos] = val;
         }
         __syncthreads();
-        uint32_t add = 0;
-        for (int v = 0; v < nw; ++v) {
-            add += wc[v][threadIdx.x];
-            wc[v][threadIdx.x] = 0;
+#pragma unroll
+        for (int k = 0; k < kBinsPerThread; ++k) {
+            int b = threadIdx.x + k * kSortThreads;
+            uint32_t add = 0;
+            for (int v = 0; v < nw; ++v) {
+                add += wc[v][b];
+                wc[v][b] = 0;
+            }
+            run[b] += add;
         }
-        run[threadIdx.x] += add;
         __syncthreads();
     }
 }
