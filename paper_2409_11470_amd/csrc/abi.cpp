@@ -274,7 +274,7 @@ static int accel_now(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t ns
     size_t stride = (size_t)s->capacity * e;
     rc = density(c, s, rho, om, nullptr, nullptr);
     if (rc) return rc;
-    rc = forces(c, s, rho, om, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, vs);
+    rc = forces(c, s, rho, om, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, vs, true);
     if (rc) return rc;
     return total_accel(c, s, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, sinks, nsinks);
 }

@@ -209,8 +209,10 @@ Geo *cell_level(apr_ctx *c, int lev);
 
 // density.hip / forces.hip
 int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters);
+// hmax_fresh: the cells' h_max already hold the state's h (a density pass on
+// this state just ran), so the refit from h is skipped.
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-           void *ay, void *az, void *dudt, void *vsig);
+           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh = false);
 // EOS pack of forces.hip: vh = (v, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0)
 // into the workspace buffers vh32/th32 (FP32) or vh64/th64 (FP64).
 int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega);

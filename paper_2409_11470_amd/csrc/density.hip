@@ -76,14 +76,13 @@ __device__ inline void m4_fg(T q, T &f, T &g)
 template <class T>
 struct DSum {
     Acc<T> w, d;   // sum m f, sum m (3f + q f')
-    int nn, nzero;
+    int cnt;       // neighbours in the low 16 bits, those at r = 0 above
     T dmin;
     __device__ void zero()
     {
         w.zero();
         d.zero();
-        nn = 0;
-        nzero = 0;
+        cnt = 0;
         dmin = T(3.0e38);
     }
     __device__ void pair(T dx, T dy, T dz, T m, T R2, T hinv)
@@ -95,9 +94,8 @@ struct DSum {
             m4_fg<T>(r * hinv, f, g);
             w.add(m * f);
             d.add(m * g);
-            nn += 1;
             bool zero = !(r2 > T(0));
-            nzero += zero ? 1 : 0;
+            cnt += zero ? 0x10001 : 1;
             T rr = zero ? T(3.0e38) : r;
             dmin = dmin < rr ? dmin : rr;
         }
@@ -106,8 +104,7 @@ struct DSum {
     {
         w.reduce16();
         d.reduce16();
-        nn = wsum16(nn);
-        nzero = wsum16(nzero);
+        cnt = wsum16(cnt);
         dmin = wmin16(dmin);
     }
 };
@@ -157,6 +154,13 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     __shared__ int s_more;
     __shared__ Walk s_walk;
     __shared__ WaveBoxes<T> s_wb;
+    __shared__ double s_Rw[kWaves];  // each wavefront's staged reach
+    // each target's results until the final store (registers are scarce)
+    struct Out {
+        T rho, om, dnn;
+        int nn;  // neighbour count; negative: the solve hit max_iter
+    };
+    __shared__ Out s_out[kCell];
 
     const Tree &tr = a.tree;
     int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -169,13 +173,10 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     const bool valid = t < cnt;
 
     double h = valid ? a.h[s0 + t] : 0.0;
-    double Rt = 0.0;
+    float Rt = 0.0f;  // reach of this target's list (2 sigma h, a 10% margin)
     int itc = 0, tlen = 0;
-    // results of this lane's target, stored once after the iteration (no global
+    // results are kept in s_out and stored once after the iteration (no global
     // writes inside the loop: every barrier waits for outstanding ones)
-    T out_rho = T(0), out_om = T(0), out_dnn = T(0);
-    int out_nn = 0;
-    bool noconv = false;
     // work counters of the block (thread 0), added once at the end
     int c_restage = 0, c_direct = 0, c_windows = 0, c_passes = 0;
     bool done = !valid;
@@ -186,19 +187,20 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
 
     // staged reach of each wavefront's targets (2 sigma of its largest h) and
     // of the whole cell (the tree walk's radius)
-    double R, Rw[kWaves];
+    double R;
     {
         wave_box<T>(&s_wb, valid, tp.x, tp.y, tp.z);
         double m = wave_max64(h);
         if (lane == 0) s_red[w] = m;
         __syncthreads();
         R = 0.0;
-        for (int k = 0; k < kWaves; ++k) {
-            Rw[k] = 2.0 * (double)kSigma * s_red[k];
-            R = fmax(R, Rw[k]);
-        }
+        for (int k = 0; k < kWaves; ++k) R = fmax(R, 2.0 * (double)kSigma * s_red[k]);
         if (threadIdx.x == 0)
-            for (int k = 0; k < kWaves; ++k) s_wb.R2[k] = 16 * k < cnt ? (T)(Rw[k] * Rw[k]) : T(-1);
+            for (int k = 0; k < kWaves; ++k) {
+                double rw = 2.0 * (double)kSigma * s_red[k];
+                s_Rw[k] = rw;
+                s_wb.R2[k] = 16 * k < cnt ? (T)(rw * rw) : T(-1);
+            }
     }
 
     // Every new search follows a Newton step that grew some h, and every
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 if (!wave_busy) continue;
                 if (!lists) {
                     // this target's candidates within 2 sigma h (with margin)
-                    Rt = done ? 0.0 : 2.0 * (double)kSigma * h;
+                    Rt = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
                     const T Rtl = (T)Rt;
                     build_lists16<T>(
                         nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
@@ -339,7 +341,8 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         bool pending = false;
         S.w.template reduce<kLanes>();
         S.d.template reduce<kLanes>();
-        int nn = sum4(S.nn), nzero = sum4(S.nzero);
+        int cnt4 = sum4(S.cnt);
+        int nn = cnt4 & 0xffff, nzero = cnt4 >> 16;
         T dmin = min4(S.dmin);
         if (!done) {
             double W = S.w.value(), D = S.d.value();
@@ -359,16 +362,20 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
             if (conv || itc >= a.max_iter) {
                 done = true;
                 h = hh;
-                out_rho = (T)rhos;
-                out_om = (T)(1.0 - D / (3.0 * W));
-                out_nn = nn;
-                out_dnn = nzero >= 2 ? T(0) : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
-                noconv = !conv;
+                if (j == 0) {
+                    Out o;
+                    o.rho = (T)rhos;
+                    o.om = (T)(1.0 - D / (3.0 * W));
+                    o.dnn = nzero >= 2 ? T(0)
+                                       : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
+                    o.nn = conv ? nn : -1 - nn;
+                    s_out[t] = o;
+                }
             } else {
                 h = hn;
                 pending = true;
-                if (2.0 * hn > Rt) lists = false;   // own list too short now
-                if (2.0 * hn > Rw[w]) needR = 2.0 * (double)kSigma * hn;
+                if (2.0 * hn > (double)Rt) lists = false;   // own list too short now
+                if (2.0 * hn > s_Rw[w]) needR = 2.0 * (double)kSigma * hn;
             }
         }
         // ---- block-wide: anything pending?  a larger search radius needed?
@@ -393,13 +400,16 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
             if (need > 0.0) {
                 // a wavefront's reach no longer covers some 2h: widen it
                 for (int k = 0; k < kWaves; ++k) {
-                    if (s_red[k] > 0.0) Rw[k] = fmax(s_red[k], 1.25 * Rw[k]);
-                    R = fmax(R, Rw[k]);
+                    double rw = s_red[k] > 0.0 ? fmax(s_red[k], 1.25 * s_Rw[k]) : s_Rw[k];
+                    R = fmax(R, rw);
                 }
                 __syncthreads();  // every thread has read s_red and the old reach
                 if (threadIdx.x == 0)
-                    for (int k = 0; k < kWaves; ++k)
-                        if (16 * k < cnt) s_wb.R2[k] = (T)(Rw[k] * Rw[k]);
+                    for (int k = 0; k < kWaves; ++k) {
+                        double rw = s_red[k] > 0.0 ? fmax(s_red[k], 1.25 * s_Rw[k]) : s_Rw[k];
+                        s_Rw[k] = rw;
+                        if (16 * k < cnt) s_wb.R2[k] = (T)(rw * rw);
+                    }
                 search = true;
             }
         }
@@ -408,13 +418,14 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     // ---- results and counters
     if (valid && j == 0) {
         int64_t i = s0 + t;
+        Out o = s_out[t];
         a.h[i] = h;
-        a.rho[i] = out_rho;
-        a.omega[i] = out_om;
-        if (a.nneigh) a.nneigh[i] = out_nn;
+        a.rho[i] = o.rho;
+        a.omega[i] = o.om;
+        if (a.nneigh) a.nneigh[i] = o.nn >= 0 ? o.nn : -1 - o.nn;
         if (a.iters) a.iters[i] = itc;
-        if (a.dnn) a.dnn[i] = out_dnn;
-        if (noconv) atomicAdd(&a.status[ST_NOCONV], 1);
+        if (a.dnn) a.dnn[i] = o.dnn;
+        if (o.nn < 0) atomicAdd(&a.status[ST_NOCONV], 1);
     }
     if (threadIdx.x == 0) {
         if (c_restage) atomicAdd(&a.status[ST_RESTAGE], c_restage);

@@ -182,7 +182,7 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 }
 
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-           void *ay, void *az, void *dudt, void *vsig)
+           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh)
 {
     if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "apr_build_cells first");
     if (!rho || !omega || !ax || !ay || !az || !dudt)
@@ -192,7 +192,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     const apr_params &p = c->p;
     if (p.eos == APR_EOS_ADIABATIC && !s->u) return fail(c, APR_ERR_INVALID, "u is required");
     // the force search needs the supports of the h the state holds now
-    int rc = cells_hmax_from(c, s->h, n);
+    int rc = hmax_fresh ? APR_OK : cells_hmax_from(c, s->h, n);
     if (rc) return rc;
     rc = eos_pack(c, s, rho, omega);
     if (rc) return rc;
