@@ -38,7 +38,8 @@ enum {
     APR_ERR_CAPACITY = 2,   /* splits need more than state->capacity */
     APR_ERR_NOCONVERGE = 3, /* some h-rho Newton solves did not converge */
     APR_ERR_HIP = 4,        /* a HIP runtime call failed */
-    APR_ERR_OVERFLOW = 5    /* a fixed-size internal list overflowed */
+    APR_ERR_OVERFLOW = 5,   /* reserved (no internal list has a fixed capacity) */
+    APR_ERR_RANGE = 6       /* a smoothing length reached a periodic box's limit */
 };
 
 enum { APR_FP64 = 0, APR_FP32 = 1 };
@@ -123,7 +124,9 @@ const char *apr_last_error(const apr_ctx *ctx);
  * search.  perm (device, optional) receives, for every new slot, the slot the
  * particle came from.  Replaces the k-d tree neighbour search of the paper's
  * host code (Sec. 2.3) with Morton-ordered leaf cells of at most 64
- * particles.  Periodic boxes need 2 max(h) < box / 4. */
+ * particles.  Periodic boxes need 2 max(h) < box / 4 (the minimum image of a cell
+ * pair then holds for all its particle pairs); apr_density flags a converged
+ * h beyond that (APR_ERR_RANGE from apr_sync_status). */
 int apr_build_cells(apr_ctx *ctx, apr_state *s, int64_t *perm);
 
 /* Density and smoothing length (paper Sec. 2.2, which defers to Phantom's
@@ -232,7 +235,7 @@ int apr_accel(apr_ctx *ctx, apr_state *s, const apr_sink *sinks, int32_t nsinks)
  * (0.3 by analogy with the paper's relaxation step, Sec. 2.4).  Synchronises. */
 int apr_timestep(apr_ctx *ctx, const apr_state *s, double C, double *dt);
 
-/* Waits for the stream and returns APR_ERR_NOCONVERGE / APR_ERR_OVERFLOW if
+/* Waits for the stream and returns APR_ERR_NOCONVERGE / APR_ERR_RANGE if
  * a kernel since the last call flagged one; *count receives the number of
  * particles that failed to converge (may be NULL).  Clears the flags. */
 int apr_sync_status(apr_ctx *ctx, int64_t *count);
@@ -249,7 +252,7 @@ enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_S
        APR_PROF_VJP = 4, APR_PROF_CAND = 5, APR_PROF_N = 6 };
 int apr_profile_enable(apr_ctx *ctx, int on);
 /* Work counters since the last reset (diagnostics), written to c[0..7]:
- * [0] h-rho solves that hit max_iter, [1] overflowed lists without fallback,
+ * [0] h-rho solves that hit max_iter, [1] smoothing lengths at the periodic limit,
  * [2] density cells whose candidates did not fit in one LDS window (staged
  * window by window instead), [3] the same for forces, [4] sub-block lists
  * that did not fit, [5] density searches repeated with a larger radius,

@@ -2,6 +2,7 @@
 import ctypes as C
 import os
 
+APR_ERR_RANGE = 6
 APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP, APR_ERR_OVERFLOW = (
     0, 1, 2, 3, 4, 5)
 APR_FP64, APR_FP32 = 0, 1

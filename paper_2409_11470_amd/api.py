@@ -298,7 +298,7 @@ def apr_profile_read(ctx, reset=True):
     return {k: (ms[k], cnt[k]) for k in range(APR_PROF_N)}
 
 
-COUNTER_NAMES = ("noconverge", "overflow", "density_multiwindow_cells",
+COUNTER_NAMES = ("noconverge", "periodic_range", "density_multiwindow_cells",
                  "force_multiwindow_cells", "subblock_direct", "density_restage",
                  "density_passes", "density_windows")
 

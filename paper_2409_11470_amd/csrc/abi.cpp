@@ -380,9 +380,11 @@ int apr_sync_status(apr_ctx *c, int64_t *count)
     APR_HIP(c, hipStreamSynchronize(c->stream));
     // the flags are cleared; the work counters [ST_DENS_DIRECT..] are kept
     APR_HIP(c, hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * 2, c->stream));
-    int32_t nc = c->h_status[ST_NOCONV], ov = c->h_status[ST_OVERFLOW];
+    int32_t nc = c->h_status[ST_NOCONV], ov = c->h_status[ST_RANGE];
     if (count) *count = nc;
-    if (ov) return fail(c, APR_ERR_OVERFLOW, "an internal candidate list overflowed");
+    if (ov)
+        return fail(c, APR_ERR_RANGE,
+                    "a smoothing length reached the periodic limit (2 h < a quarter of the box)");
     if (nc) return fail(c, APR_ERR_NOCONVERGE, std::to_string(nc) + " h-rho solves did not converge");
     return APR_OK;
 }

@@ -23,7 +23,7 @@ constexpr double kPi = 3.14159265358979323846;
 // Status words on the device (ctx->d_status).
 enum {
     ST_NOCONV = 0,        // h-rho solves that hit max_iter
-    ST_OVERFLOW = 1,      // a list that has no fallback overflowed
+    ST_RANGE = 1,         // a converged h at or beyond the periodic limit (2h < box/4)
     ST_DENS_DIRECT = 2,   // density: cells whose staged set did not fit in LDS
     ST_FORCE_DIRECT = 3,  // forces: same
     ST_SUB_DIRECT = 4,    // sub-block lists that did not fit

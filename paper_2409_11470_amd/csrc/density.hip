@@ -54,6 +54,7 @@ struct DensArgs {
     float *hmax_new;      // per cell
     CandList pre;         // candidate cells walked ahead (radius 2 sigma hmax)
     double m0, hfact, tol;
+    double hlim;          // periodic boxes: h must stay below this (0: no limit)
     int max_iter;
     int32_t *status;
 };
@@ -426,6 +427,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         if (a.iters) a.iters[i] = itc;
         if (a.dnn) a.dnn[i] = o.dnn;
         if (o.nn < 0) atomicAdd(&a.status[ST_NOCONV], 1);
+        if (a.hlim > 0.0 && !(h < a.hlim)) atomicOr(&a.status[ST_RANGE], 1);
     }
     if (threadIdx.x == 0) {
         if (c_restage) atomicAdd(&a.status[ST_RESTAGE], c_restage);
@@ -476,6 +478,12 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
     float *hmax_new = wsa<float>(c, "hmax_new", (size_t)cb);
     int32_t *st = c->d_status;
     Tree tr = make_tree(c);
+    // periodic: 2 h < box / 4 on every axis
+    double hlim = 0.0;
+    if (c->p.periodic) {
+        hlim = 1e300;
+        for (int k = 0; k < 3; ++k) hlim = fmin(hlim, 0.125 * (c->p.box_hi[k] - c->p.box_lo[k]));
+    }
     CandList pre;
     int rc0 = cand_pre(c, tr, false, 2.0 * (double)kSigma, &pre);
     if (rc0) return rc0;
@@ -495,6 +503,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;
+        a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
         hipLaunchKernelGGL(k_density<float>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
@@ -514,6 +523,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;
+        a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
         hipLaunchKernelGGL(k_density<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,

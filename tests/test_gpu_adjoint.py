@@ -93,7 +93,7 @@ CASES = [
     ("adiabatic", lambda: _cluster(343, 2, 400)),
     ("isothermal", lambda: _cluster(343, 0, 401)),
     ("locally_isothermal", lambda: _cluster(343, 1, 402, shift=1.3)),
-    ("periodic_mixed_mass", lambda: _periodic_box(8)),
+    ("periodic_mixed_mass", lambda: _periodic_box(12)),
 ]
 
 

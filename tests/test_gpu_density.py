@@ -3,9 +3,11 @@ particle id) on the same seeded inputs.  Tolerances: relative error of rho,
 h and Omega below 1e-5 for the FP64 form and 1e-3 for the FP32 form."""
 import numpy as np
 import pytest
+import torch
 
+import paper_2409_11470_amd as A
 import workloads as W
-from _gpu import gpu_density, oracle_density, sample_balls
+from _gpu import gpu_density, oracle_density, params_for, sample_balls
 
 pytestmark = pytest.mark.gpu
 
@@ -85,3 +87,20 @@ def test_tiny_sets(n):
     if conv.any():
         for k in ("h", "rho", "omega"):
             assert _rel(g[k][conv], o[k][conv]) < 1e-5, k
+
+
+def test_periodic_support_limit_reported():
+    # 4^3 particles in a periodic unit box: h = 0.3, so 2h exceeds a quarter of
+    # the box, where the minimum image of a cell pair no longer holds for its
+    # particle pairs; the density pass must report it
+    st, p = W.lattice_box(nside=4)
+    ctx = A.Context(params_for(p, "fp64"))
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_build_cells(ctx, ds)
+    n = ds.n
+    rho = torch.zeros(n, dtype=torch.float64, device="cuda")
+    om = torch.zeros_like(rho)
+    A.apr_density(ctx, ds, rho, om)
+    with pytest.raises(A.AprError) as e:
+        A.apr_sync_status(ctx)
+    assert e.value.code == A.APR_ERR_RANGE
