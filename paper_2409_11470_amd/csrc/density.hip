@@ -27,7 +27,7 @@ namespace apr {
 
 namespace {
 
-constexpr float kSigma = 1.1f;  // staged radius margin over 2 h_max
+constexpr float kSigma = 1.01f;  // staged radius margin over 2 h_max
 
 template <class T>
 struct StageCap;
@@ -110,31 +110,56 @@ struct DSum {
     }
 };
 
-// Stages the candidates with staged offset in [w0, w0 + STAGE) that are within
-// reach of some wavefront's targets: positions in the target cell's frame.
-// sB holds each candidate cell's first offset.
+// Candidate particle `lane` of candidate cell ci in the target cell's frame;
+// false for lanes beyond the cell's size or out of every wavefront's reach.
+template <class T>
+__device__ inline bool cand_point(const vec4_t<T> *pm, const MetaBuf<T> &mb, int ci, int lane,
+                                  const WaveBoxes<T> &B, vec4_t<T> &p)
+{
+    const CandMeta<T> x = mb.m[ci];
+    if (lane >= (int)mb.bn[ci]) return false;
+    p = pm[x.b0 + lane];
+    p.x = p.x + x.sx;
+    p.y = p.y + x.sy;
+    p.z = p.z + x.sz;
+    return wave_reach<T, false>(B, p.x, p.y, p.z, T(0));
+}
+
+// Counts, per candidate cell, the particles within reach of some
+// wavefront's targets (into sB).  Two cells per wavefront at a time, so that
+// two loads are in flight.
+template <class T>
+__device__ inline void count_cands(const vec4_t<T> *pm, const MetaBuf<T> &mb, int nc,
+                                   const WaveBoxes<T> &B, int32_t *sB)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    for (int ci = w; ci < nc; ci += 2 * kWaves) {
+        const int c1 = ci + kWaves;
+        vec4_t<T> p0, p1;
+        bool h0 = cand_point<T>(pm, mb, ci, lane, B, p0);
+        bool h1 = c1 < nc && cand_point<T>(pm, mb, c1, lane, B, p1);
+        uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+        if (lane == 0) {
+            sB[ci] = __popcll(m0);
+            if (c1 < nc) sB[c1] = __popcll(m1);
+        }
+    }
+}
+
+// Stages the counted candidates with staged offset in [w0, w0 + STAGE):
+// positions in the target cell's frame.  sB holds each candidate cell's
+// first offset.
 template <class T, int STAGE>
-__device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<T> *pm,
-                                    const int32_t *sA, const int32_t *sB, int nc, int total,
+__device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
+                                    const int32_t *sB, int nc, int total,
                                     const WaveBoxes<T> &B, int w0, vec4_t<T> *stg)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
     for (int ci = w; ci < nc; ci += kWaves) {
         int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
         if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
-        int cc = sA[ci];
-        int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-        double sh[3];
-        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-        bool hit = false;
         vec4_t<T> p;
-        if (lane < bn) {
-            p = pm[b0 + lane];
-            p.x = p.x + (T)sh[0];
-            p.y = p.y + (T)sh[1];
-            p.z = p.z + (T)sh[2];
-            hit = wave_reach<T, false>(B, p.x, p.y, p.z, T(0));
-        }
+        bool hit = cand_point<T>(pm, mb, ci, lane, B, p);
         uint64_t m = __ballot(hit);
         int off = o0 + __popcll(m & lanemask_lt()) - w0;
         if (hit && off >= 0 && off < STAGE) stg[off] = p;
@@ -148,7 +173,8 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     constexpr int STAGE = StageCap<T>::value;
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V stg[STAGE];
-    __shared__ uint16_t tls[kCell][kDTCap];
+    __shared__ ListsMeta<T, kDTCap> s_lm;  // per-target lists, or candidates' metadata
+    uint16_t(*tls)[kDTCap] = s_lm.tls;
     __shared__ uint16_t sub[kWaves][STAGE];
     __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
@@ -251,20 +277,9 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 nc = s_ncand;
                 last = s_more == 0;
                 if (!last) multi = true;
-                for (int ci = w; ci < nc; ci += kWaves) {
-                    int cc = sA[ci];
-                    int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                    double sh[3];
-                    cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-                    bool hit = false;
-                    if (lane < bn) {
-                        V p = a.pm[b0 + lane];
-                        hit = wave_reach<T, false>(s_wb, p.x + (T)sh[0], p.y + (T)sh[1],
-                                                   p.z + (T)sh[2], T(0));
-                    }
-                    uint64_t m = __ballot(hit);
-                    if (lane == 0) sB[ci] = __popcll(m);
-                }
+                load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
+                __syncthreads();
+                count_cands<T>(a.pm, s_lm.meta, nc, s_wb, sB);
                 __syncthreads();
                 if (w == 0) {
                     int tot = wave_excl_scan_lds(sB, nc);
@@ -278,7 +293,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
                 lists = false;
                 if (nwin == 1) {
-                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, s_wb, 0, stg);
+                    stage_window<T, STAGE>(a.pm, s_lm.meta, sB, nc, total, s_wb, 0, stg);
                     __syncthreads();
                 }
             }
@@ -287,8 +302,12 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 int w0 = win * STAGE;
                 int nstg = min(STAGE, total - w0);
                 if (nwin > 1) {
-                    __syncthreads();  // the previous window is no longer read
-                    stage_window<T, STAGE>(tr, tg, a.pm, sA, sB, nc, total, s_wb, w0, stg);
+                    // the previous window and its lists are no longer read; the
+                    // lists took the metadata's place
+                    __syncthreads();
+                    load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
+                    __syncthreads();
+                    stage_window<T, STAGE>(a.pm, s_lm.meta, sB, nc, total, s_wb, w0, stg);
                     __syncthreads();
                 }
                 if (!wave_busy) continue;

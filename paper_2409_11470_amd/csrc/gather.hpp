@@ -32,7 +32,9 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
     __shared__ int32_t sA[kCandCap], sB[kCandCap];
     __shared__ V stg[NS][STAGE];
     __shared__ uint16_t sub[kWaves][STAGE];
-    __shared__ uint16_t tls[kCell][kTCap];
+    __shared__ ListsMeta<T, kTCap> s_lm;  // per-target lists, or candidates' metadata
+    uint16_t(*tls)[kTCap] = s_lm.tls;
+    const MetaBuf<T> &mb = s_lm.meta;
     __shared__ int s_ncand, s_total, s_more, s_tlen[kCell];
     __shared__ Walk s_walk;
 
@@ -84,22 +86,28 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
         __syncthreads();
         const int nc = s_ncand;
         const bool more = s_more != 0;
-        // count the candidates b within max(R, 2 h_b) of the target cell box
-        for (int ci = w; ci < nc; ci += kWaves) {
-            int cc = sA[ci];
-            int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-            double sh[3];
-            cell_shift(tr.lev[0][cc], tg, tr.box, sh);
-            bool hit = false;
-            if (lane < bn) {
-                V p = op.load(0, b0 + lane);
-                T hb = op.load(1, b0 + lane).w;
-                T d2 = pt_box_d2<T>(p.x + (T)sh[0], p.y + (T)sh[1], p.z + (T)sh[2], T(0), T(0),
-                                    T(0), ex, ey, ez);
-                hit = d2 < R2c || d2 * hb * hb < T(4);
+        load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
+        __syncthreads();
+        // count the candidates b within max(R, 2 h_b) of the target cell box,
+        // two cells per wavefront at a time (four loads in flight)
+        auto near = [&](int ci, int ln) {
+            const CandMeta<T> x = mb.m[ci];
+            if (ln >= (int)mb.bn[ci]) return false;
+            V p = op.load(0, x.b0 + ln);
+            T hb = op.load(1, x.b0 + ln).w;
+            T d2 = pt_box_d2<T>(p.x + x.sx, p.y + x.sy, p.z + x.sz, T(0), T(0), T(0), ex, ey,
+                                ez);
+            return d2 < R2c || d2 * hb * hb < T(4);
+        };
+        for (int ci = w; ci < nc; ci += 2 * kWaves) {
+            const int c1 = ci + kWaves;
+            bool h0 = near(ci, lane);
+            bool h1 = c1 < nc && near(c1, lane);
+            uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+            if (lane == 0) {
+                sB[ci] = __popcll(m0);
+                if (c1 < nc) sB[c1] = __popcll(m1);
             }
-            uint64_t m = __ballot(hit);
-            if (lane == 0) sB[ci] = __popcll(m);
         }
         __syncthreads();
         if (w == 0) {
@@ -114,22 +122,26 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
         for (int win = 0; win < nwin && total > 0; ++win) {
             const int w0 = win * STAGE;
             const int nstg = min(STAGE, total - w0);
-            if (win > 0) __syncthreads();  // the previous window is no longer read
+            if (win > 0) {
+                // the previous window and its lists are no longer read; the
+                // lists took the metadata's place
+                __syncthreads();
+                load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
+                __syncthreads();
+            }
             for (int ci = w; ci < nc; ci += kWaves) {
                 int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
                 if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
-                int cc = sA[ci];
-                int32_t b0 = tr.cs[cc], bn = tr.cs[cc + 1] - b0;
-                double sh[3];
-                cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+                const CandMeta<T> x = mb.m[ci];
+                const int32_t b0 = x.b0, bn = mb.bn[ci];
                 bool hit = false;
                 V p, v;
                 if (lane < bn) {
                     p = op.load(0, b0 + lane);
                     v = op.load(1, b0 + lane);
-                    p.x = p.x + (T)sh[0];
-                    p.y = p.y + (T)sh[1];
-                    p.z = p.z + (T)sh[2];
+                    p.x = p.x + x.sx;
+                    p.y = p.y + x.sy;
+                    p.z = p.z + x.sz;
                     T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
                     hit = d2 < R2c || d2 * v.w * v.w < T(4);
                 }

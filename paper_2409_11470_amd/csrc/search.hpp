@@ -339,6 +339,51 @@ __device__ inline bool wave_reach(const WaveBoxes<T> &B, T x, T y, T z, T hb2)
     return hit;
 }
 
+// What staging needs of one candidate cell: its first particle, its size
+// (at most kCell) and the offset from its frame to the target cell's frame
+// (minimum image), read once for all candidates of a chunk so that the
+// counting and staging loops wait on one global load per cell, not three
+// chained ones.
+template <class T>
+struct CandMeta {
+    T sx, sy, sz;
+    int32_t b0;
+};
+template <class T>
+struct MetaBuf {
+    CandMeta<T> m[kCandCap];
+    uint8_t bn[kCandCap];
+};
+// The per-target lists and the candidates' metadata are never live at once
+// (metadata: from the walk to the end of staging; lists: from their build to
+// the next staging), so they share LDS.
+template <class T, int CAP>
+union ListsMeta {
+    uint16_t tls[kCell][CAP];
+    MetaBuf<T> meta;
+};
+
+// All threads of the workgroup fill mb for candidates [0, nc) of sA; the
+// caller synchronises before reading it.
+template <class T>
+__device__ inline void load_meta(const Tree &tr, const Geo &tg, const int32_t *sA, int nc,
+                                 MetaBuf<T> *mb)
+{
+    for (int ci = threadIdx.x; ci < nc; ci += kSearchThreads) {
+        int cc = sA[ci];
+        int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
+        double sh[3];
+        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+        CandMeta<T> x;
+        x.sx = (T)sh[0];
+        x.sy = (T)sh[1];
+        x.sz = (T)sh[2];
+        x.b0 = b0;
+        mb->m[ci] = x;
+        mb->bn[ci] = (uint8_t)(b1 - b0);
+    }
+}
+
 // Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
 template <class T>
 __device__ inline T wmax_groups(T v)
