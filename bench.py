@@ -56,7 +56,7 @@ FLOP_FORCE_PAIR = 59
 # with the digest of the kernel's sources at the time; reported only while the
 # sources are unchanged.
 MEASURED_TRAFFIC = {
-    "k_density<float>": dict(
+    "k_density<float, false>": dict(
         bytes_per_launch=27665844,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
@@ -339,10 +339,10 @@ def main():
     # roofline of the dominant kernel of the FP32 form (plain VALU arithmetic)
     n = r32["n"]
     if r32["density_ms"] >= r32["forces_ms"]:
-        kern, ms = "k_density<float>", r32["density_ms"]
+        kern, ms = "k_density<float, false>", r32["density_ms"]
         flops = FLOP_DENSITY_PAIR * (r32["density_pairs"] + n)
     else:
-        kern, ms = "k_forces<float>", r32["forces_ms"]
+        kern, ms = "k_forces<float, false>", r32["forces_ms"]
         flops = FLOP_FORCE_PAIR * r32["force_pairs"]
     achieved = flops / (ms * 1e-3) / 1e12
     traffic = measured_traffic(kern)

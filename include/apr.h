@@ -117,6 +117,14 @@ void apr_default_params(apr_params *p);
 int apr_ctx_create(apr_ctx **ctx, const apr_params *p, void *stream);
 int apr_ctx_destroy(apr_ctx *ctx);
 int apr_ctx_set_stream(apr_ctx *ctx, void *stream);
+
+/* Launch grid (workgroups, one target cell each) of the per-cell kernels from
+ * the next apr_build_cells on; 0 restores the default, the last cell count
+ * read back plus 1/8 and 64.  An implementation setting with no counterpart
+ * in the paper: results do not depend on it (cells beyond the grid are taken
+ * by a second, normally empty launch), so it serves tuning and tests.
+ * Returns APR_ERR_INVALID for grid < 0. */
+int apr_set_cell_grid(apr_ctx *ctx, int64_t grid);
 const char *apr_last_error(const apr_ctx *ctx);
 
 /* Sorts the particles into Morton order IN PLACE (all non-NULL state arrays

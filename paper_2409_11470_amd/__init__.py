@@ -12,7 +12,8 @@ from ._abi import (  # noqa: F401
     APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP, APR_PROF_CAND, AprError, lib, lib_path,
     Params, Zone, Sink, CState, apr_default_params)
 from .api import (  # noqa: F401
-    Context, DeviceState, apr_ctx_create, apr_ctx_destroy, apr_build_cells, apr_density,
+    Context, DeviceState, apr_ctx_create, apr_ctx_destroy, apr_set_cell_grid, apr_build_cells,
+    apr_density,
     apr_forces, apr_vjp, apr_neighbours, apr_split_merge, apr_step, apr_accel, apr_timestep,
     apr_sync_status, apr_profile_enable, apr_profile_read, apr_counters, make_params, make_zones,
     make_sinks)

@@ -72,6 +72,7 @@ def lib():
     L.apr_ctx_create.argtypes = [C.POINTER(_vp), C.POINTER(Params), _vp]
     L.apr_ctx_destroy.argtypes = [_vp]
     L.apr_ctx_set_stream.argtypes = [_vp, _vp]
+    L.apr_set_cell_grid.argtypes = [_vp, C.c_int64]
     L.apr_last_error.restype = C.c_char_p
     L.apr_last_error.argtypes = [_vp]
     L.apr_build_cells.argtypes = [_vp, C.POINTER(CState), _vp]
@@ -90,7 +91,8 @@ def lib():
     L.apr_profile_enable.argtypes = [_vp, C.c_int]
     L.apr_counters.argtypes = [_vp, _i64p, C.c_int]
     L.apr_profile_read.argtypes = [_vp, C.POINTER(C.c_double), _i64p, C.c_int]
-    for f in ("apr_ctx_create", "apr_ctx_destroy", "apr_ctx_set_stream", "apr_build_cells",
+    for f in ("apr_ctx_create", "apr_ctx_destroy", "apr_ctx_set_stream", "apr_set_cell_grid",
+              "apr_build_cells",
               "apr_density", "apr_forces", "apr_vjp", "apr_neighbours", "apr_split_merge", "apr_step",
               "apr_accel", "apr_timestep", "apr_sync_status", "apr_profile_enable",
               "apr_profile_read", "apr_counters"):

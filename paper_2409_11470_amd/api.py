@@ -182,6 +182,10 @@ def apr_ctx_destroy(ctx):
     ctx.close()
 
 
+def apr_set_cell_grid(ctx, grid):
+    ctx.check(lib().apr_set_cell_grid(ctx.ptr, int(grid)))
+
+
 def apr_build_cells(ctx, st, perm=None):
     cs = st.cstate()
     ctx.check(lib().apr_build_cells(ctx.ptr, C.byref(cs), _ptr(perm)))

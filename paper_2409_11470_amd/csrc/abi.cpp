@@ -151,13 +151,16 @@ int apr_ctx_create(apr_ctx **out, const apr_params *p, void *stream)
     if (hipMalloc(&c->d_status, sizeof(int32_t) * ST_WORDS) != hipSuccess ||
         hipHostMalloc(&c->h_status, sizeof(int32_t) * ST_WORDS, hipHostMallocDefault) !=
             hipSuccess ||
+        hipHostMalloc(&c->count_pin, sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
         hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * ST_WORDS, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         if (c->d_status) (void)hipFree(c->d_status);
         if (c->h_status) (void)hipHostFree(c->h_status);
+        if (c->count_pin) (void)hipHostFree(c->count_pin);
         delete c;
         return APR_ERR_HIP;
     }
+    *c->count_pin = 0;  // no build has written a count yet
     *out = c;
     return APR_OK;
 }
@@ -175,6 +178,7 @@ int apr_ctx_destroy(apr_ctx *c)
         }
     if (c->d_status) (void)hipFree(c->d_status);
     if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->count_pin) (void)hipHostFree(c->count_pin);
     delete c;
     return APR_OK;
 }
@@ -183,6 +187,14 @@ int apr_ctx_set_stream(apr_ctx *c, void *stream)
 {
     if (!c) return APR_ERR_INVALID;
     c->stream = (hipStream_t)stream;
+    return APR_OK;
+}
+
+int apr_set_cell_grid(apr_ctx *c, int64_t grid)
+{
+    if (!c) return APR_ERR_INVALID;
+    if (grid < 0) return fail(c, APR_ERR_INVALID, "cell grid must be >= 0");
+    c->grid_set = grid;
     return APR_OK;
 }
 

@@ -191,18 +191,20 @@ struct DensVJP {
     }
 };
 
-template <class T>
+template <class T, bool REST>
 __global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<T> op,
-                                                              CandList pre, int32_t *status)
+                                                              CandList pre, int32_t *status,
+                                                              int64_t first)
 {
-    gather_pairs<T, ForceVJP<T>, VJPStage<T>::force>(tr, op, pre, status, -1);
+    gather_pairs<T, ForceVJP<T>, VJPStage<T>::force, REST>(tr, op, pre, status, -1, first);
 }
 
-template <class T>
+template <class T, bool REST>
 __global__ __launch_bounds__(kSearchThreads) void k_vjp_dens(Tree tr, DensVJP<T> op,
-                                                             CandList pre, int32_t *status)
+                                                             CandList pre, int32_t *status,
+                                                             int64_t first)
 {
-    gather_pairs<T, DensVJP<T>, VJPStage<T>::dens>(tr, op, pre, status, -1);
+    gather_pairs<T, DensVJP<T>, VJPStage<T>::dens, REST>(tr, op, pre, status, -1, first);
 }
 
 template <class T>
@@ -312,7 +314,7 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
           const void *dudt_bar, void *xbar, void *ybar, void *zbar, void *mbar)
 {
     using V = vec4_t<T>;
-    int64_t n = s->n, cb = c->cells_bound;
+    const int64_t n = s->n, grid = c->node_grid[0];
     const apr_params &p = c->p;
     bool has_force = ax_bar || ay_bar || az_bar || dudt_bar;
     int rc = cells_hmax_from(c, s->h, n);
@@ -348,8 +350,10 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
         op.alpha = (T)p.av_alpha;
         op.beta = (T)p.av_beta;
         for (int k = 0; k < 9; ++k) op.out[k] = fout[k];
-        hipLaunchKernelGGL(k_vjp_force<T>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, pre, c->d_status);
+        hipLaunchKernelGGL((k_vjp_force<T, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+                           c->stream, tr, op, pre, c->d_status, (int64_t)0);
+        hipLaunchKernelGGL((k_vjp_force<T, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                           c->stream, tr, op, pre, c->d_status, grid);
         APR_LAUNCHED(c);
     }
     FPtrs<T> fp;
@@ -388,8 +392,10 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     dop.xbar[1] = (T *)ybar;
     dop.xbar[2] = (T *)zbar;
     dop.mbar = (T *)mbar;
-    hipLaunchKernelGGL(k_vjp_dens<T>, dim3((unsigned)cb), dim3(kSearchThreads), 0, c->stream,
-                       tr, dop, pre, c->d_status);
+    hipLaunchKernelGGL((k_vjp_dens<T, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+                       c->stream, tr, dop, pre, c->d_status, (int64_t)0);
+    hipLaunchKernelGGL((k_vjp_dens<T, true>), dim3(kRestGrid), dim3(kSearchThreads), 0, c->stream,
+                       tr, dop, pre, c->d_status, grid);
     APR_LAUNCHED(c);
     return APR_OK;
 }

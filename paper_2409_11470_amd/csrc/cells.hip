@@ -153,10 +153,13 @@ __global__ __launch_bounds__(kTileThreads) void k_leaf_flags(const uint32_t *key
 }
 
 // One workgroup: exclusive scan of v[0..nb) in place, with operator max
-// (identity -1) or +; the total goes to *total when given.
+// (identity -1) or +; the total goes to *total when given, and with the
+// build number `no` to the pinned host word *pin when given (one 64-bit
+// store, so the host never reads a count with another build's number).
 template <bool MAX>
 __global__ __launch_bounds__(kTileThreads) void k_scan_blocks(int32_t *v, int64_t nb,
-                                                              int32_t *total)
+                                                              int32_t *total, uint64_t *pin,
+                                                              uint32_t no)
 {
     __shared__ int32_t red[kTileThreads / kWave + 1];
     const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
@@ -192,6 +195,9 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_blocks(int32_t *v, int64_
         ex = op(ex, x);
     }
     if (t == 0 && total) *total = red[kTileThreads / kWave];
+    if (t == 0 && pin)
+        __hip_atomic_store(pin, ((uint64_t)no << 32) | (uint32_t)red[kTileThreads / kWave],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Cell starts inside leaves: every 64 particles from the leaf's first.  The
@@ -351,6 +357,13 @@ __device__ inline T wave_max(T v)
     return v;
 }
 
+// Per-node kernels take one wavefront per item (4 per workgroup) and stride
+// over the count the device holds, so any launch grid is correct.
+#define APR_FOR_WAVE_ITEMS(j, count)                                                   \
+    for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave, \
+                 j##_end = (count), j##_step = (int64_t)gridDim.x * (blockDim.x / kWave); \
+         j < j##_end; j += j##_step)
+
 // One wavefront per cell: bounding box, centre, rounded-up half extents and
 // h_max; per particle the position relative to the cell centre and the
 // normalised mass 2^-level, in the precision of the pair arithmetic.
@@ -359,95 +372,100 @@ __global__ __launch_bounds__(256) void k_cell_geo(const Hdr *hdr, const int32_t 
                                                   const double *x, const double *y,
                                                   const double *z, const double *h,
                                                   const int8_t *level, Geo *cells,
-                                                  vec4_t<T> *pm, int64_t bound)
+                                                  vec4_t<T> *pm)
 {
-    int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= bound || c >= hdr->ncells) return;
-    int lane = lane_id();
-    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
-    int64_t i = s0 + lane;
-    bool in = i < s1;
-    double px = in ? x[i] : 0.0, py = in ? y[i] : 0.0, pz = in ? z[i] : 0.0;
-    double ph = in ? h[i] : 0.0;
-    double inf = __builtin_huge_val();
-    double lx = wave_min(in ? px : inf), ly = wave_min(in ? py : inf), lz = wave_min(in ? pz : inf);
-    double ux = wave_max(in ? px : -inf), uy = wave_max(in ? py : -inf),
-           uz = wave_max(in ? pz : -inf);
-    double hm = wave_max(ph);
-    double cx = 0.5 * (lx + ux), cy = 0.5 * (ly + uy), cz = 0.5 * (lz + uz);
-    if (lane == 0) {
-        Geo g;
-        g.cx = cx; g.cy = cy; g.cz = cz;
-        g.ex = f_up(fmax(ux - cx, cx - lx));
-        g.ey = f_up(fmax(uy - cy, cy - ly));
-        g.ez = f_up(fmax(uz - cz, cz - lz));
-        g.hmax = f_up(hm);
-        cells[c] = g;
-    }
-    if (in) {
-        vec4_t<T> v;
-        v.x = (T)(px - cx);
-        v.y = (T)(py - cy);
-        v.z = (T)(pz - cz);
-        v.w = (T)ldexp(1.0, -(int)level[i]);
-        pm[i] = v;
+    const int lane = lane_id();
+    APR_FOR_WAVE_ITEMS(c, hdr->ncells)
+    {
+        int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+        int64_t i = s0 + lane;
+        bool in = i < s1;
+        double px = in ? x[i] : 0.0, py = in ? y[i] : 0.0, pz = in ? z[i] : 0.0;
+        double ph = in ? h[i] : 0.0;
+        double inf = __builtin_huge_val();
+        double lx = wave_min(in ? px : inf), ly = wave_min(in ? py : inf),
+               lz = wave_min(in ? pz : inf);
+        double ux = wave_max(in ? px : -inf), uy = wave_max(in ? py : -inf),
+               uz = wave_max(in ? pz : -inf);
+        double hm = wave_max(ph);
+        double cx = 0.5 * (lx + ux), cy = 0.5 * (ly + uy), cz = 0.5 * (lz + uz);
+        if (lane == 0) {
+            Geo g;
+            g.cx = cx; g.cy = cy; g.cz = cz;
+            g.ex = f_up(fmax(ux - cx, cx - lx));
+            g.ey = f_up(fmax(uy - cy, cy - ly));
+            g.ez = f_up(fmax(uz - cz, cz - lz));
+            g.hmax = f_up(hm);
+            cells[c] = g;
+        }
+        if (in) {
+            vec4_t<T> v;
+            v.x = (T)(px - cx);
+            v.y = (T)(py - cy);
+            v.z = (T)(pz - cz);
+            v.w = (T)ldexp(1.0, -(int)level[i]);
+            pm[i] = v;
+        }
     }
 }
 
 // One wavefront per node: union of its (up to) 64 children.
 __global__ __launch_bounds__(256) void k_tree_level(const Hdr *hdr, int lev, const Geo *child,
-                                                    Geo *node, int64_t bound)
+                                                    Geo *node)
 {
-    int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (j >= bound || j >= hdr->nnode[lev]) return;
-    int lane = lane_id();
-    int64_t k = j * kFan + lane;
-    bool in = k < hdr->nnode[lev - 1];
-    double inf = __builtin_huge_val();
-    Geo g;
-    if (in) g = child[k];
-    double lx = wave_min(in ? g.cx - (double)g.ex : inf);
-    double ly = wave_min(in ? g.cy - (double)g.ey : inf);
-    double lz = wave_min(in ? g.cz - (double)g.ez : inf);
-    double ux = wave_max(in ? g.cx + (double)g.ex : -inf);
-    double uy = wave_max(in ? g.cy + (double)g.ey : -inf);
-    double uz = wave_max(in ? g.cz + (double)g.ez : -inf);
-    float hm = wave_max(in ? g.hmax : 0.0f);
-    if (lane == 0) {
-        Geo o;
-        o.cx = 0.5 * (lx + ux); o.cy = 0.5 * (ly + uy); o.cz = 0.5 * (lz + uz);
-        o.ex = f_up(fmax(ux - o.cx, o.cx - lx));
-        o.ey = f_up(fmax(uy - o.cy, o.cy - ly));
-        o.ez = f_up(fmax(uz - o.cz, o.cz - lz));
-        o.hmax = hm;
-        node[j] = o;
+    const int lane = lane_id();
+    APR_FOR_WAVE_ITEMS(j, hdr->nnode[lev])
+    {
+        int64_t k = j * kFan + lane;
+        bool in = k < hdr->nnode[lev - 1];
+        double inf = __builtin_huge_val();
+        Geo g;
+        if (in) g = child[k];
+        double lx = wave_min(in ? g.cx - (double)g.ex : inf);
+        double ly = wave_min(in ? g.cy - (double)g.ey : inf);
+        double lz = wave_min(in ? g.cz - (double)g.ez : inf);
+        double ux = wave_max(in ? g.cx + (double)g.ex : -inf);
+        double uy = wave_max(in ? g.cy + (double)g.ey : -inf);
+        double uz = wave_max(in ? g.cz + (double)g.ez : -inf);
+        float hm = wave_max(in ? g.hmax : 0.0f);
+        if (lane == 0) {
+            Geo o;
+            o.cx = 0.5 * (lx + ux); o.cy = 0.5 * (ly + uy); o.cz = 0.5 * (lz + uz);
+            o.ex = f_up(fmax(ux - o.cx, o.cx - lx));
+            o.ey = f_up(fmax(uy - o.cy, o.cy - ly));
+            o.ez = f_up(fmax(uz - o.cz, o.cz - lz));
+            o.hmax = hm;
+            node[j] = o;
+        }
     }
 }
 
 // hmax of tree nodes only (boxes unchanged).
 __global__ __launch_bounds__(256) void k_tree_hmax(const Hdr *hdr, int lev, const Geo *child,
-                                                   Geo *node, int64_t bound)
+                                                   Geo *node)
 {
-    int64_t j = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (j >= bound || j >= hdr->nnode[lev]) return;
-    int lane = lane_id();
-    int64_t k = j * kFan + lane;
-    bool in = k < hdr->nnode[lev - 1];
-    float hm = wave_max(in ? child[k].hmax : 0.0f);
-    if (lane == 0) node[j].hmax = hm;
+    const int lane = lane_id();
+    APR_FOR_WAVE_ITEMS(j, hdr->nnode[lev])
+    {
+        int64_t k = j * kFan + lane;
+        bool in = k < hdr->nnode[lev - 1];
+        float hm = wave_max(in ? child[k].hmax : 0.0f);
+        if (lane == 0) node[j].hmax = hm;
+    }
 }
 
 // Cells' hmax from a given h array.
 __global__ __launch_bounds__(256) void k_cell_hmax(const Hdr *hdr, const int32_t *cell_start,
-                                                   const double *h, Geo *cells, int64_t bound)
+                                                   const double *h, Geo *cells)
 {
-    int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= bound || c >= hdr->ncells) return;
-    int lane = lane_id();
-    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
-    int64_t i = s0 + lane;
-    double hm = wave_max(i < s1 ? h[i] : 0.0);
-    if (lane == 0) cells[c].hmax = f_up(hm);
+    const int lane = lane_id();
+    APR_FOR_WAVE_ITEMS(c, hdr->ncells)
+    {
+        int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+        int64_t i = s0 + lane;
+        double hm = wave_max(i < s1 ? h[i] : 0.0);
+        if (lane == 0) cells[c].hmax = f_up(hm);
+    }
 }
 
 }  // namespace
@@ -455,23 +473,21 @@ __global__ __launch_bounds__(256) void k_cell_hmax(const Hdr *hdr, const int32_t
 const Hdr *cell_hdr(apr_ctx *c) { return wsa<Hdr>(c, "cell_hdr", 1); }
 const int32_t *cell_start(apr_ctx *c)
 {
-    return wsa<int32_t>(c, "cell_start", (size_t)c->cells_bound + 1);
+    return wsa<int32_t>(c, "cell_start", (size_t)c->node_cap[0] + 1);
 }
 Geo *cell_level(apr_ctx *c, int lev)
 {
     static const char *names[kMaxLev + 1] = {"geo0", "geo1", "geo2", "geo3", "geo4", "geo5",
                                              "geo6"};
-    return wsa<Geo>(c, names[lev], (size_t)c->nnode_bound[lev] + 1);
+    return wsa<Geo>(c, names[lev], (size_t)c->node_cap[lev] + 1);
 }
 
 int refit_hmax_from_cells(apr_ctx *c)
 {
     Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
-    for (int k = 1; k <= c->nlev; ++k) {
-        int64_t b = c->nnode_bound[k];
-        hipLaunchKernelGGL(k_tree_hmax, dim3((unsigned)ceil_div(b, 4)), dim3(256), 0,
-                           c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k), b);
-    }
+    for (int k = 1; k <= c->nlev; ++k)
+        hipLaunchKernelGGL(k_tree_hmax, dim3((unsigned)ceil_div(c->node_grid[k], 4)), dim3(256),
+                           0, c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k));
     APR_LAUNCHED(c);
     return APR_OK;
 }
@@ -480,9 +496,8 @@ int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
 {
     if (c->cells_n != n) return fail(c, APR_ERR_INVALID, "cells not built for this state");
     Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
-    int64_t b = c->cells_bound;
-    hipLaunchKernelGGL(k_cell_hmax, dim3((unsigned)ceil_div(b, 4)), dim3(256), 0, c->stream,
-                       hdr, cell_start(c), h, cell_level(c, 0), b);
+    hipLaunchKernelGGL(k_cell_hmax, dim3((unsigned)ceil_div(c->node_grid[0], 4)), dim3(256), 0,
+                       c->stream, hdr, cell_start(c), h, cell_level(c, 0));
     APR_LAUNCHED(c);
     return refit_hmax_from_cells(c);
 }
@@ -505,6 +520,23 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     if (n >= (int64_t)1 << 31) return fail(c, APR_ERR_INVALID, "too many particles");
     Box b = make_box(c->p);
     int seglev = c->p.periodic ? 2 : 3;
+    // The cell count only sizes launch grids (the per-cell kernels take the
+    // count on the device): use the newest count an earlier build has written
+    // to the pinned word, scaled to n.
+    {
+        uint64_t v = __atomic_load_n(c->count_pin, __ATOMIC_ACQUIRE);
+        uint32_t no = (uint32_t)(v >> 32);
+        if (no != 0 && no > c->count_no && c->build_no - no < 16) {
+            c->count_no = no;
+            c->count_last = (int64_t)(uint32_t)v;
+            c->count_last_n = c->build_n[no % 16];
+        }
+    }
+    const uint32_t no = ++c->build_no;
+    c->build_n[no % 16] = n;
+    int64_t est = c->count_last > 0 && c->count_last_n > 0
+                      ? std::max<int64_t>(1, c->count_last * n / c->count_last_n)
+                      : 0;
 
     uint32_t *keys = wsa<uint32_t>(c, "mkeys", (size_t)n);
     uint32_t *vals = wsa<uint32_t>(c, "mvals", (size_t)n);
@@ -554,30 +586,41 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     hipLaunchKernelGGL(k_leaf_flags, dim3(gt), dim3(kTileThreads), 0, c->stream, keys, n, seglev,
                        lflag, blast);
     hipLaunchKernelGGL(k_scan_blocks<true>, dim3(1), dim3(kTileThreads), 0, c->stream, blast, nt,
-                       (int32_t *)nullptr);
+                       (int32_t *)nullptr, (uint64_t *)nullptr, 0u);
     hipLaunchKernelGGL(k_cell_flags, dim3(gt), dim3(kTileThreads), 0, c->stream, lflag, blast, n,
                        cflag, bsum);
     hipLaunchKernelGGL(k_scan_blocks<false>, dim3(1), dim3(kTileThreads), 0, c->stream, bsum, nt,
-                       tot);
+                       tot, c->count_pin, no);
     APR_LAUNCHED(c);
-    // the cell count sizes every search launch: read it back once per build
-    int32_t ncell_h = 0;
-    APR_HIP(c, hipMemcpyAsync(&ncell_h, tot, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    APR_HIP(c, hipStreamSynchronize(c->stream));
-    int64_t cb = (int64_t)ncell_h;
-    if (cb < 1 || cb > n) return fail(c, APR_ERR_HIP, "cell count out of range");
-    c->cells_bound = cb;
+    // the first build of a context waits for its count
+    if (est <= 0) {
+        APR_HIP(c, hipStreamSynchronize(c->stream));
+        uint64_t v = __atomic_load_n(c->count_pin, __ATOMIC_ACQUIRE);
+        est = (int64_t)(uint32_t)v;
+        if ((uint32_t)(v >> 32) != no || est < 1 || est > n)
+            return fail(c, APR_ERR_HIP, "cell count out of range");
+        c->count_no = no;
+        c->count_last = est;
+        c->count_last_n = n;
+    }
+    // buffers: at most one cell per particle; grids: the estimate with a margin.
+    // Levels: enough for n cells, so the top level never has more than kFan
+    // nodes (with fewer cells the upper levels hold a single node).
+    int64_t grid = c->grid_set > 0 ? c->grid_set : std::min<int64_t>(n, est + est / 8 + 64);
     int nlev = 0;
-    int64_t m = cb;
-    c->nnode_bound[0] = cb;
+    int64_t m = n;
+    c->node_cap[0] = n;
+    c->node_grid[0] = grid;
     while (m > kFan) {
         m = ceil_div(m, kFan);
+        grid = ceil_div(grid, kFan);
         nlev += 1;
-        c->nnode_bound[nlev] = m;
+        c->node_cap[nlev] = m;
+        c->node_grid[nlev] = grid;
     }
-    if (nlev > kMaxLev) return fail(c, APR_ERR_INVALID, "too many cells");
+    if (nlev > kMaxLev) return fail(c, APR_ERR_INVALID, "too many particles for the tree");
     c->nlev = nlev;
-    int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)cb + 1);
+    int32_t *cs = wsa<int32_t>(c, "cell_start", (size_t)c->node_cap[0] + 1);
     if (!cs) return fail(c, APR_ERR_HIP, "cell workspace");
     hipLaunchKernelGGL(k_cell_start, dim3(gt), dim3(kTileThreads), 0, c->stream, cflag, bsum, n,
                        cs, hdr, nlev);
@@ -586,19 +629,19 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     Geo *cells = cell_level(c, 0);
     if (c->p.precision == APR_FP32) {
         float4 *pm = wsa<float4>(c, "pm32", (size_t)n);
-        hipLaunchKernelGGL(k_cell_geo<float>, dim3((unsigned)ceil_div(cb, 4)), dim3(256), 0,
-                           c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level, cells, pm, cb);
+        hipLaunchKernelGGL(k_cell_geo<float>, dim3((unsigned)ceil_div(c->node_grid[0], 4)),
+                           dim3(256), 0, c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level,
+                           cells, pm);
     } else {
         double4 *pm = wsa<double4>(c, "pm64", (size_t)n);
-        hipLaunchKernelGGL(k_cell_geo<double>, dim3((unsigned)ceil_div(cb, 4)), dim3(256), 0,
-                           c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level, cells, pm, cb);
+        hipLaunchKernelGGL(k_cell_geo<double>, dim3((unsigned)ceil_div(c->node_grid[0], 4)),
+                           dim3(256), 0, c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level,
+                           cells, pm);
     }
     APR_LAUNCHED(c);
-    for (int k = 1; k <= nlev; ++k) {
-        int64_t bk = c->nnode_bound[k];
-        hipLaunchKernelGGL(k_tree_level, dim3((unsigned)ceil_div(bk, 4)), dim3(256), 0,
-                           c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k), bk);
-    }
+    for (int k = 1; k <= nlev; ++k)
+        hipLaunchKernelGGL(k_tree_level, dim3((unsigned)ceil_div(c->node_grid[k], 4)), dim3(256),
+                           0, c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k));
     APR_LAUNCHED(c);
     c->cells_n = n;
     c->dens_n = -1;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -68,11 +69,22 @@ struct apr_ctx {
     std::vector<Buf> bufs;
     int32_t *d_status = nullptr;   // apr::ST_WORDS ints
     int32_t *h_status = nullptr;   // pinned host copy
-    // cell structure of the last apr_build_cells
+    // cell structure of the last apr_build_cells.  The cell count lives on
+    // the device (Hdr); per-cell kernels stride over it, so their launch
+    // grids may be any size: the host sizes them from the last count it read
+    // back (asynchronously, into pinned memory) and sizes buffers by bounds
+    // that always hold (at most one cell per particle).
     int64_t cells_n = -1;          // particles it was built for
-    int64_t cells_bound = 0;       // upper bound on the cell count
-    int nlev = 0;                  // tree levels above the cells
-    int64_t nnode_bound[apr::kMaxLev + 1] = {};
+    int nlev = 0;                  // tree levels above the cells (enough for n cells)
+    int64_t node_cap[apr::kMaxLev + 1] = {};   // buffer bound per level (level 0: cells)
+    int64_t node_grid[apr::kMaxLev + 1] = {};  // launch grid per level
+    uint64_t *count_pin = nullptr; // pinned host word: (build number << 32) | cell count,
+                                   // written by the cell build's last scan kernel
+    uint32_t build_no = 0;         // builds so far
+    uint32_t count_no = 0;         // build number of count_last
+    int64_t build_n[16] = {};      // particles of the last 16 builds (by number % 16)
+    int64_t count_last = 0, count_last_n = 0;  // last count read, and its n
+    int64_t grid_set = 0;          // apr_set_cell_grid (0: from the count)
     // derived values of the last density / force evaluation (workspace)
     int64_t dens_n = -1;           // n of the last apr_density (for the split cap)
     int64_t force_n = -1;          // n of the last force evaluation (for the timestep)
@@ -141,6 +153,16 @@ __device__ inline int64_t xcd_swizzle(int64_t b, int64_t nb)
     // XCDs 0..full-1 own `per` items, the rest own per-1
     int64_t base = x < full ? x * per : full * per + (x - full) * (per - 1);
     return base + r;
+}
+
+// First cell of workgroup b of a per-cell kernel launched with grid G over nc
+// cells: cells [0, min(nc, G)) go to the XCDs in contiguous ranges (blocks
+// are dealt to the XCDs in turn), so a grid larger than the count leaves the
+// XCDs balanced; -1 if b has no cell.  Cells from G on are the caller's.
+__device__ inline int64_t first_cell(int64_t b, int64_t G, int64_t nc)
+{
+    const int64_t m = nc < G ? nc : G;
+    return b < m ? xcd_swizzle(b, m) : -1;
 }
 
 // Minimum-image component of a displacement (periodic box of side L).

@@ -167,7 +167,7 @@ __device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
 }
 
 template <class T>
-__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(DensArgs<T> a)
+__device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t cell)
 {
     using V = vec4_t<T>;
     constexpr int STAGE = StageCap<T>::value;
@@ -190,8 +190,6 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     __shared__ Out s_out[kCell];
 
     const Tree &tr = a.tree;
-    int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
-    if (cell >= tr.hdr->ncells) return;
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
@@ -246,7 +244,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
         const bool walking = search || multi;
         // the first search can take the candidates walked ahead of this kernel
         int pre_n = -1;
-        if (pass == 0 && a.pre.ncand && R <= a.pre.rfac * (double)tg.hmax)
+        if (pass == 0 && a.pre.ncand && cell < a.pre.cap && R <= a.pre.rfac * (double)tg.hmax)
             pre_n = a.pre.ncand[cell];
         const bool use_pre = walking && pre_n >= 0;
         if (walking && !use_pre) {
@@ -338,8 +336,16 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
                 T hinv = T(1) / hf;
                 T R2 = T(4) * hf * hf;
                 if (tlen <= kDTCap) {
-                    for (int k = j; k < tlen; k += kLanes) {
-                        V p = stg[mylist[k]];
+                    // two entries per step (same order per lane), both reads in flight
+                    int k = j;
+                    for (; k + kLanes < tlen; k += 2 * kLanes) {
+                        const int e0 = mylist[k], e1 = mylist[k + kLanes];
+                        const V p0 = lds_ld4<T>(&stg[e0]), p1 = lds_ld4<T>(&stg[e1]);
+                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2, hinv);
+                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2, hinv);
+                    }
+                    if (k < tlen) {
+                        const V p = lds_ld4<T>(&stg[mylist[k]]);
                         S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
                     }
                 } else {
@@ -468,12 +474,31 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     }
 }
 
-__global__ void k_set_cell_hmax(const Hdr *hdr, const float *hmax_new, Geo *cells,
-                                int64_t bound)
+// One workgroup per target cell, cells [0, grid) with the grid from the
+// host's estimate of the cell count; a second launch (REST) strides over any
+// cells from `first` on, nearly always none.  Two kernels rather than one
+// loop: a loop around the search body costs it registers.
+template <class T, bool REST>
+__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(DensArgs<T> a,
+                                                                              int64_t first)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= bound || c >= hdr->ncells) return;
-    cells[c].hmax = hmax_new[c];
+    const int64_t nc = a.tree.hdr->ncells;
+    if (!REST) {
+        const int64_t cell = first_cell(blockIdx.x, gridDim.x, nc);
+        if (cell >= 0) density_cell<T>(a, cell);
+        return;
+    }
+    for (int64_t cell = first + blockIdx.x; cell < nc; cell += gridDim.x) {
+        density_cell<T>(a, cell);
+        __syncthreads();  // the next cell reuses the LDS
+    }
+}
+
+__global__ void k_set_cell_hmax(const Hdr *hdr, const float *hmax_new, Geo *cells)
+{
+    const int64_t nc = hdr->ncells, step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += step)
+        cells[c].hmax = hmax_new[c];
 }
 
 }  // namespace
@@ -493,8 +518,8 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
 {
     if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "apr_build_cells first");
     if (!rho || !omega) return fail(c, APR_ERR_INVALID, "rho and omega are required");
-    int64_t cb = c->cells_bound;
-    float *hmax_new = wsa<float>(c, "hmax_new", (size_t)cb);
+    const int64_t grid = c->node_grid[0];
+    float *hmax_new = wsa<float>(c, "hmax_new", (size_t)c->node_cap[0]);
     int32_t *st = c->d_status;
     Tree tr = make_tree(c);
     // periodic: 2 h < box / 4 on every axis
@@ -525,8 +550,11 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
-        hipLaunchKernelGGL(k_density<float>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, a);
+        hipLaunchKernelGGL((k_density<float, false>), dim3((unsigned)grid), dim3(kSearchThreads),
+                           0, c->stream, a, (int64_t)0);
+        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
+        hipLaunchKernelGGL((k_density<float, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                           c->stream, a, grid);
     } else {
         DensArgs<double> a;
         a.tree = tr;
@@ -545,13 +573,15 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
-        hipLaunchKernelGGL(k_density<double>, dim3((unsigned)cb), dim3(kSearchThreads), 0,
-                           c->stream, a);
+        hipLaunchKernelGGL((k_density<double, false>), dim3((unsigned)grid), dim3(kSearchThreads),
+                           0, c->stream, a, (int64_t)0);
+        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
+        hipLaunchKernelGGL((k_density<double, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                           c->stream, a, grid);
     }
-    prof_end(c, tok);
     APR_LAUNCHED(c);
-    hipLaunchKernelGGL(k_set_cell_hmax, dim3((unsigned)ceil_div(cb, 256)), dim3(256), 0,
-                       c->stream, cell_hdr(c), hmax_new, cell_level(c, 0), cb);
+    hipLaunchKernelGGL(k_set_cell_hmax, dim3((unsigned)ceil_div(grid, 256)), dim3(256), 0,
+                       c->stream, cell_hdr(c), hmax_new, cell_level(c, 0));
     APR_LAUNCHED(c);
     int rc = refit_hmax_from_cells(c);
     if (rc) return rc;

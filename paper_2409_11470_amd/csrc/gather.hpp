@@ -24,8 +24,8 @@
 namespace apr {
 
 template <class T, class OP, int STAGE>
-__device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, int32_t *status,
-                             int st_word)
+__device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const CandList &pre,
+                                            const int64_t cell, int32_t *status, int st_word)
 {
     using V = vec4_t<T>;
     constexpr int NS = OP::NS;
@@ -38,8 +38,6 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
     __shared__ int s_ncand, s_total, s_more, s_tlen[kCell];
     __shared__ Walk s_walk;
 
-    int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
-    if (cell >= tr.hdr->ncells) return;
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
@@ -64,7 +62,7 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
 
     bool multiwin = false;  // counted once at the end (no global atomics in the loop)
     // candidates walked ahead of this kernel (same radius), else walk here
-    const int pre_n = (pre.ncand && pre.rfac == 2.0) ? pre.ncand[cell] : -1;
+    const int pre_n = (pre.ncand && pre.rfac == 2.0 && cell < pre.cap) ? pre.ncand[cell] : -1;
     if (pre_n < 0 && w == 0) walk_init(tr, tg, R, true, &s_walk);
     for (int chunk = 0;; ++chunk) {
         // ---- next chunk of candidate cells
@@ -198,6 +196,26 @@ __device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, 
     }
     op.finish(acc, s0 + t, own, valid && j == 0);
     if (threadIdx.x == 0 && multiwin && st_word >= 0) atomicAdd(&status[st_word], 1);
+}
+
+// One workgroup per target cell, cells [0, grid) with the grid from the
+// host's estimate of the cell count; the REST launch strides over any cells
+// from `first` on, nearly always none (a loop around the search body costs it
+// registers, hence two kernels).
+template <class T, class OP, int STAGE, bool REST>
+__device__ void gather_pairs(const Tree &tr, const OP &op, const CandList &pre, int32_t *status,
+                             int st_word, int64_t first)
+{
+    const int64_t nc = tr.hdr->ncells;
+    if (!REST) {
+        const int64_t cell = first_cell(blockIdx.x, gridDim.x, nc);
+        if (cell >= 0) gather_cell<T, OP, STAGE>(tr, op, pre, cell, status, st_word);
+        return;
+    }
+    for (int64_t cell = first + blockIdx.x; cell < nc; cell += gridDim.x) {
+        gather_cell<T, OP, STAGE>(tr, op, pre, cell, status, st_word);
+        __syncthreads();  // the next cell reuses the LDS
+    }
 }
 
 }  // namespace apr

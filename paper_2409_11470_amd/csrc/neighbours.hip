@@ -37,7 +37,8 @@ __device__ inline bool is_neighbour(double xa, double ya, double za, double ha, 
     return in;
 }
 
-// one wavefront per target cell; lane = target
+// one wavefront per target cell (striding over the device's cell count);
+// lane = target
 __global__ __launch_bounds__(64) void k_neigh(Tree tr, const double *x, const double *y,
                                               const double *z, const double *h, int mode,
                                               int64_t *counts, const int64_t *offsets,
@@ -45,36 +46,40 @@ __global__ __launch_bounds__(64) void k_neigh(Tree tr, const double *x, const do
 {
     __shared__ int32_t sA[kCandCap];
     __shared__ Walk s_walk;
-    int64_t cell = xcd_swizzle(blockIdx.x, gridDim.x);
-    if (cell >= tr.hdr->ncells) return;
-    const Geo tg = tr.lev[0][cell];
-    int lane = lane_id();
-    int32_t s0 = tr.cs[cell], s1 = tr.cs[cell + 1];
-    int64_t a = s0 + lane;
-    bool valid = a < s1;
-    double xa = valid ? x[a] : 0.0, ya = valid ? y[a] : 0.0, za = valid ? z[a] : 0.0;
-    double ha = valid ? h[a] : 0.0;
-    int64_t k = 0;
-    int64_t off = (list && valid) ? offsets[a] : 0;
-    const double R = 2.0 * (double)tg.hmax;
-    walk_init(tr, tg, R, mode == 1, &s_walk);
-    for (;;) {
-        int nc = walk_next(tr, tg, R, mode == 1, &s_walk, sA, kCandCap);
-        for (int ci = 0; ci < nc; ++ci) {
-            int cc = sA[ci];
-            int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
-            for (int32_t b = b0; b < b1; ++b) {
-                double xb = x[b], yb = y[b], zb = z[b], hb = h[b];
-                if (valid && b != a && is_neighbour(xa, ya, za, ha, xb, yb, zb, hb, tr.box, mode)) {
-                    if (list && off + k < cap) list[off + k] = b;
-                    k += 1;
+    const int lane = lane_id();
+    const int64_t ncells = tr.hdr->ncells;
+    for (int64_t cell = first_cell(blockIdx.x, gridDim.x, ncells); cell >= 0 && cell < ncells;
+         cell += gridDim.x) {
+        const Geo tg = tr.lev[0][cell];
+        int32_t s0 = tr.cs[cell], s1 = tr.cs[cell + 1];
+        int64_t a = s0 + lane;
+        bool valid = a < s1;
+        double xa = valid ? x[a] : 0.0, ya = valid ? y[a] : 0.0, za = valid ? z[a] : 0.0;
+        double ha = valid ? h[a] : 0.0;
+        int64_t k = 0;
+        int64_t off = (list && valid) ? offsets[a] : 0;
+        const double R = 2.0 * (double)tg.hmax;
+        walk_init(tr, tg, R, mode == 1, &s_walk);
+        for (;;) {
+            int nc = walk_next(tr, tg, R, mode == 1, &s_walk, sA, kCandCap);
+            for (int ci = 0; ci < nc; ++ci) {
+                int cc = sA[ci];
+                int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
+                for (int32_t b = b0; b < b1; ++b) {
+                    double xb = x[b], yb = y[b], zb = z[b], hb = h[b];
+                    if (valid && b != a &&
+                        is_neighbour(xa, ya, za, ha, xb, yb, zb, hb, tr.box, mode)) {
+                        if (list && off + k < cap) list[off + k] = b;
+                        k += 1;
+                    }
                 }
             }
+            wave_sync();  // sA is read before the next chunk is written
+            if (walk_done(tr, &s_walk)) break;
         }
-        wave_sync();  // sA is read before the next chunk is written
-        if (walk_done(tr, &s_walk)) break;
+        if (valid && !list) counts[a] = k;
+        wave_sync();  // the walk state is rewritten for the next cell
     }
-    if (valid && !list) counts[a] = k;
 }
 
 }  // namespace
@@ -89,7 +94,7 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
     int rc = cells_hmax_from(c, h, n);
     if (rc) return rc;
     Tree tr = make_tree(c);
-    unsigned nb = (unsigned)c->cells_bound;
+    unsigned nb = (unsigned)c->node_grid[0];
     if (!list) {
         hipLaunchKernelGGL(k_neigh, dim3(nb), dim3(64), 0, c->stream, tr, s->x, s->y, s->z, h,
                            mode, counts, offsets, (int64_t *)nullptr, (int64_t)0);

@@ -29,6 +29,7 @@ namespace apr {
 
 constexpr int kSearchThreads = 256;
 constexpr int kWaves = kSearchThreads / kWave;
+constexpr int kRestGrid = 256;   // workgroups of a search kernel's REST launch
 constexpr int kCandCap = 256;    // candidate cells per chunk of the walk
 constexpr int kSubCap = 512;     // staged candidates per sub-block
 constexpr int kGroup = 16;       // lanes per target (sub-block layout)
@@ -162,11 +163,13 @@ __device__ inline int walk_next(const Tree &t, const Geo &tg, double R, bool sym
 
 // Candidate cells of every cell from a walk ahead of the search kernel (see
 // candidates.hip): cand[cell * kCandCap + k], k < ncand[cell]; ncand -1 means
-// "walk yourself".  The walk used radius rfac * hmax of the cell.
+// "walk yourself", and so do cells >= cap (the lists are sized from the host's
+// estimate of the cell count).  The walk used radius rfac * hmax of the cell.
 struct CandList {
     const int32_t *cand = nullptr;
     const int32_t *ncand = nullptr;
     double rfac = 0.0;
+    int64_t cap = 0;
 };
 int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out);
 
@@ -382,6 +385,22 @@ __device__ inline void load_meta(const Tree &tr, const Geo &tg, const int32_t *s
         mb->m[ci] = x;
         mb->bn[ci] = (uint8_t)(b1 - b0);
     }
+}
+
+// One staged entry as a single vector read: the pair loops test the
+// position before they use the mass, and a per-field read lets the compiler
+// defer the mass into the taken branch, one more LDS round trip per pair.
+template <class T>
+__device__ inline vec4_t<T> lds_ld4(const vec4_t<T> *p)
+{
+    typedef T n4 __attribute__((ext_vector_type(4)));
+    const n4 v = *reinterpret_cast<const n4 *>(p);
+    vec4_t<T> r;
+    r.x = v.x;
+    r.y = v.y;
+    r.z = v.z;
+    r.w = v.w;
+    return r;
 }
 
 // Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
