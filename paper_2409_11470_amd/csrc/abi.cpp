@@ -275,7 +275,7 @@ static int accel_now(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t ns
 {
     int rc;
     if (build) {
-        rc = build_cells(c, s, nullptr);
+        rc = build_cells(c, s, nullptr, false);  // accelerations recomputed below
         if (rc) return rc;
     }
     void *rho, *om, *a, *vs;
@@ -321,7 +321,7 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
         rc = apr_split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp);
         if (rc) return rc;
     }
-    rc = build_cells(c, s, nullptr);
+    rc = build_cells(c, s, nullptr, false);  // accelerations recomputed next
     if (rc) return rc;
     rc = accel_now(c, s, sinks, nsinks, false);
     if (rc) return rc;

@@ -502,18 +502,18 @@ int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
     return refit_hmax_from_cells(c);
 }
 
-static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm);
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel);
 
-int build_cells(apr_ctx *c, apr_state *s, int64_t *perm)
+int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
 {
     c->divv_n = -1;  // the permutation below reorders the particles
     int tok = prof_begin(c, APR_PROF_CELLS);
-    int rc = build_cells_impl(c, s, perm);
+    int rc = build_cells_impl(c, s, perm, keep_accel);
     prof_end(c, tok);
     return rc;
 }
 
-static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
 {
     int64_t n = s->n;
     if (n <= 0) return fail(c, APR_ERR_INVALID, "empty state");
@@ -552,14 +552,15 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm)
     hipLaunchKernelGGL(k_morton, dim3(g), dim3(256), 0, c->stream, s->x, s->y, s->z, n, b, keys,
                        vals);
     APR_LAUNCHED(c);
-    int rc = radix_sort_u32(c, keys, vals, n, kKeyBits);
+    int rc = radix_sort_u32(c, keys, vals, n, kKeyBits, &keys, &vals);
     if (rc) return rc;
 
     // permute the state in place through temporaries
     PermArgs pa;
     std::memset(&pa, 0, sizeof(pa));
     double *arrs[12] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->u, s->h,
-                        s->ax, s->ay, s->az, s->dudt};
+                        keep_accel ? s->ax : nullptr, keep_accel ? s->ay : nullptr,
+                        keep_accel ? s->az : nullptr, keep_accel ? s->dudt : nullptr};
     static const char *tn[12] = {"pt0", "pt1", "pt2", "pt3", "pt4", "pt5",
                                  "pt6", "pt7", "pt8", "pt9", "pt10", "pt11"};
     for (int k = 0; k < 12; ++k) {

@@ -219,10 +219,13 @@ int exclusive_scan_u32(apr_ctx *c, const uint32_t *in, uint32_t *out, int64_t n,
                        uint32_t *total_dev);
 int exclusive_scan_i64(apr_ctx *c, const int64_t *in, int64_t *out, int64_t n,
                        int64_t *total_dev);
-int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits);
+int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits,
+                   uint32_t **keys_out = nullptr, uint32_t **vals_out = nullptr);
 
 // cells.hip
-int build_cells(apr_ctx *c, apr_state *s, int64_t *perm);
+// keep_accel false: ax, ay, az, dudt are left unpermuted (the caller
+// recomputes them before reading them)
+int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel = true);
 int refit_hmax_from_cells(apr_ctx *c);   // tree nodes' hmax from the cells' hmax
 int cells_hmax_from(apr_ctx *c, const double *h, int64_t n);  // cells' hmax from h, then refit
 const Hdr *cell_hdr(apr_ctx *c);

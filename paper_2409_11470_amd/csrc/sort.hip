@@ -1,7 +1,8 @@
 // Device-wide exclusive scans and a stable LSD radix sort of (uint32 key,
 // uint32 value) pairs, built from wavefront-level scans (shuffles) and
 // ballot-based ranking.  No spin-waits: every scan is reduce-then-scan over
-// three launches, so every kernel finishes on its own.
+// two launches (the second sums the earlier tiles' totals itself), so every
+// kernel finishes on its own.
 #include "common.hpp"
 
 namespace apr {
@@ -61,35 +62,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the partial sums (nb <= kScanTile).
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(T *partial, int64_t nb,
-                                                                 T *total)
-{
-    __shared__ T lw[kScanThreads / kWave + 1];
-    int64_t base = (int64_t)threadIdx.x * kScanItems;
-    T v[kScanItems];
-    T s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < nb ? partial[base + k] : T(0);
-        s += v[k];
-    }
-    T tot;
-    T ex = block_excl_scan(s, lw, &tot);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < nb) partial[base + k] = ex;
-        ex += v[k];
-    }
-    if (threadIdx.x == 0 && total) *total = tot;
-}
-
+// Each tile: its offset is the sum of the earlier tiles' totals (summed here,
+// nb <= kScanTile of them), then the tile's own exclusive scan; the last tile
+// writes the grand total when asked.
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out, int64_t n,
-                                                             const T *partial)
+                                                             const T *partial, T *total)
 {
     __shared__ T lw[kScanThreads / kWave + 1];
+    T pre = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kScanThreads) pre += partial[k];
+    T off;
+    block_excl_scan(pre, lw, &off);  // off: the block-wide sum of pre
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T s = 0;
@@ -99,12 +83,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
         s += v[k];
     }
     T tot;
-    T ex = block_excl_scan(s, lw, &tot) + partial[blockIdx.x];
+    T ex = block_excl_scan(s, lw, &tot) + off;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = ex;
         ex += v[k];
     }
+    if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
 }
 
 template <class T>
@@ -122,10 +107,8 @@ int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const ch
     if (!partial) return fail(c, APR_ERR_HIP, "scan workspace");
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
                        in, n, partial);
-    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kScanThreads), 0, c->stream, partial,
-                       nb, total_dev);
     hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
-                       in, out, n, partial);
+                       in, out, n, partial, total_dev);
     APR_LAUNCHED(c);
     return APR_OK;
 }
@@ -261,11 +244,15 @@ int fill_u32(apr_ctx *c, uint32_t *p, uint32_t v, int64_t n)
     return APR_OK;
 }
 
-// Sorts keys (low `bits` bits significant) and carries vals; vals is filled
-// with 0..n-1 first when vals == nullptr is not allowed: callers pass a buffer.
-// Result is left in keys / vals.
-int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits)
+// Sorts keys (low `bits` bits significant) and carries vals (callers pass a
+// buffer).  The result is left in keys / vals, or, when keys_out and vals_out
+// are given, wherever the last pass wrote it (no copy back): *keys_out and
+// *vals_out point there (keys / vals, or the sort's own workspace).
+int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bits,
+                   uint32_t **keys_out, uint32_t **vals_out)
 {
+    if (keys_out) *keys_out = keys;
+    if (vals_out) *vals_out = vals;
     if (n <= 1) return APR_OK;
     if (n >= (int64_t)1 << 31) return fail(c, APR_ERR_INVALID, "too many particles to sort");
     int64_t nb = ceil_div(n, kSortTile);
@@ -288,7 +275,10 @@ int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bi
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    if (ka != keys) {
+    if (keys_out && vals_out) {
+        *keys_out = ka;
+        *vals_out = va;
+    } else if (ka != keys) {
         APR_HIP(c, hipMemcpyAsync(keys, ka, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
         APR_HIP(c, hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream));
     }
