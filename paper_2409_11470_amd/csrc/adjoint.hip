@@ -76,7 +76,7 @@ struct ForceVJP {
         T rinv = prsqrt(r2);
         T r = r2 * rinv;
         T rx = dx * rinv, ry = dy * rinv, rz = dz * rinv;
-        T hp = own[1].w, hq = nb[1].w;
+        T hp = own[0].w, hq = nb[0].w;
         T qp = r * hp, qq = r * hq;
         bool inp = qp < T(2), inq = qq < T(2);
         T fp, dfp, d2fp, fq, dfq, d2fq;
@@ -100,7 +100,7 @@ struct ForceVJP {
             dAp = T(-0.5) * (alpha * cp - T(2) * beta * vdr) * Gp;
             dAq = T(-0.5) * (alpha * cq - T(2) * beta * vdr) * Gq;
         }
-        T mp = own[0].w, mq = nb[0].w;
+        T mp = own[1].w, mq = nb[1].w;
         T ubp = own[3].w, ubq = nb[3].w;
         T Sx = mp * nb[3].x - mq * own[3].x, Sy = mp * nb[3].y - mq * own[3].y,
           Sz = mp * nb[3].z - mq * own[3].z;
@@ -158,7 +158,7 @@ struct DensVJP {
     {
         T rinv = prsqrt(r2);
         T r = r2 * rinv;
-        T hp = own[1].w, hq = nb[1].w;
+        T hp = own[0].w, hq = nb[0].w;
         T qp = r * hp, qq = r * hq;
         bool inp = qp < T(2), inq = qq < T(2);
         T fp, dfp, d2fp, fq, dfq, d2fq;
@@ -171,7 +171,7 @@ struct DensVJP {
         T Hq = inq ? -(qq * d2fq + T(4) * dfq) * hq5 : T(0);
         T Wq = inq ? fq * hq3 : T(0);
         T Whq = inq ? -(T(3) * fq + qq * dfq) * hq4 : T(0);
-        T mp = own[0].w, mq = nb[0].w;
+        T mp = own[1].w, mq = nb[1].w;
         T cp = own[1].x, Dp = own[1].y, cq = nb[1].x, Dq = nb[1].y;
         T coef = (cp * mq * Fp + cq * mp * Fq + Dp * mq * Hp + Dq * mp * Hq) * rinv;
         A.a[0].add(coef * dx);
@@ -183,7 +183,7 @@ struct DensVJP {
     {
         for (int k = 0; k < 4; ++k) A.a[k].template reduce<kLanes>();
         if (!write) return;
-        T hp = own[1].w;
+        T hp = own[0].w;
         double self = (double)own[1].x * (double)(hp * hp * hp) -
                       3.0 * (double)own[1].y * (double)(hp * hp * hp * hp);
         for (int k = 0; k < 3; ++k) xbar[k][i] = (T)(xb[k][i] + scx * A.a[k].value());

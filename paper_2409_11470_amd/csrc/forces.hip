@@ -98,13 +98,13 @@ struct ForceOp {
         A.u.zero();
         A.dv.zero();
         A.vs = alpha * own[2].z;
-        A.hi = own[1].w;
+        A.hi = own[0].w;
         A.hi2 = A.hi * A.hi;
         A.hi4 = A.hi2 * A.hi2;
     }
     __device__ void pair(Acc &A, const V *own, T dx, T dy, T dz, T r2, const V *nb) const
     {
-        T hb = nb[1].w, hb2 = hb * hb;
+        T hb = nb[0].w, hb2 = hb * hb;
         bool ina = r2 * A.hi2 < T(4);
         bool inb = r2 * hb2 < T(4);
         T rinv = prsqrt(r2);
@@ -121,7 +121,7 @@ struct ForceOp {
             Bb = nb[2].x - T(0.5) * nb[2].y * vsb * vdr;
             A.vs = A.vs > vsa ? A.vs : vsa;
         }
-        T mb = nb[0].w;
+        T mb = nb[1].w;
         T term = mb * (Aa * Fa + Bb * Fb) * rinv;
         A.x.add(-term * dx);
         A.y.add(-term * dy);

@@ -11,6 +11,9 @@
 //                                       centre, normalised mass), and
 //                                       [1].w = 1/h
 //   V load(int k, int64_t i) const;     array k of particle i (global)
+// The op's own[] and nb[] hold these arrays with the w components of [0] and
+// [1] exchanged, [0] = (position, 1/h) and [1].w = the mass, so that the list
+// tests read one vector per candidate.
 //   struct Acc;                         per-lane partial sums of one target
 //   void init(Acc &, const V *own) const;
 //   void pair(Acc &, const V *own, T dx, T dy, T dz, T r2, const V *nb) const;
@@ -46,8 +49,6 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     const bool valid = t < cnt;
     uint16_t *mylist = tls[t < kCell ? t : 0];
     const double R = 2.0 * (double)tg.hmax;  // targets' own supports
-    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
-    const T R2c = (T)(R * R);
 
     V own[NS];
 #pragma unroll
@@ -55,10 +56,22 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
         if (valid) own[k] = op.load(k, s0 + t);
         else { own[k].x = T(0); own[k].y = T(0); own[k].z = T(0); own[k].w = T(0); }
     }
+    {
+        const T m = own[0].w;
+        own[0].w = own[1].w;
+        own[1].w = m;
+    }
     typename OP::Acc acc;
     op.init(acc, own);
     const bool wave_busy = __any(valid);
-    const T ra = valid ? T(2) / own[1].w : T(0);
+    const T ra = valid ? T(2) / own[0].w : T(0);
+    // staged: candidates within max(R, 2 h_b) of the target cell's box
+    const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
+    const T R2c = (T)(R * R);
+    auto cell_reach = [&](T x, T y, T z, T hb) {
+        T d2 = pt_box_d2<T>(x, y, z, T(0), T(0), T(0), ex, ey, ez);
+        return d2 < R2c * kReachSlack<T> || d2 * hb * hb < T(4) * kReachSlack<T>;
+    };
 
     bool multiwin = false;  // counted once at the end (no global atomics in the loop)
     // candidates walked ahead of this kernel (same radius), else walk here
@@ -86,16 +99,14 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
         const bool more = s_more != 0;
         load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
         __syncthreads();
-        // count the candidates b within max(R, 2 h_b) of the target cell box,
-        // two cells per wavefront at a time (four loads in flight)
+        // count the staged candidates, two cells per wavefront at a time (four
+        // loads in flight)
         auto near = [&](int ci, int ln) {
             const CandMeta<T> x = mb.m[ci];
             if (ln >= (int)mb.bn[ci]) return false;
             V p = op.load(0, x.b0 + ln);
             T hb = op.load(1, x.b0 + ln).w;
-            T d2 = pt_box_d2<T>(p.x + x.sx, p.y + x.sy, p.z + x.sz, T(0), T(0), T(0), ex, ey,
-                                ez);
-            return d2 < R2c || d2 * hb * hb < T(4);
+            return cell_reach(p.x + x.sx, p.y + x.sy, p.z + x.sz, hb);
         };
         for (int ci = w; ci < nc; ci += 2 * kWaves) {
             const int c1 = ci + kWaves;
@@ -140,8 +151,10 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                     p.x = p.x + x.sx;
                     p.y = p.y + x.sy;
                     p.z = p.z + x.sz;
-                    T d2 = pt_box_d2<T>(p.x, p.y, p.z, T(0), T(0), T(0), ex, ey, ez);
-                    hit = d2 < R2c || d2 * v.w * v.w < T(4);
+                    hit = cell_reach(p.x, p.y, p.z, v.w);
+                    const T m = p.w;  // staged: [0] = (position, 1/h), [1].w = mass
+                    p.w = v.w;
+                    v.w = m;
                 }
                 uint64_t m = __ballot(hit);
                 int off = o0 + __popcll(m & lanemask_lt()) - w0;
@@ -165,19 +178,19 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                 },
                 [&](int k) { return __shfl(ra, 4 * k, kWave); },
                 [&](T d2, T Rs2, int e) {
-                    T hb = stg[1][e].w;
-                    return d2 < Rs2 || d2 * hb * hb < T(4);
+                    T hb = stg[0][e].w;
+                    return d2 < Rs2 * kReachSlack<T> || d2 * hb * hb < T(4) * kReachSlack<T>;
                 },
                 [&](const V &q, T rk, int e) {
                     V p = stg[0][e];
-                    T hb = stg[1][e].w;
+                    T hb = p.w;
                     T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
                     T r2 = dx * dx + dy * dy + dz * dz;
                     return r2 < rk * rk || r2 * hb * hb < T(4);
                 });
             const int tlen = s_tlen[t < kCell ? t : 0];
             if (!valid) continue;
-            const T ha_inv2 = own[1].w * own[1].w;
+            const T ha_inv2 = own[0].w * own[0].w;
             const bool ownlist = tlen <= kTCap;
             const int len = ownlist ? tlen : nstg;
             for (int k = j; k < len; k += kLanes) {
@@ -187,7 +200,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                 for (int a = 0; a < NS; ++a) nb[a] = stg[a][e];
                 T dx = own[0].x - nb[0].x, dy = own[0].y - nb[0].y, dz = own[0].z - nb[0].z;
                 T r2 = dx * dx + dy * dy + dz * dz;
-                T hb = nb[1].w;
+                T hb = nb[0].w;
                 if ((r2 * ha_inv2 < T(4) || r2 * hb * hb < T(4)) && r2 > T(0))
                     op.pair(acc, own, dx, dy, dz, r2, nb);
             }

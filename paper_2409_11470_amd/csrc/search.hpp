@@ -403,6 +403,12 @@ __device__ inline vec4_t<T> lds_ld4(const vec4_t<T> *p)
     return r;
 }
 
+// Staging and the per-block box tests keep a relative slack over the exact
+// criteria: a candidate that the exact per-target test accepts must pass them
+// whatever the rounding of the (differently grouped) distance sums.
+template <class T>
+constexpr T kReachSlack = T(1) + T(1.0 / (1 << 20));
+
 // Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
 template <class T>
 __device__ inline T wmax_groups(T v)
