@@ -313,7 +313,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     // this target's candidates within 2 sigma h (with margin)
                     Rt = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
                     const T Rtl = (T)Rt;
-                    build_lists16<T>(
+                    build_lists16<T, false>(
                         nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
                         [&](int k) {
                             V q;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                             return q;
                         },
                         [&](int k) { return __shfl(Rtl, 4 * k, kWave); },
-                        [&](T d2, T Rs2, int) { return d2 < Rs2; },
+                        [&](T d2, T Rs2, const V &) { return d2 < Rs2; },
                         [&](const V &q, T rk, int e) {
                             V p = stg[e];
                             T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;

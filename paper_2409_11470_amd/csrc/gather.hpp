@@ -68,9 +68,9 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     // staged: candidates within max(R, 2 h_b) of the target cell's box
     const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
     const T R2c = (T)(R * R);
-    auto cell_reach = [&](T x, T y, T z, T hb) {
+    auto cell_reach = [&](T x, T y, T z, T hb) -> bool {
         T d2 = pt_box_d2<T>(x, y, z, T(0), T(0), T(0), ex, ey, ez);
-        return d2 < R2c * kReachSlack<T> || d2 * hb * hb < T(4) * kReachSlack<T>;
+        return (d2 < R2c * kReachSlack<T>) | (d2 * hb * hb < T(4) * kReachSlack<T>);
     };
 
     bool multiwin = false;  // counted once at the end (no global atomics in the loop)
@@ -167,7 +167,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
             }
             __syncthreads();
             if (!wave_busy) continue;
-            build_lists16<T>(
+            build_lists16<T, true>(
                 nstg, stg[0], sub[w], &tls[0][0], kTCap, s_tlen,
                 [&](int k) {
                     V q;
@@ -177,16 +177,16 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                     return q;
                 },
                 [&](int k) { return __shfl(ra, 4 * k, kWave); },
-                [&](T d2, T Rs2, int e) {
-                    T hb = stg[0][e].w;
-                    return d2 < Rs2 * kReachSlack<T> || d2 * hb * hb < T(4) * kReachSlack<T>;
+                [&](T d2, T Rs2, const V &p) -> bool {
+                    // both tests, no branch: the entry is one vector read
+                    return (d2 < Rs2 * kReachSlack<T>) | (d2 * p.w * p.w < T(4) * kReachSlack<T>);
                 },
-                [&](const V &q, T rk, int e) {
-                    V p = stg[0][e];
+                [&](const V &q, T rk, int e) -> bool {
+                    const V p = lds_ld4<T>(&stg[0][e]);
                     T hb = p.w;
                     T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
                     T r2 = dx * dx + dy * dy + dz * dz;
-                    return r2 < rk * rk || r2 * hb * hb < T(4);
+                    return (r2 < rk * rk) | (r2 * hb * hb < T(4));
                 });
             const int tlen = s_tlen[t < kCell ? t : 0];
             if (!valid) continue;
@@ -197,11 +197,11 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                 int e = ownlist ? mylist[k] : k;
                 V nb[NS];
 #pragma unroll
-                for (int a = 0; a < NS; ++a) nb[a] = stg[a][e];
+                for (int a = 0; a < NS; ++a) nb[a] = lds_ld4<T>(&stg[a][e]);
                 T dx = own[0].x - nb[0].x, dy = own[0].y - nb[0].y, dz = own[0].z - nb[0].z;
                 T r2 = dx * dx + dy * dy + dz * dz;
                 T hb = nb[0].w;
-                if ((r2 * ha_inv2 < T(4) || r2 * hb * hb < T(4)) && r2 > T(0))
+                if (((r2 * ha_inv2 < T(4)) | (r2 * hb * hb < T(4))) & (r2 > T(0)))
                     op.pair(acc, own, dx, dy, dz, r2, nb);
             }
         }

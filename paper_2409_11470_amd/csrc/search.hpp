@@ -337,7 +337,8 @@ __device__ inline bool wave_reach(const WaveBoxes<T> &B, T x, T y, T z, T hb2)
     for (int k = 0; k < kWaves; ++k) {
         T r2 = B.R2[k];
         T d2 = pt_lohi_d2<T>(x, y, z, B.lo[k], B.hi[k]);
-        hit = hit || (r2 >= T(0) && (d2 < r2 || (SYM && d2 * hb2 < T(4))));
+        // bitwise, no branches: most candidates are tested against every box anyway
+        hit = hit | ((r2 >= T(0)) & ((d2 < r2) | (SYM & (d2 * hb2 < T(4)))));
     }
     return hit;
 }
@@ -472,14 +473,15 @@ struct Acc {
 // Per-target candidate lists for the 16 targets of a wavefront (targets
 // 16 w + k, k = 0..15), built with 16 lanes per target: for each sub-block of
 // 4 targets the wavefront lists the staged entries near the sub-block's box
-// (box_ok(d2, Rs2, e): d2 the squared distance of entry e to the box, Rs the
-// largest reach of the sub-block's targets), then each target's 16 lanes keep
+// (box_ok(d2, Rs2, p): d2 the squared distance of entry p to the box, Rs the
+// largest reach of the sub-block's targets; with FULL the entry is read as one
+// vector, w included), then each target's 16 lanes keep
 // the entries that accept(target position, reach, e).  pos(k) and reach(k)
 // give target slot k's position and reach (0: no list); every lane calls them.
 // sub is the wavefront's scratch list (room for nstg entries).  Writes
 // tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length above cap means the
 // list is incomplete and the caller must walk the staged set instead.
-template <class T, class Pos, class Reach, class BoxOk, class Accept>
+template <class T, bool FULL, class Pos, class Reach, class BoxOk, class Accept>
 __device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *sub,
                                      uint16_t *tls, int cap, int *tlen, Pos pos, Reach reach,
                                      BoxOk box_ok, Accept accept)
@@ -507,9 +509,9 @@ __device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *s
                 int idx = base + lane;
                 bool hit = false;
                 if (idx < nstg) {
-                    vec4_t<T> p = stg[idx];
-                    hit = box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2,
-                                 idx);
+                    // FULL: box_ok reads the w component too (one vector read)
+                    const vec4_t<T> p = FULL ? lds_ld4<T>(&stg[idx]) : stg[idx];
+                    hit = box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2, p);
                 }
                 uint64_t m = __ballot(hit);
                 if (hit) sub[nsub + __popcll(m & lanemask_lt())] = (uint16_t)idx;
