@@ -270,8 +270,9 @@ static void step_buffers(apr_ctx *c, int64_t cap, void **rho, void **om, void **
     *vs = ws(c, "st_vsig", cap * e);
 }
 
+// kick_dt != 0: the closing half-kick of a step rides on the acceleration total
 static int accel_now(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t nsinks,
-                     bool build)
+                     bool build, double kick_dt = 0.0)
 {
     int rc;
     if (build) {
@@ -288,7 +289,8 @@ static int accel_now(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t ns
     if (rc) return rc;
     rc = forces(c, s, rho, om, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, vs, true);
     if (rc) return rc;
-    return total_accel(c, s, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, sinks, nsinks);
+    return total_accel(c, s, ab, ab + stride, ab + 2 * stride, ab + 3 * stride, sinks, nsinks,
+                       kick_dt);
 }
 
 int apr_accel(apr_ctx *c, apr_state *s, const apr_sink *sinks, int32_t nsinks)
@@ -309,9 +311,7 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
     if (!s->ax || !s->ay || !s->az || !s->dudt)
         return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt");
     if (nsinks > 0 && !sinks) return fail(c, APR_ERR_INVALID, "sinks");
-    rc = kick(c, s, 0.5 * dt);
-    if (rc) return rc;
-    rc = drift(c, s, dt);
+    rc = kick_drift(c, s, 0.5 * dt, dt);  // opening half-kick and drift, one pass
     if (rc) return rc;
     if (nzones > 0) {
         // the refinement pass opens the step (before this step's density); its
@@ -323,9 +323,7 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
     }
     rc = build_cells(c, s, nullptr, false);  // accelerations recomputed next
     if (rc) return rc;
-    rc = accel_now(c, s, sinks, nsinks, false);
-    if (rc) return rc;
-    return kick(c, s, 0.5 * dt);
+    return accel_now(c, s, sinks, nsinks, false, 0.5 * dt);  // with the closing half-kick
 }
 
 int apr_timestep(apr_ctx *c, const apr_state *s, double C, double *dt)

@@ -454,6 +454,25 @@ __global__ __launch_bounds__(256) void k_tree_hmax(const Hdr *hdr, int lev, cons
     }
 }
 
+// The cells' new hmax (one per cell, from the density pass) into their Geo and
+// the level-1 nodes' hmax in the same pass: one wavefront per 64 cells (a
+// level-1 node; node == nullptr when the tree has no level above the cells).
+__global__ __launch_bounds__(256) void k_hmax_new_level1(const Hdr *hdr, const float *hmax_new,
+                                                         Geo *cells, Geo *node)
+{
+    const int lane = lane_id();
+    const int64_t nc = hdr->ncells;
+    APR_FOR_WAVE_ITEMS(j, (nc + kFan - 1) / kFan)
+    {
+        int64_t k = j * kFan + lane;
+        bool in = k < nc;
+        float v = in ? hmax_new[k] : 0.0f;
+        if (in) cells[k].hmax = v;
+        float hm = wave_max(v);
+        if (lane == 0 && node) node[j].hmax = hm;
+    }
+}
+
 // Cells' hmax from a given h array.
 __global__ __launch_bounds__(256) void k_cell_hmax(const Hdr *hdr, const int32_t *cell_start,
                                                    const double *h, Geo *cells)
@@ -486,6 +505,20 @@ int refit_hmax_from_cells(apr_ctx *c)
 {
     Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
     for (int k = 1; k <= c->nlev; ++k)
+        hipLaunchKernelGGL(k_tree_hmax, dim3((unsigned)ceil_div(c->node_grid[k], 4)), dim3(256),
+                           0, c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k));
+    APR_LAUNCHED(c);
+    return APR_OK;
+}
+
+int set_hmax_new(apr_ctx *c, const float *hmax_new)
+{
+    Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
+    const int64_t g1 = ceil_div(c->node_grid[0], kFan);  // level-1 nodes (groups of 64 cells)
+    hipLaunchKernelGGL(k_hmax_new_level1, dim3((unsigned)ceil_div(g1, 4)), dim3(256), 0,
+                       c->stream, hdr, hmax_new, cell_level(c, 0),
+                       c->nlev >= 1 ? cell_level(c, 1) : (Geo *)nullptr);
+    for (int k = 2; k <= c->nlev; ++k)
         hipLaunchKernelGGL(k_tree_hmax, dim3((unsigned)ceil_div(c->node_grid[k], 4)), dim3(256),
                            0, c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k));
     APR_LAUNCHED(c);

@@ -227,6 +227,7 @@ int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bi
 // recomputes them before reading them)
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel = true);
 int refit_hmax_from_cells(apr_ctx *c);   // tree nodes' hmax from the cells' hmax
+int set_hmax_new(apr_ctx *c, const float *hmax_new);  // cells' hmax from hmax_new[cell], then the tree's
 int cells_hmax_from(apr_ctx *c, const double *h, int64_t n);  // cells' hmax from h, then refit
 const Hdr *cell_hdr(apr_ctx *c);
 const int32_t *cell_start(apr_ctx *c);
@@ -252,10 +253,10 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
                int64_t *offsets, int64_t *list, int64_t cap, int64_t *total);
 
 // integrate.hip
-int kick(apr_ctx *c, apr_state *s, double dt);
-int drift(apr_ctx *c, apr_state *s, double dt);
+int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt);  // kick by dtk, then drift
+// kick_dt != 0: also v += kick_dt a (and u) with the new accelerations
 int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
-                const void *dudt, const apr_sink *sinks, int nsinks);
+                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt = 0.0);
 int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, double *dt);
 
 // splitmerge.hip

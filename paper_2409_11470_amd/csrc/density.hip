@@ -494,12 +494,6 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(Den
     }
 }
 
-__global__ void k_set_cell_hmax(const Hdr *hdr, const float *hmax_new, Geo *cells)
-{
-    const int64_t nc = hdr->ncells, step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += step)
-        cells[c].hmax = hmax_new[c];
-}
 
 }  // namespace
 
@@ -580,10 +574,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
                            c->stream, a, grid);
     }
     APR_LAUNCHED(c);
-    hipLaunchKernelGGL(k_set_cell_hmax, dim3((unsigned)ceil_div(grid, 256)), dim3(256), 0,
-                       c->stream, cell_hdr(c), hmax_new, cell_level(c, 0));
-    APR_LAUNCHED(c);
-    int rc = refit_hmax_from_cells(c);
+    int rc = set_hmax_new(c, hmax_new);  // cells' and tree nodes' h_max for the force search
     if (rc) return rc;
     c->dens_n = s->n;
     return APR_OK;

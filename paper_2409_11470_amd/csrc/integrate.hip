@@ -7,37 +7,32 @@ namespace apr {
 
 namespace {
 
-__global__ void k_kick(int64_t n, double *vx, double *vy, double *vz, double *u,
-                       const double *ax, const double *ay, const double *az,
-                       const double *dudt, double dt)
+// The step's opening half-kick, v += dtk a (and u += dtk du/dt), then the
+// drift x += dt v (wrapped into a periodic box), in one pass.  With divv (the
+// velocity divergence of the last force evaluation) the smoothing length is
+// predicted from the continuity equation, dh/dt = (h/3) div v, as the Newton
+// guess of the next density pass: h *= exp(dt div v / 3), the factor kept in
+// [0.8, 1.25].
+__global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz, double *u, const double *ax, const double *ay,
+                             const double *az, const double *dudt, double *h, const float *divv,
+                             double dtk, double dt, Box b)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    vx[i] += dt * ax[i];
-    vy[i] += dt * ay[i];
-    vz[i] += dt * az[i];
-    if (u && dudt) u[i] += dt * dudt[i];
-}
-
-// x += dt v (wrapped into a periodic box).  With divv (the velocity
-// divergence of the last force evaluation) the smoothing length is predicted
-// from the continuity equation, dh/dt = (h/3) div v, as the Newton guess of
-// the next density pass: h *= exp(dt div v / 3), the factor kept in [0.8, 1.25].
-__global__ void k_drift(int64_t n, double *x, double *y, double *z, const double *vx,
-                        const double *vy, const double *vz, double *h, const float *divv,
-                        double dt, Box b)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const double v[3] = {vx[i] + dtk * ax[i], vy[i] + dtk * ay[i], vz[i] + dtk * az[i]};
+    vx[i] = v[0];
+    vy[i] = v[1];
+    vz[i] = v[2];
+    if (u && dudt) u[i] += dtk * dudt[i];
     if (divv) {
         double f = exp(dt * (double)divv[i] / 3.0);
         h[i] *= fmin(fmax(f, 0.8), 1.25);
     }
     double *p[3] = {x, y, z};
-    const double *v[3] = {vx, vy, vz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double xn = p[k][i] + dt * v[k][i];
+        double xn = p[k][i] + dt * v[k];
         if (b.periodic) {
             double hi = b.lo[k] + b.L[k];
             if (xn >= hi) xn -= b.L[k];
@@ -54,10 +49,13 @@ struct Sinks {
     double x[kMaxSinks][3], m[kMaxSinks], eps2[kMaxSinks];
 };
 
+// With vx non-null it also applies the step's closing half-kick with the new
+// accelerations, v += kdt a, u += kdt du/dt.
 template <class T>
 __global__ void k_total_accel(int64_t n, const double *x, const double *y, const double *z,
                               const T *hax, const T *hay, const T *haz, const T *hdu, Sinks S,
-                              double *ax, double *ay, double *az, double *dudt)
+                              double *ax, double *ay, double *az, double *dudt, double kdt,
+                              double *vx, double *vy, double *vz, double *u)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -75,6 +73,12 @@ __global__ void k_total_accel(int64_t n, const double *x, const double *y, const
     ay[i] = gy;
     az[i] = gz;
     if (dudt) dudt[i] = (double)hdu[i];
+    if (vx) {
+        vx[i] += kdt * gx;
+        vy[i] += kdt * gy;
+        vz[i] += kdt * gz;
+        if (u && dudt) u[i] += kdt * (double)hdu[i];
+    }
 }
 
 template <class T>
@@ -112,30 +116,22 @@ __global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, do
 
 }  // namespace
 
-int kick(apr_ctx *c, apr_state *s, double dt)
+int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt)
 {
     if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
     int64_t n = s->n;
     double *u = c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
-    hipLaunchKernelGGL(k_kick, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, n,
-                       s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt, dt);
-    APR_LAUNCHED(c);
-    return APR_OK;
-}
-
-int drift(apr_ctx *c, apr_state *s, double dt)
-{
-    int64_t n = s->n;
     const float *divv = c->divv_n == n ? wsa<float>(c, "divv", (size_t)n) : nullptr;
-    hipLaunchKernelGGL(k_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream, n,
-                       s->x, s->y, s->z, s->vx, s->vy, s->vz, s->h, divv, dt, make_box(c->p));
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
+                       n, s->x, s->y, s->z, s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt,
+                       s->h, divv, dtk, dt, make_box(c->p));
     APR_LAUNCHED(c);
     c->cells_n = -1;
     return APR_OK;
 }
 
 int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
-                const void *dudt, const apr_sink *sinks, int nsinks)
+                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt)
 {
     if (nsinks < 0 || nsinks > kMaxSinks) return fail(c, APR_ERR_INVALID, "too many sinks");
     if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
@@ -150,15 +146,19 @@ int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const 
     }
     int64_t n = s->n;
     unsigned g = (unsigned)ceil_div(n, 256);
+    const bool k = kick_dt != 0.0;
+    double *u = k && c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
+    double *vx = k ? s->vx : nullptr, *vy = k ? s->vy : nullptr, *vz = k ? s->vz : nullptr;
     if (c->p.precision == APR_FP32)
         hipLaunchKernelGGL(k_total_accel<float>, dim3(g), dim3(256), 0, c->stream, n, s->x, s->y,
                            s->z, (const float *)ax, (const float *)ay, (const float *)az,
-                           (const float *)dudt, S, s->ax, s->ay, s->az, s->dudt);
+                           (const float *)dudt, S, s->ax, s->ay, s->az, s->dudt, kick_dt, vx, vy,
+                           vz, u);
     else
         hipLaunchKernelGGL(k_total_accel<double>, dim3(g), dim3(256), 0, c->stream, n, s->x,
                            s->y, s->z, (const double *)ax, (const double *)ay,
                            (const double *)az, (const double *)dudt, S, s->ax, s->ay, s->az,
-                           s->dudt);
+                           s->dudt, kick_dt, vx, vy, vz, u);
     APR_LAUNCHED(c);
     return APR_OK;
 }
