@@ -224,7 +224,9 @@ int apr_split_merge(apr_ctx *ctx, apr_state *s, const apr_zone *zones, int32_t n
 /* Kick-drift-kick leapfrog step of size dt on the state (the paper's host
  * code integrates; the scheme here is the standard KDK):
  *   v += dt/2 a, u += dt/2 du/dt;  x += dt v (wrapped if periodic), and the
- *   Newton guess h *= exp(dt div v / 3) from the last force pass;
+ *   Newton guess h *= exp(dt D / 3), D the velocity divergence of the last
+ *   force pass, extrapolated with the one before it when both are at hand
+ *   (D + dt/(2 dt_last) (D - D_prev)), the factor clamped to [0.8, 1.25];
  *   split/merge if nzones > 0 (Sec. 2.6: refinement opens the step; the
  *   nearest-neighbour cap uses the last density pass);
  *   rebuild cells, density;  hydro forces + sink gravity -> a, du/dt;

@@ -319,6 +319,8 @@ struct PermArgs {
     int64_t *id, *idt;
     const uint32_t *perm;
     int64_t *perm_out;
+    const float *fin;  // one float array gathered into another (no write-back)
+    float *fout;
     int64_t n;
 };
 
@@ -331,6 +333,7 @@ __global__ void k_gather(PermArgs a)
     a.levt[i] = a.lev[j];
     a.idt[i] = a.id[j];
     if (a.perm_out) a.perm_out[i] = j;
+    if (a.fin) a.fout[i] = a.fin[j];
 }
 
 __global__ void k_scatter_back(PermArgs a)
@@ -535,18 +538,25 @@ int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
     return refit_hmax_from_cells(c);
 }
 
-static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel);
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel,
+                            bool carry_divv);
 
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
 {
-    c->divv_n = -1;  // the permutation below reorders the particles
+    // the last velocity divergence moves with the particles into "divv_prev"
+    // (for the h predictor's extrapolation); "divv" is stale afterwards
+    const bool dv = c->divv_n == s->n;
+    c->divv_n = -1;
+    c->divv_prev_n = -1;
     int tok = prof_begin(c, APR_PROF_CELLS);
-    int rc = build_cells_impl(c, s, perm, keep_accel);
+    int rc = build_cells_impl(c, s, perm, keep_accel, dv);
     prof_end(c, tok);
+    if (rc == APR_OK && dv) c->divv_prev_n = s->n;
     return rc;
 }
 
-static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
+static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel,
+                            bool carry_divv)
 {
     int64_t n = s->n;
     if (n <= 0) return fail(c, APR_ERR_INVALID, "empty state");
@@ -610,6 +620,11 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_a
     pa.perm = vals;
     pa.perm_out = perm;
     pa.n = n;
+    if (carry_divv) {
+        pa.fin = wsa<float>(c, "divv", (size_t)n);
+        pa.fout = wsa<float>(c, "divv_prev", (size_t)n);
+        if (!pa.fin || !pa.fout) return fail(c, APR_ERR_HIP, "permute workspace");
+    }
     hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, c->stream, pa);
     hipLaunchKernelGGL(k_scatter_back, dim3(g), dim3(256), 0, c->stream, pa);
     APR_LAUNCHED(c);

@@ -90,6 +90,9 @@ struct apr_ctx {
     int64_t force_n = -1;          // n of the last force evaluation (for the timestep)
     int64_t divv_n = -1;           // velocity divergence of the last force evaluation is in the
                                    // workspace "divv" in the current particle order (else -1)
+    int64_t divv_prev_n = -1;      // the one before it, carried through the last cell build's
+                                   // permutation, is in "divv_prev" (else -1)
+    double dt_last = 0.0;          // dt of the last step (the spacing of those two)
     // kernel timing: pairs of events per index, summed at read time
     bool prof = false;
     struct EvPair {

@@ -313,7 +313,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     // this target's candidates within 2 sigma h (with margin)
                     Rt = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
                     const T Rtl = (T)Rt;
-                    build_lists16<T, false>(
+                    build_lists<T, false, kListLanes>(
                         nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
                         [&](int k) {
                             V q;

@@ -167,7 +167,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
             }
             __syncthreads();
             if (!wave_busy) continue;
-            build_lists16<T, true>(
+            build_lists<T, true, kListLanes>(
                 nstg, stg[0], sub[w], &tls[0][0], kTCap, s_tlen,
                 [&](int k) {
                     V q;

@@ -11,12 +11,14 @@ namespace {
 // drift x += dt v (wrapped into a periodic box), in one pass.  With divv (the
 // velocity divergence of the last force evaluation) the smoothing length is
 // predicted from the continuity equation, dh/dt = (h/3) div v, as the Newton
-// guess of the next density pass: h *= exp(dt div v / 3), the factor kept in
-// [0.8, 1.25].
+// guess of the next density pass: h *= exp(dt D / 3), the factor kept in
+// [0.8, 1.25].  D = div v, or with the divergence of the force evaluation
+// before (divv_prev) the two-step extrapolation D = div v + w (div v -
+// divv_prev), w = dt / (2 dt_last), which centres it on the new step.
 __global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, double *u, const double *ax, const double *ay,
                              const double *az, const double *dudt, double *h, const float *divv,
-                             double dtk, double dt, Box b)
+                             const float *divv_prev, double w, double dtk, double dt, Box b)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -26,7 +28,9 @@ __global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double 
     vz[i] = v[2];
     if (u && dudt) u[i] += dtk * dudt[i];
     if (divv) {
-        double f = exp(dt * (double)divv[i] / 3.0);
+        double D = (double)divv[i];
+        if (divv_prev) D += w * (D - (double)divv_prev[i]);
+        double f = exp(dt * D / 3.0);
         h[i] *= fmin(fmax(f, 0.8), 1.25);
     }
     double *p[3] = {x, y, z};
@@ -122,11 +126,16 @@ int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt)
     int64_t n = s->n;
     double *u = c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
     const float *divv = c->divv_n == n ? wsa<float>(c, "divv", (size_t)n) : nullptr;
+    const float *divv_prev = divv && c->divv_prev_n == n && c->dt_last > 0.0
+                                 ? wsa<float>(c, "divv_prev", (size_t)n)
+                                 : nullptr;
+    const double w = divv_prev ? dt / (2.0 * c->dt_last) : 0.0;
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
                        n, s->x, s->y, s->z, s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt,
-                       s->h, divv, dtk, dt, make_box(c->p));
+                       s->h, divv, divv_prev, w, dtk, dt, make_box(c->p));
     APR_LAUNCHED(c);
     c->cells_n = -1;
+    c->dt_last = dt;
     return APR_OK;
 }
 

@@ -33,6 +33,7 @@ constexpr int kRestGrid = 256;   // workgroups of a search kernel's REST launch
 constexpr int kCandCap = 256;    // candidate cells per chunk of the walk
 constexpr int kSubCap = 512;     // staged candidates per sub-block
 constexpr int kGroup = 16;       // lanes per target (sub-block layout)
+constexpr int kListLanes = 16;   // lanes per target while building the per-target lists
 constexpr int kLanes = 4;        // lanes per target (one target per lane group of 4)
 constexpr int kTCap = 128;       // per-target candidate list (u16 LDS indices)
 // Workgroups per CU the density and force kernels are compiled for: the FP32
@@ -410,24 +411,6 @@ __device__ inline vec4_t<T> lds_ld4(const vec4_t<T> *p)
 template <class T>
 constexpr T kReachSlack = T(1) + T(1.0 / (1 << 20));
 
-// Max over the 4 groups of a wavefront (lanes 0, 16, 32, 48 hold group values).
-template <class T>
-__device__ inline T wmax_groups(T v)
-{
-    T u = __shfl_xor(v, 16, kWave);
-    v = v > u ? v : u;
-    u = __shfl_xor(v, 32, kWave);
-    return v > u ? v : u;
-}
-template <class T>
-__device__ inline T wmin_groups(T v)
-{
-    T u = __shfl_xor(v, 16, kWave);
-    v = v < u ? v : u;
-    u = __shfl_xor(v, 32, kWave);
-    return v < u ? v : u;
-}
-
 // Square root and reciprocal square root in the pair precision: the FP32
 // form uses the hardware v_sqrt_f32 / v_rsq_f32 (about 1 ulp), the FP64 form
 // the correctly rounded library functions.
@@ -470,34 +453,61 @@ struct Acc {
     __device__ double value() const { return (double)s - (double)c; }
 };
 
-// Per-target candidate lists for the 16 targets of a wavefront (targets
-// 16 w + k, k = 0..15), built with 16 lanes per target: for each sub-block of
-// 4 targets the wavefront lists the staged entries near the sub-block's box
-// (box_ok(d2, Rs2, p): d2 the squared distance of entry p to the box, Rs the
-// largest reach of the sub-block's targets; with FULL the entry is read as one
-// vector, w included), then each target's 16 lanes keep
-// the entries that accept(target position, reach, e).  pos(k) and reach(k)
-// give target slot k's position and reach (0: no list); every lane calls them.
-// sub is the wavefront's scratch list (room for nstg entries).  Writes
-// tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length above cap means the
-// list is incomplete and the caller must walk the staged set instead.
-template <class T, bool FULL, class Pos, class Reach, class BoxOk, class Accept>
-__device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *sub,
-                                     uint16_t *tls, int cap, int *tlen, Pos pos, Reach reach,
-                                     BoxOk box_ok, Accept accept)
+// Min / max over the groups of G lanes of a wavefront (every lane ends with
+// the result over the lanes j, j + G, j + 2G, ...).
+template <int G, class T>
+__device__ inline T wmin_lanes(T v)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, j = lane & 15;
-    for (int sb = 0; sb < 4; ++sb) {
-        const int k = 4 * sb + g;  // this lane's target slot in the wave
+#pragma unroll
+    for (int o = G; o < kWave; o <<= 1) {
+        T u = __shfl_xor(v, o, kWave);
+        v = v < u ? v : u;
+    }
+    return v;
+}
+template <int G, class T>
+__device__ inline T wmax_lanes(T v)
+{
+#pragma unroll
+    for (int o = G; o < kWave; o <<= 1) {
+        T u = __shfl_xor(v, o, kWave);
+        v = v > u ? v : u;
+    }
+    return v;
+}
+
+// Per-target candidate lists for the 16 targets of a wavefront (targets
+// 16 w + k, k = 0..15), built with G lanes per target (G = 16: sub-blocks of 4
+// targets; G = 8: of 8): for each sub-block the wavefront lists the staged
+// entries near the sub-block's box (box_ok(d2, Rs2, p): d2 the squared
+// distance of entry p to the box, Rs the largest reach of the sub-block's
+// targets; with FULL the entry is read as one vector, w included), then each
+// target's G lanes keep the entries that accept(target position, reach, e).
+// pos(k) and reach(k) give target slot k's position and reach (0: no list);
+// every lane calls them.  sub is the wavefront's scratch list (room for nstg
+// entries).  Writes tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length
+// above cap means the list is incomplete and the caller must walk the staged
+// set instead.
+template <class T, bool FULL, int G, class Pos, class Reach, class BoxOk, class Accept>
+__device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub, uint16_t *tls,
+                                   int cap, int *tlen, Pos pos, Reach reach, BoxOk box_ok,
+                                   Accept accept)
+{
+    static_assert(G == 8 || G == 16, "8 or 16 lanes per target");
+    constexpr int TPS = kWave / G;   // targets per sub-block
+    constexpr int NSB = 16 / TPS;    // sub-blocks per wavefront
+    const int w = threadIdx.x / kWave, lane = lane_id(), g = lane / G, j = lane % G;
+    for (int sb = 0; sb < NSB; ++sb) {
+        const int k = TPS * sb + g;  // this lane's target slot in the wave
         vec4_t<T> tp = pos(k);
         T rk = reach(k);
         T bigT = T(3.0e38);
         bool act = rk > T(0);
-        T lox = wmin_groups(act ? tp.x : bigT), loy = wmin_groups(act ? tp.y : bigT),
-          loz = wmin_groups(act ? tp.z : bigT);
-        T hix = wmax_groups(act ? tp.x : -bigT), hiy = wmax_groups(act ? tp.y : -bigT),
-          hiz = wmax_groups(act ? tp.z : -bigT);
-        T Rs = wmax_groups(rk);
+        T lox = wmin_lanes<G>(act ? tp.x : bigT), loy = wmin_lanes<G>(act ? tp.y : bigT),
+          loz = wmin_lanes<G>(act ? tp.z : bigT);
+        T hix = wmax_lanes<G>(act ? tp.x : -bigT), hiy = wmax_lanes<G>(act ? tp.y : -bigT),
+          hiz = wmax_lanes<G>(act ? tp.z : -bigT);
+        T Rs = wmax_lanes<G>(rk);
         int len = 0;
         if (Rs > T(0)) {
             T Rs2 = Rs * Rs;
@@ -519,7 +529,8 @@ __device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *s
             }
             wave_sync();
             uint16_t *L = tls + (size_t)(16 * w + k) * cap;
-            for (int base = 0; base < nsub; base += kGroup) {
+            constexpr uint64_t gmask = G == 16 ? 0xffffull : 0xffull;
+            for (int base = 0; base < nsub; base += G) {
                 int k0 = base + j;
                 bool hit = false;
                 int e = 0;
@@ -528,7 +539,7 @@ __device__ inline void build_lists16(int nstg, const vec4_t<T> *stg, uint16_t *s
                     hit = accept(tp, rk, e);
                 }
                 uint64_t m = __ballot(hit);
-                uint32_t gm = (uint32_t)(m >> (16 * g)) & 0xffffu;
+                uint32_t gm = (uint32_t)((m >> (G * g)) & gmask);
                 int p = len + __popc(gm & ((1u << j) - 1u));
                 if (hit && p < cap) L[p] = (uint16_t)e;
                 len += __popc(gm);

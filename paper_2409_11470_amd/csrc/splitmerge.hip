@@ -847,6 +847,7 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     if (*n_split + *n_merged > 0) {  // the particle set changed: cells are stale
         c->cells_n = -1;
         c->divv_n = -1;
+        c->divv_prev_n = -1;
         c->dens_n = -1;
         c->force_n = -1;
     }
