@@ -22,10 +22,14 @@
 // sums; double: the same code in FP64).  The Newton update and its
 // convergence test are FP64 in both forms.
 //
-// One workgroup (4 wavefronts) per target cell; each wavefront serves 4
-// sub-blocks of 4 targets with 16 lanes per target.  If a target's 2h
-// outgrows the staged radius the workgroup searches and stages again with
-// the larger radius (bounded: h at most doubles per Newton step, max_iter).
+// One workgroup (4 wavefronts) per target cell of up to 64 particles; a
+// wavefront takes 16 targets.  The candidates within reach of some
+// wavefront's targets are staged in LDS; each wavefront then lists, per
+// target, the staged entries within 2 sigma h (4 targets at a time, 16 lanes
+// each), and every Newton pass sums a target's list with 4 lanes.  If a
+// target's 2h outgrows the staged radius the workgroup searches and stages
+// again with the larger radius (bounded: h at most doubles per Newton step,
+// max_iter).
 #include "search.hpp"
 
 namespace apr {
