@@ -230,12 +230,25 @@ __device__ inline T wave_reduce(T v, F op)
 __device__ inline int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __device__ inline int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 
-__global__ void k_max_level(int64_t n, const int8_t *level, int32_t *out)
+// Highest level present: a grid-stride pass (at most kMaxLevelBlocks
+// workgroups), reduced within each workgroup, one atomic per workgroup (one
+// per wavefront made a million particles wait on 16k atomics to one word).
+constexpr int kMaxLevelBlocks = 1024;
+__global__ __launch_bounds__(256) void k_max_level(int64_t n, const int8_t *level, int32_t *out)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t v = i < n ? (int32_t)level[i] : 0;
+    __shared__ int32_t red[256 / kWave];
+    int32_t v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v = imax(v, (int32_t)level[i]);
     v = wave_reduce(v, imax);
-    if (__lane_id() == 0) atomicMax(out, v);
+    if (__lane_id() == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = red[0];
+        for (int k = 1; k < 256 / kWave; ++k) m = imax(m, red[k]);
+        atomicMax(out, m);
+    }
 }
 
 __global__ void k_cand_flags(int64_t n, const int8_t *level, const uint8_t *changed,
@@ -708,8 +721,8 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     if (do_merge && n > 1) {
         APR_HIP(c, hipMemsetAsync(imax, 0, 4, c->stream));
         APR_HIP(c, hipMemsetAsync(mcount, 0, 8, c->stream));
-        hipLaunchKernelGGL(k_max_level, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
-                           imax);
+        hipLaunchKernelGGL(k_max_level, dim3(std::min<unsigned>(grid(n), kMaxLevelBlocks)),
+                           dim3(256), 0, c->stream, n, s->level, imax);
         APR_LAUNCHED(c);
         int32_t lmax = 0;
         APR_HIP(c, hipMemcpyAsync(&lmax, imax, 4, hipMemcpyDeviceToHost, c->stream));
