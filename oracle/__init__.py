@@ -38,6 +38,15 @@ def lib():
         L.orc_m4_df.argtypes = [C.c_double]
         L.orc_m4_d2f.restype = C.c_double
         L.orc_m4_d2f.argtypes = [C.c_double]
+        for nm in ("orc_wc2_f", "orc_wc2_df", "orc_wc2_d2f"):
+            getattr(L, nm).restype = C.c_double
+            getattr(L, nm).argtypes = [C.c_double]
+        for nm in ("orc_kf", "orc_kdf", "orc_kd2f"):
+            getattr(L, nm).restype = C.c_double
+            getattr(L, nm).argtypes = [C.c_int32, C.c_double]
+        for nm in ("orc_wk", "orc_dwdhk"):
+            getattr(L, nm).restype = C.c_double
+            getattr(L, nm).argtypes = [C.c_int32, C.c_double, C.c_double]
         L.orc_w.restype = C.c_double
         L.orc_w.argtypes = [C.c_double, C.c_double]
         L.orc_dwdh.restype = C.c_double
@@ -45,7 +54,7 @@ def lib():
         L.orc_density.restype = C.c_int64
         L.orc_density.argtypes = [C.c_int64, _d, _d, _d, _i8, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_int32, _d, _d, C.c_int64, _i64,
-                                  _d, _d, _d, _d, _i32, _d, _i32]
+                                  _d, _d, _d, _d, _i32, _d, _i32, C.c_int32]
         L.orc_neighbours.restype = None
         L.orc_neighbours.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_int32, C.c_int32, _d, _d,
                                      C.c_int64, _i64, _i64, _i64, _i64]
@@ -56,7 +65,7 @@ def lib():
         L.orc_forces.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, _d, _i8, _d, _d, _d,
                                  C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_double, C.c_int32, _d, _d,
-                                 C.c_int64, _i64, _d, _d, _d, _d, _d, _d, _d]
+                                 C.c_int64, _i64, _d, _d, _d, _d, _d, _d, _d, C.c_int32]
         L.orc_kick.restype = None
         L.orc_kick.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, C.c_double]
         L.orc_drift.restype = None
@@ -115,17 +124,45 @@ def m4_d2f(q):
     return lib().orc_m4_d2f(float(q))
 
 
-def w(r, h):
-    return lib().orc_w(float(r), float(h))
+KERNEL_M4, KERNEL_WC2 = 0, 1
 
 
-def dwdh(r, h):
-    return lib().orc_dwdh(float(r), float(h))
+def wc2_f(q):
+    return lib().orc_wc2_f(float(q))
+
+
+def wc2_df(q):
+    return lib().orc_wc2_df(float(q))
+
+
+def wc2_d2f(q):
+    return lib().orc_wc2_d2f(float(q))
+
+
+def kf(q, kernel=KERNEL_M4):
+    """f(q) of the chosen kernel (W = f(q)/(pi h^3))."""
+    return lib().orc_kf(int(kernel), float(q))
+
+
+def kdf(q, kernel=KERNEL_M4):
+    return lib().orc_kdf(int(kernel), float(q))
+
+
+def kd2f(q, kernel=KERNEL_M4):
+    return lib().orc_kd2f(int(kernel), float(q))
+
+
+def w(r, h, kernel=KERNEL_M4):
+    return lib().orc_wk(int(kernel), float(r), float(h))
+
+
+def dwdh(r, h, kernel=KERNEL_M4):
+    return lib().orc_dwdhk(int(kernel), float(r), float(h))
 
 
 # -------------------------------------------------------------------- density
 def density(x, y, z, level, h_in, *, m0, hfact=1.2, tol=1e-12, max_iter=50, periodic=False,
-            lo=(0, 0, 0), hi=(1, 1, 1), targets=None):
+            lo=(0, 0, 0), hi=(1, 1, 1), targets=None, kernel=KERNEL_M4):
     """h-rho Newton solve for every target (all particles if targets is None).
 
     h_in is indexed like the targets.  Returns a dict of per-target arrays
@@ -145,7 +182,7 @@ def density(x, y, z, level, h_in, *, m0, hfact=1.2, tol=1e-12, max_iter=50, peri
                               _p(tg, _i64), _p(h_in, _d), _p(out["h"], _d),
                               _p(out["rho"], _d), _p(out["omega"], _d),
                               _p(out["nneigh"], _i32), _p(out["dnn"], _d),
-                              _p(out["iters"], _i32))
+                              _p(out["iters"], _i32), int(kernel))
     out["failures"] = int(fails)
     return out
 
@@ -188,7 +225,7 @@ def eos(x, y, rho, u=None, *, eos, cs0=1.0, q_cs=0.25, r_ref=1.0, gamma=5.0 / 3.
 # --------------------------------------------------------------------- forces
 def forces(x, y, z, vx, vy, vz, u, level, h, rho, omega, *, m0, eos, cs0=1.0, q_cs=0.25,
            r_ref=1.0, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, lo=(0, 0, 0),
-           hi=(1, 1, 1), targets=None):
+           hi=(1, 1, 1), targets=None, kernel=KERNEL_M4):
     """Hydro acceleration, du/dt, vsig and the L1 bounds anorm, unorm per target."""
     arrs = [_f64(a) for a in (x, y, z, vx, vy, vz)]
     u = None if u is None else _f64(u)
@@ -203,7 +240,7 @@ def forces(x, y, z, vx, vy, vz, u, level, h, rho, omega, *, m0, eos, cs0=1.0, q_
                      _p(rho, _d), _p(omega, _d), m0, eos, cs0, q_cs, r_ref, gamma, alpha,
                      beta, int(bool(periodic)), _p(lo, _d), _p(hi, _d), nt, _p(tg, _i64),
                      *[_p(out[k], _d) for k in ("ax", "ay", "az", "dudt", "vsig", "anorm",
-                                                 "unorm")])
+                                                 "unorm")], int(kernel))
     return out
 
 

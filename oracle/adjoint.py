@@ -2,7 +2,8 @@
 
 Dense PyTorch CPU float64: every pair of particles is formed explicitly and
 masked by the kernel support, so this is only for a few thousand particles.
-The forward follows the same definitions as apr_oracle.c (M4 kernel, h-rho
+The forward follows the same definitions as apr_oracle.c (M4 or Wendland C2
+kernel, h-rho
 relation h = h_fact (m/rho)^(1/3), grad-h Omega, per-particle artificial
 viscosity, isothermal / locally isothermal / adiabatic EOS); the gradient is
 torch autograd of it.
@@ -32,6 +33,18 @@ def _m4(q):
     return f, df
 
 
+def _wc2(q):
+    """f, f' of the Wendland C2 kernel, 21/16 (1 - q/2)^4 (1 + 2q) (zero for q >= 2)."""
+    u = torch.clamp(1.0 - 0.5 * q, min=0.0)
+    f = (21.0 / 16.0) * u ** 4 * (1.0 + 2.0 * q)
+    df = -(105.0 / 16.0) * q * u ** 3
+    return f, df
+
+
+def _kern(q, kernel):
+    return _wc2(q) if kernel == 1 else _m4(q)
+
+
 def _pairs(x, periodic, L):
     d = x[:, None, :] - x[None, :, :]
     if periodic:
@@ -46,22 +59,23 @@ def _pairs(x, periodic, L):
     return d, r, eye
 
 
-def _rho_terms(r, h, m):
+def _rho_terms(r, h, m, kernel=0):
     """rho_sum(h) and sum_b m_b dW/dh for every a (h is per row a)."""
     q = r / h[:, None]
-    f, df = _m4(q)
+    f, df = _kern(q, kernel)
     hh = h[:, None]
     W = f / (PI * hh ** 3)
     dWdh = -(3.0 * f + q * df) / (PI * hh ** 4)
     return (m[None, :] * W).sum(1), (m[None, :] * dWdh).sum(1)
 
 
-def converge_h(x, m, h0, hfact=1.2, tol=1e-14, max_iter=100, periodic=False, L=(1, 1, 1)):
+def converge_h(x, m, h0, hfact=1.2, tol=1e-14, max_iter=100, periodic=False, L=(1, 1, 1),
+               kernel=0):
     with torch.no_grad():
         _, r, _ = _pairs(x, periodic, L)
         h = h0.clone()
         for _ in range(max_iter):
-            rs, drs = _rho_terms(r, h, m)
+            rs, drs = _rho_terms(r, h, m, kernel)
             rhoh = m * (hfact / h) ** 3
             F = rs - rhoh
             dF = drs + 3.0 * rhoh / h
@@ -87,25 +101,26 @@ def eos(x, rho, u, eos, cs0=1.0, q_cs=0.25, r_ref=1.0, gamma=5.0 / 3.0):
 
 
 def forward(x, m, v, u, h0, *, eos_kind, hfact=1.2, cs0=1.0, q_cs=0.25, r_ref=1.0,
-            gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, L=(1, 1, 1)):
+            gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, L=(1, 1, 1), kernel=0):
     """rho [n], a [n, 3], du/dt [n], h [n], Omega [n] as differentiable functions
-    of x [n, 3] and m [n] (v, u held fixed)."""
-    hs = converge_h(x.detach(), m.detach(), h0, hfact=hfact, periodic=periodic, L=L)
+    of x [n, 3] and m [n] (v, u held fixed).  kernel: 0 M4, 1 Wendland C2."""
+    hs = converge_h(x.detach(), m.detach(), h0, hfact=hfact, periodic=periodic, L=L,
+                    kernel=kernel)
     d, r, eye = _pairs(x, periodic, L)
     # implicit h: one Newton step from h* with F'(h*) held fixed
-    rs, drs = _rho_terms(r, hs, m)
+    rs, drs = _rho_terms(r, hs, m, kernel)
     rhoh = m * (hfact / hs) ** 3
     F = rs - rhoh
     dF = (drs + 3.0 * rhoh / hs).detach()
     h = hs - F / dF
-    rho, drho = _rho_terms(r, h, m)
+    rho, drho = _rho_terms(r, h, m, kernel)
     omega = 1.0 + h * drho / (3.0 * rho)
     P, c = eos(x, rho, u, eos_kind, cs0, q_cs, r_ref, gamma)
     # pair terms, b != a, r < 2 max(h_a, h_b)
     ha, hb = h[:, None], h[None, :]
     qa, qb = r / ha, r / hb
-    _, dfa = _m4(qa)
-    _, dfb = _m4(qb)
+    _, dfa = _kern(qa, kernel)
+    _, dfb = _kern(qb, kernel)
     Fa = dfa / (PI * ha ** 4)
     Fb = dfb / (PI * hb ** 4)
     rsafe = torch.where(eye, torch.ones_like(r), r)

@@ -62,15 +62,61 @@ double orc_m4_d2f(double q)
     return 0.0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Wendland C2 (Wendland 1995), 3D, compact support 2h: the kernel of the    */
+/* paper's example applications (Sec. 3, with h_fact = 1.3 and kernel       */
+/* radius 2h).  Written in the same form W = f(q)/(pi h^3):                 */
+/*   f(q) = 21/16 (1 - q/2)^4 (1 + 2 q)   0 <= q < 2,   0 for q >= 2         */
+/* The factor 21/16 normalises it: 4 int_0^2 q^2 (1 - q/2)^4 (1 + 2 q) dq    */
+/* = 16/21 (two Beta integrals after q = 2 s).                              */
+/* ------------------------------------------------------------------------ */
+double orc_wc2_f(double q)
+{
+    if (q >= 2.0) return 0.0;
+    double u = 1.0 - 0.5 * q;
+    return (21.0 / 16.0) * u * u * u * u * (1.0 + 2.0 * q);
+}
+
+/* df/dq = -105/16 q (1 - q/2)^3 */
+double orc_wc2_df(double q)
+{
+    if (q >= 2.0) return 0.0;
+    double u = 1.0 - 0.5 * q;
+    return -(105.0 / 16.0) * q * u * u * u;
+}
+
+/* d2f/dq2 = -105/16 (1 - q/2)^2 (1 - 2 q) */
+double orc_wc2_d2f(double q)
+{
+    if (q >= 2.0) return 0.0;
+    double u = 1.0 - 0.5 * q;
+    return -(105.0 / 16.0) * u * u * (1.0 - 2.0 * q);
+}
+
+/* Kernel choice: 0 = M4 cubic spline, 1 = Wendland C2 (both support 2h). */
+double orc_kf(int32_t kernel, double q) { return kernel == 1 ? orc_wc2_f(q) : orc_m4_f(q); }
+double orc_kdf(int32_t kernel, double q) { return kernel == 1 ? orc_wc2_df(q) : orc_m4_df(q); }
+double orc_kd2f(int32_t kernel, double q)
+{
+    return kernel == 1 ? orc_wc2_d2f(q) : orc_m4_d2f(q);
+}
+
 /* W(r, h) */
-double orc_w(double r, double h) { return orc_m4_f(r / h) / (ORC_PI * h * h * h); }
+double orc_wk(int32_t kernel, double r, double h)
+{
+    return orc_kf(kernel, r / h) / (ORC_PI * h * h * h);
+}
 
 /* dW/dh at fixed r:  -(3 f + q f') / (pi h^4) */
-double orc_dwdh(double r, double h)
+double orc_dwdhk(int32_t kernel, double r, double h)
 {
     double q = r / h;
-    return -(3.0 * orc_m4_f(q) + q * orc_m4_df(q)) / (ORC_PI * h * h * h * h);
+    return -(3.0 * orc_kf(kernel, q) + q * orc_kdf(kernel, q)) / (ORC_PI * h * h * h * h);
 }
+
+/* the M4 forms of the two above */
+double orc_w(double r, double h) { return orc_wk(0, r, h); }
+double orc_dwdh(double r, double h) { return orc_dwdhk(0, r, h); }
 
 /* Particle mass from the refinement level: m(l) = m(0) / 2^l
  * (paper, Sec. 2.1, rules 4 and 5 and the equation under them). */
@@ -113,7 +159,7 @@ int64_t orc_density(int64_t n, const double *x, const double *y, const double *z
                     int32_t max_iter, int32_t periodic, const double *lo, const double *hi,
                     int64_t nt, const int64_t *targets, const double *h_in,
                     double *h_out, double *rho, double *omega, int32_t *nneigh,
-                    double *dnn, int32_t *iters)
+                    double *dnn, int32_t *iters, int32_t kernel)
 {
     double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
     int64_t failures = 0;
@@ -139,8 +185,8 @@ int64_t orc_density(int64_t n, const double *x, const double *y, const double *z
                 if (!(r2 < R2)) continue;
                 double r = sqrt(r2);
                 double mb = pmass(m0, level[b]);
-                rs += mb * orc_w(r, h);
-                drs += mb * orc_dwdh(r, h);
+                rs += mb * orc_wk(kernel, r, h);
+                drs += mb * orc_dwdhk(kernel, r, h);
                 nn += 1;
                 if (b != a && r < dmin) dmin = r;
             }
@@ -262,7 +308,8 @@ void orc_forces(int64_t n, const double *x, const double *y, const double *z,
                 double m0, int32_t eos, double cs0, double q_cs, double r_ref, double gamma,
                 double alpha, double beta, int32_t periodic, const double *lo,
                 const double *hi, int64_t nt, const int64_t *targets, double *ax, double *ay,
-                double *az, double *dudt, double *vsig, double *anorm, double *unorm)
+                double *az, double *dudt, double *vsig, double *anorm, double *unorm,
+                int32_t kernel)
 {
     double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
 #pragma omp parallel for schedule(dynamic, 16)
@@ -288,8 +335,8 @@ void orc_forces(int64_t n, const double *x, const double *y, const double *z,
             if (r2 == 0.0) continue;
             double r = sqrt(r2);
             double rx = dx / r, ry = dy / r, rz = dz / r;
-            double Fa = ina ? orc_m4_df(r / ha) / (ORC_PI * ha * ha * ha * ha) : 0.0;
-            double Fb = inb ? orc_m4_df(r / hb) / (ORC_PI * hb * hb * hb * hb) : 0.0;
+            double Fa = ina ? orc_kdf(kernel, r / ha) / (ORC_PI * ha * ha * ha * ha) : 0.0;
+            double Fb = inb ? orc_kdf(kernel, r / hb) / (ORC_PI * hb * hb * hb * hb) : 0.0;
             double Pb, cb;
             orc_eos_one(eos, cs0, q_cs, r_ref, gamma, x[b], y[b], rho[b], u ? u[b] : 0.0,
                         &Pb, &cb);

@@ -9,9 +9,14 @@ import workloads as W
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _golden():
+# (kernel, h_fact, golden file): M4 at 1.2, Wendland C2 at 1.3
+KERNELS = [pytest.param((0, 1.2, "lattice_m4.txt"), id="m4"),
+           pytest.param((1, 1.3, "lattice_wc2.txt"), id="wc2")]
+
+
+def _golden(fname="lattice_m4.txt"):
     vals = {}
-    for l in open(os.path.join(GOLDEN, "lattice_m4.txt")):
+    for l in open(os.path.join(GOLDEN, fname)):
         if l.startswith("#") or not l.strip():
             continue
         k, v = l.split()
@@ -24,10 +29,11 @@ def _dens(orc, st, p, **kw):
                        periodic=p["periodic"], lo=p["lo"], hi=p["hi"], **kw)
 
 
-def test_lattice_closed_form(orc):
-    g = _golden()
+@pytest.mark.parametrize("kern", KERNELS)
+def test_lattice_closed_form(orc, kern):
+    g = _golden(kern[2])
     st, p = W.lattice_box()
-    d = _dens(orc, st, p, tol=1e-13)
+    d = _dens(orc, st, p, tol=1e-13, kernel=kern[0], hfact=kern[1])
     dx = 1.0 / 16
     assert d["failures"] == 0
     assert np.all(d["nneigh"] == int(g["nneigh_incl_self"]))
@@ -36,24 +42,28 @@ def test_lattice_closed_form(orc):
     assert np.max(np.abs(d["omega"] - g["omega"])) < 1e-9
     # every particle of a lattice is alike; nearest neighbour at dx
     assert np.max(np.abs(d["dnn"] - dx)) < 1e-15
-    # Newton from a guess 3e-4 off converges quadratically: 3 sums reach 1e-13
-    assert d["iters"].max() <= 4
+    # Newton from the guess 1.2 dx converges quadratically: M4 (3e-4 off)
+    # needs 3 sums to reach 1e-13, Wendland C2 (7e-2 off) a few more
+    assert d["iters"].max() <= (4 if kern[0] == 0 else 7)
 
 
-def test_lattice_fixed_h(orc):
-    # one Newton sum at h = 1.2 dx exactly (max_iter = 1 reports the first sums)
-    g = _golden()
+@pytest.mark.parametrize("kern", KERNELS)
+def test_lattice_fixed_h(orc, kern):
+    # one Newton sum at h = h_fact dx exactly (max_iter = 1 reports the first sums)
+    g = _golden(kern[2])
     st, p = W.lattice_box()
-    d = _dens(orc, st, p, max_iter=1)
-    assert np.max(np.abs(d["rho"] - g["rho_over_rho0_at_h1.2"])) < 1e-12
+    st = dict(st, h=np.full_like(st["h"], kern[1] / 16))
+    d = _dens(orc, st, p, max_iter=1, kernel=kern[0], hfact=kern[1])
+    assert np.max(np.abs(d["rho"] - g["rho_over_rho0_at_h%g" % kern[1]])) < 1e-12
 
 
-def test_h_rho_relation_holds(orc):
+@pytest.mark.parametrize("kern", KERNELS)
+def test_h_rho_relation_holds(orc, kern):
     st, p = W.shock_box(nside=12)
     p = dict(p, m0=1.0 / 12 ** 3)
-    d = _dens(orc, st, p, tol=1e-13)
+    d = _dens(orc, st, p, tol=1e-13, kernel=kern[0], hfact=kern[1])
     m = p["m0"] / 2.0 ** st["level"]
-    rel = np.abs(d["rho"] - m * (1.2 / d["h"]) ** 3) / d["rho"]
+    rel = np.abs(d["rho"] - m * (kern[1] / d["h"]) ** 3) / d["rho"]
     assert d["failures"] == 0 and rel.max() < 1e-11
 
 
@@ -83,15 +93,17 @@ def test_length_scaling(orc):
     assert np.max(np.abs(d1["rho"] * s ** 3 / d0["rho"] - 1)) < 1e-10
 
 
-def test_omega_matches_difference(orc):
+@pytest.mark.parametrize("kern", KERNELS)
+def test_omega_matches_difference(orc, kern):
     # Omega = 1 + h/(3 rho) d rho_sum/dh at fixed positions, by a central
     # difference of the density sum (max_iter = 1 evaluates the sum at h_in)
     st, p = W.shock_box(nside=10)
     p = dict(p, m0=1e-3)
-    d = _dens(orc, st, p, tol=1e-13)
+    kw = dict(kernel=kern[0], hfact=kern[1])
+    d = _dens(orc, st, p, tol=1e-13, **kw)
     e = 1e-7
-    up = _dens(orc, dict(st, h=d["h"] * (1 + e)), p, max_iter=1)
-    dn = _dens(orc, dict(st, h=d["h"] * (1 - e)), p, max_iter=1)
+    up = _dens(orc, dict(st, h=d["h"] * (1 + e)), p, max_iter=1, **kw)
+    dn = _dens(orc, dict(st, h=d["h"] * (1 - e)), p, max_iter=1, **kw)
     drho = (up["rho"] - dn["rho"]) / (2 * e * d["h"])
     om = 1.0 + d["h"] * drho / (3.0 * d["rho"])
     assert np.max(np.abs(om - d["omega"])) < 1e-6

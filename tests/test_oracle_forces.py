@@ -16,33 +16,36 @@ import pytest
 import workloads as W
 
 G = 5.0 / 3.0
+# (kernel, h_fact): M4 at 1.2, Wendland C2 at 1.3 (the paper's pairings)
+KERNELS = [pytest.param((0, 1.2), id="m4"), pytest.param((1, 1.3), id="wc2")]
 
 
-def _cluster(orc, n=216, levels=(0, 1), vscale=0.0, seed_k=101):
+def _cluster(orc, n=216, levels=(0, 1), vscale=0.0, seed_k=101, kern=(0, 1.2)):
     st, dx = W.random_cluster(n, seed_k=seed_k, levels=levels, vscale=vscale)
     d = orc.density(st["x"], st["y"], st["z"], st["level"], st["h"], m0=1.0, tol=1e-14,
-                    max_iter=60)
+                    max_iter=60, kernel=kern[0], hfact=kern[1])
     assert d["failures"] == 0
     return st, dx, d
 
 
-def _forces(orc, st, d, u, **kw):
+def _forces(orc, st, d, u, kern=(0, 1.2), **kw):
     kw.setdefault("eos", 2)
     kw.setdefault("gamma", G)
     return orc.forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], u, st["level"],
-                      d["h"], d["rho"], d["omega"], m0=1.0, **kw)
+                      d["h"], d["rho"], d["omega"], m0=1.0, kernel=kern[0], **kw)
 
 
-def test_pressure_force_is_energy_gradient(orc):
-    st, dx, d = _cluster(orc)
+@pytest.mark.parametrize("kern", KERNELS)
+def test_pressure_force_is_energy_gradient(orc, kern):
+    st, dx, d = _cluster(orc, kern=kern)
     m = 2.0 ** -st["level"].astype(float)
     K = np.random.default_rng(7).uniform(1.0, 2.0, st["x"].shape[0])
     u = K * d["rho"] ** (G - 1) / (G - 1)
-    f = _forces(orc, st, d, u, alpha=0.0, beta=0.0)
+    f = _forces(orc, st, d, u, kern, alpha=0.0, beta=0.0)
 
     def energy(pos):
         dd = orc.density(pos[0], pos[1], pos[2], st["level"], d["h"], m0=1.0, tol=1e-14,
-                         max_iter=60)
+                         max_iter=60, kernel=kern[0], hfact=kern[1])
         assert dd["failures"] == 0
         return np.sum(m * K * dd["rho"] ** (G - 1) / (G - 1))
 
@@ -57,25 +60,28 @@ def test_pressure_force_is_energy_gradient(orc):
             assert abs(m[a] * f[key][a] + dEdx) < 2e-6 * m[a] * f["anorm"][a]
 
 
-def test_dudt_is_pdv_work(orc):
-    st, dx, d = _cluster(orc, vscale=0.3)
+@pytest.mark.parametrize("kern", KERNELS)
+def test_dudt_is_pdv_work(orc, kern):
+    st, dx, d = _cluster(orc, vscale=0.3, kern=kern)
     u = np.random.default_rng(8).uniform(1.0, 2.0, st["x"].shape[0])
-    f = _forces(orc, st, d, u, alpha=0.0, beta=0.0)
+    f = _forces(orc, st, d, u, kern, alpha=0.0, beta=0.0)
     pos = np.array([st["x"], st["y"], st["z"]])
     vel = np.array([st["vx"], st["vy"], st["vz"]])
     e = 1e-6
-    rp = orc.density(*(pos + e * vel), st["level"], d["h"], m0=1.0, tol=1e-14, max_iter=60)
-    rm = orc.density(*(pos - e * vel), st["level"], d["h"], m0=1.0, tol=1e-14, max_iter=60)
+    kw = dict(m0=1.0, tol=1e-14, max_iter=60, kernel=kern[0], hfact=kern[1])
+    rp = orc.density(*(pos + e * vel), st["level"], d["h"], **kw)
+    rm = orc.density(*(pos - e * vel), st["level"], d["h"], **kw)
     drho = (rp["rho"] - rm["rho"]) / (2 * e)
     expect = (G - 1) * u / d["rho"] * drho
     assert np.max(np.abs(f["dudt"] - expect) / f["unorm"]) < 1e-6
 
 
-def test_conservation(orc):
-    st, dx, d = _cluster(orc, vscale=0.5)
+@pytest.mark.parametrize("kern", KERNELS)
+def test_conservation(orc, kern):
+    st, dx, d = _cluster(orc, vscale=0.5, kern=kern)
     m = 2.0 ** -st["level"].astype(float)
     u = np.random.default_rng(9).uniform(1.0, 2.0, st["x"].shape[0])
-    f = _forces(orc, st, d, u, alpha=1.0, beta=2.0)
+    f = _forces(orc, st, d, u, kern, alpha=1.0, beta=2.0)
     a = np.array([f["ax"], f["ay"], f["az"]])
     x = np.array([st["x"], st["y"], st["z"]])
     v = np.array([st["vx"], st["vy"], st["vz"]])
@@ -87,14 +93,15 @@ def test_conservation(orc):
     assert abs(dE) < 1e-14 * np.sum(m * (np.linalg.norm(v, axis=0) * f["anorm"] + f["unorm"]))
 
 
-def test_lattice_pressure_force_vanishes(orc):
+@pytest.mark.parametrize("kern", KERNELS)
+def test_lattice_pressure_force_vanishes(orc, kern):
     st, p = W.lattice_box()
     d = orc.density(st["x"], st["y"], st["z"], st["level"], st["h"], m0=p["m0"], periodic=True,
-                    lo=p["lo"], hi=p["hi"], tol=1e-13)
+                    lo=p["lo"], hi=p["hi"], tol=1e-13, kernel=kern[0], hfact=kern[1])
     z = np.zeros_like(st["x"])
     f = orc.forces(st["x"], st["y"], st["z"], z, z, z, None, st["level"], d["h"], d["rho"],
                    d["omega"], m0=p["m0"], eos=0, cs0=1.0, periodic=True, lo=p["lo"],
-                   hi=p["hi"])
+                   hi=p["hi"], kernel=kern[0])
     amax = np.max(np.abs([f["ax"], f["ay"], f["az"]]), axis=0)
     assert np.all(amax <= 1e-13 * f["anorm"])
     assert np.all(f["dudt"] == 0.0)
