@@ -20,8 +20,13 @@
  *    Sec. 2.1, rules 4 and 5).
  *  - "void *" arrays are float * when params.precision == APR_FP32 and
  *    double * when it is APR_FP64.
- *  - Kernel: M4 cubic spline with support 2h (paper appendix A, kernel table;
- *    h_fact = 1.2 there).
+ *  - Kernel (params.kernel): the M4 cubic spline (paper appendix A, kernel
+ *    table, h_fact = 1.2 there) or the Wendland C2 kernel that the paper's
+ *    example applications use (Sec. 3: kernel radius 2h, h_fact = 1.3).  Both
+ *    have support 2h and are written W(r, h) = f(r/h)/(pi h^3):
+ *      M4   f = 1 - 3/2 q^2 + 3/4 q^3 (q < 1),  1/4 (2 - q)^3 (1 <= q < 2)
+ *      WC2  f = 21/16 (1 - q/2)^4 (1 + 2 q)      (q < 2)
+ *    h_fact is params.hfact whichever the kernel; set 1.3 with Wendland C2.
  */
 #ifndef APR_H
 #define APR_H
@@ -45,6 +50,7 @@ enum {
 enum { APR_FP64 = 0, APR_FP32 = 1 };
 enum { APR_EOS_ISOTHERMAL = 0, APR_EOS_LOCALLY_ISOTHERMAL = 1, APR_EOS_ADIABATIC = 2 };
 enum { APR_SPLIT_TANGENTIAL = 0, APR_SPLIT_RANDOM = 1 };
+enum { APR_KERNEL_M4 = 0, APR_KERNEL_WC2 = 1 };
 
 typedef struct apr_ctx apr_ctx;
 
@@ -86,9 +92,10 @@ typedef struct {
 typedef struct {
     int32_t precision;  /* APR_FP64 or APR_FP32 (pair arithmetic and derived outputs) */
     int32_t eos;        /* APR_EOS_* */
-    double hfact;       /* h = hfact (m / rho)^(1/3); 1.2 for M4 */
+    double hfact;       /* h = hfact (m / rho)^(1/3); 1.2 for M4, 1.3 for Wendland C2 */
     double tol_h;       /* Newton stops when |dh| < tol_h h */
     int32_t max_iter;   /* Newton iterations per particle */
+    int32_t kernel;     /* APR_KERNEL_M4 or APR_KERNEL_WC2 (support 2h either way) */
     double cs0;         /* sound speed (isothermal) or its value at R = r_ref */
     double q_cs;        /* locally isothermal: cs = cs0 (R / r_ref)^-q_cs, R cylindrical */
     double r_ref;
@@ -108,7 +115,7 @@ typedef struct {
     double G;           /* gravitational constant for sinks */
 } apr_params;
 
-/* Fills *p with defaults: FP32, adiabatic, hfact 1.2, tol 1e-6, 50 iterations,
+/* Fills *p with defaults: FP32, M4 kernel, adiabatic, hfact 1.2, tol 1e-6, 50 iterations,
  * alpha 1, beta 2, gamma 5/3, r_sep 0.2, nn_cap 0.35, tangential, G = 1. */
 void apr_default_params(apr_params *p);
 

@@ -8,6 +8,7 @@ APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP, APR_
 APR_FP64, APR_FP32 = 0, 1
 APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL, APR_EOS_ADIABATIC = 0, 1, 2
 APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM = 0, 1
+APR_KERNEL_M4, APR_KERNEL_WC2 = 0, 1
 (APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP,
  APR_PROF_CAND, APR_PROF_N) = (0, 1, 2, 3, 4, 5, 6)
 
@@ -26,7 +27,8 @@ class AprError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eos", C.c_int32), ("hfact", C.c_double),
-                ("tol_h", C.c_double), ("max_iter", C.c_int32), ("cs0", C.c_double),
+                ("tol_h", C.c_double), ("max_iter", C.c_int32), ("kernel", C.c_int32),
+                ("cs0", C.c_double),
                 ("q_cs", C.c_double), ("r_ref", C.c_double), ("gamma", C.c_double),
                 ("av_alpha", C.c_double), ("av_beta", C.c_double), ("periodic", C.c_int32),
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("m0", C.c_double),

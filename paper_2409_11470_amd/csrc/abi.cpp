@@ -96,6 +96,7 @@ int check_params(const apr_params *p, std::string &why)
 {
     if (p->precision != APR_FP32 && p->precision != APR_FP64) return why = "precision", 1;
     if (p->eos < 0 || p->eos > 2) return why = "eos", 1;
+    if (p->kernel != APR_KERNEL_M4 && p->kernel != APR_KERNEL_WC2) return why = "kernel", 1;
     if (!(p->hfact > 0) || !(p->tol_h > 0) || p->max_iter < 1) return why = "hfact/tol/max_iter", 1;
     if (!(p->m0 > 0)) return why = "m0", 1;
     for (int k = 0; k < 3; ++k)
@@ -113,6 +114,7 @@ void apr_default_params(apr_params *p)
 {
     std::memset(p, 0, sizeof(*p));
     p->precision = APR_FP32;
+    p->kernel = APR_KERNEL_M4;
     p->eos = APR_EOS_ADIABATIC;
     p->hfact = 1.2;
     p->tol_h = 1e-6;

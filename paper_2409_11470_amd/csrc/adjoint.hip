@@ -22,6 +22,7 @@
 //   D_q m_p H_q) rhat with H = d2W/dr dh and Dbar = Omegabar h/(3 rho);
 //   m_p gets sum_q c_q W(r, h_q) + Dbar_q dW/dh(r, h_q), self term included.
 #include "gather.hpp"
+#include "sph_kernel.hpp"
 
 namespace apr {
 
@@ -41,19 +42,7 @@ struct VJPStage<double> {
     static constexpr int force = 256, dens = 512;
 };
 
-// M4: f, f', f'' from t = 2 - q, u = max(1 - q, 0) (0 <= q < 2).
-template <class T>
-__device__ inline void m4_all(T q, T &f, T &df, T &d2f)
-{
-    T t = T(2) - q;
-    T u = T(1) - q;
-    u = u > T(0) ? u : T(0);
-    f = T(0.25) * t * t * t - u * u * u;
-    df = T(3) * u * u - T(0.75) * t * t;
-    d2f = T(1.5) * t - T(6) * u;
-}
-
-template <class T>
+template <class T, int K>
 struct ForceVJP {
     static constexpr int NS = 4;
     using V = vec4_t<T>;
@@ -80,8 +69,8 @@ struct ForceVJP {
         T qp = r * hp, qq = r * hq;
         bool inp = qp < T(2), inq = qq < T(2);
         T fp, dfp, d2fp, fq, dfq, d2fq;
-        m4_all<T>(inp ? qp : T(2), fp, dfp, d2fp);
-        m4_all<T>(inq ? qq : T(2), fq, dfq, d2fq);
+        Kern<K>::template eval<T, 2>(inp ? qp : T(2), fp, dfp, d2fp);
+        Kern<K>::template eval<T, 2>(inq ? qq : T(2), fq, dfq, d2fq);
         T hp2 = hp * hp, hp4 = hp2 * hp2, hp5 = hp4 * hp;
         T hq2 = hq * hq, hq4 = hq2 * hq2, hq5 = hq4 * hq;
         T Fp = inp ? dfp * hp4 : T(0), Fpr = inp ? d2fp * hp5 : T(0);
@@ -138,7 +127,7 @@ struct ForceVJP {
     }
 };
 
-template <class T>
+template <class T, int K>
 struct DensVJP {
     static constexpr int NS = 2;
     using V = vec4_t<T>;
@@ -162,8 +151,8 @@ struct DensVJP {
         T qp = r * hp, qq = r * hq;
         bool inp = qp < T(2), inq = qq < T(2);
         T fp, dfp, d2fp, fq, dfq, d2fq;
-        m4_all<T>(inp ? qp : T(2), fp, dfp, d2fp);
-        m4_all<T>(inq ? qq : T(2), fq, dfq, d2fq);
+        Kern<K>::template eval<T, 2>(inp ? qp : T(2), fp, dfp, d2fp);
+        Kern<K>::template eval<T, 2>(inq ? qq : T(2), fq, dfq, d2fq);
         T hp2 = hp * hp, hp4 = hp2 * hp2, hp5 = hp4 * hp;
         T hq2 = hq * hq, hq3 = hq2 * hq, hq4 = hq2 * hq2, hq5 = hq4 * hq;
         T Fp = inp ? dfp * hp4 : T(0), Fq = inq ? dfq * hq4 : T(0);
@@ -184,27 +173,28 @@ struct DensVJP {
         for (int k = 0; k < 4; ++k) A.a[k].template reduce<kLanes>();
         if (!write) return;
         T hp = own[0].w;
-        double self = (double)own[1].x * (double)(hp * hp * hp) -
-                      3.0 * (double)own[1].y * (double)(hp * hp * hp * hp);
+        // self pair (r = 0): c W(0, h) + Dbar dW/dh(0, h), with f(0) of the kernel
+        double self = Kern<K>::f0 * ((double)own[1].x * (double)(hp * hp * hp) -
+                                     3.0 * (double)own[1].y * (double)(hp * hp * hp * hp));
         for (int k = 0; k < 3; ++k) xbar[k][i] = (T)(xb[k][i] + scx * A.a[k].value());
         mbar[i] = (T)(mb[i] + scm * (A.a[3].value() + self));
     }
 };
 
-template <class T, bool REST>
-__global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<T> op,
+template <class T, int K, bool REST>
+__global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<T, K> op,
                                                               CandList pre, int32_t *status,
                                                               int64_t first)
 {
-    gather_pairs<T, ForceVJP<T>, VJPStage<T>::force, REST>(tr, op, pre, status, -1, first);
+    gather_pairs<T, ForceVJP<T, K>, VJPStage<T>::force, REST>(tr, op, pre, status, -1, first);
 }
 
-template <class T, bool REST>
-__global__ __launch_bounds__(kSearchThreads) void k_vjp_dens(Tree tr, DensVJP<T> op,
+template <class T, int K, bool REST>
+__global__ __launch_bounds__(kSearchThreads) void k_vjp_dens(Tree tr, DensVJP<T, K> op,
                                                              CandList pre, int32_t *status,
                                                              int64_t first)
 {
-    gather_pairs<T, DensVJP<T>, VJPStage<T>::dens, REST>(tr, op, pre, status, -1, first);
+    gather_pairs<T, DensVJP<T, K>, VJPStage<T>::dens, REST>(tr, op, pre, status, -1, first);
 }
 
 template <class T>
@@ -231,6 +221,7 @@ struct LocalArgs {
     const double *x, *y, *u, *h;
     const int8_t *level;
     double m0, hfact, cs0, q_cs, r_ref, gamma;
+    double f0;  // f(0) of the kernel (the self pair)
     int eos, has_force;
 };
 
@@ -270,7 +261,7 @@ __global__ void k_vjp_local(LocalArgs a, const T *rho, const T *omega, const T *
         hb = sc * (double)f.p[7][i];
         S2 = sc * (double)f.p[8][i];
     }
-    S2 += 12.0 * m / (pi * h * h * h * h * h);  // self term of sum_q m_q d2W/dh2
+    S2 += 12.0 * a.f0 * m / (pi * h * h * h * h * h);  // self term of sum_q m_q d2W/dh2
     if (h_bar) hb += (double)h_bar[i];
     double Ob = -(Ptb * Pt + Gb * G) / om;
     double rb = (rho_bar ? (double)rho_bar[i] : 0.0) - (2.0 * Ptb * Pt + Gb * G) / r;
@@ -308,7 +299,7 @@ __global__ void k_vjp_local(LocalArgs a, const T *rho, const T *omega, const T *
     dv[i] = o;
 }
 
-template <class T>
+template <class T, int K>
 int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
           const void *rho_bar, const void *h_bar, const void *ax_bar, const void *ay_bar, const void *az_bar,
           const void *dudt_bar, void *xbar, void *ybar, void *zbar, void *mbar)
@@ -342,7 +333,7 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
         hipLaunchKernelGGL(k_pack_cot<T>, dim3(g), dim3(256), 0, c->stream, n,
                            (const T *)ax_bar, (const T *)ay_bar, (const T *)az_bar,
                            (const T *)dudt_bar, cot);
-        ForceVJP<T> op;
+        ForceVJP<T, K> op;
         op.pm = pm;
         op.vh = vh;
         op.th = th;
@@ -350,9 +341,9 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
         op.alpha = (T)p.av_alpha;
         op.beta = (T)p.av_beta;
         for (int k = 0; k < 9; ++k) op.out[k] = fout[k];
-        hipLaunchKernelGGL((k_vjp_force<T, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+        hipLaunchKernelGGL((k_vjp_force<T, K, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
                            c->stream, tr, op, pre, c->d_status, (int64_t)0);
-        hipLaunchKernelGGL((k_vjp_force<T, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+        hipLaunchKernelGGL((k_vjp_force<T, K, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
                            c->stream, tr, op, pre, c->d_status, grid);
         APR_LAUNCHED(c);
     }
@@ -376,12 +367,13 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     la.q_cs = p.q_cs;
     la.r_ref = p.r_ref;
     la.gamma = p.gamma;
+    la.f0 = Kern<K>::f0;
     la.eos = p.eos;
     la.has_force = has_force;
     hipLaunchKernelGGL(k_vjp_local<T>, dim3(g), dim3(256), 0, c->stream, la, (const T *)rho,
                        (const T *)omega, (const T *)rho_bar, (const T *)h_bar, fp, xb[0], xb[1], xb[2], mb, dv);
     APR_LAUNCHED(c);
-    DensVJP<T> dop;
+    DensVJP<T, K> dop;
     dop.pm = pm;
     dop.dv = dv;
     for (int k = 0; k < 3; ++k) dop.xb[k] = xb[k];
@@ -392,9 +384,9 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     dop.xbar[1] = (T *)ybar;
     dop.xbar[2] = (T *)zbar;
     dop.mbar = (T *)mbar;
-    hipLaunchKernelGGL((k_vjp_dens<T, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+    hipLaunchKernelGGL((k_vjp_dens<T, K, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
                        c->stream, tr, dop, pre, c->d_status, (int64_t)0);
-    hipLaunchKernelGGL((k_vjp_dens<T, true>), dim3(kRestGrid), dim3(kSearchThreads), 0, c->stream,
+    hipLaunchKernelGGL((k_vjp_dens<T, K, true>), dim3(kRestGrid), dim3(kSearchThreads), 0, c->stream,
                        tr, dop, pre, c->d_status, grid);
     APR_LAUNCHED(c);
     return APR_OK;
@@ -411,11 +403,11 @@ int vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, cons
         return fail(c, APR_ERR_INVALID, "null argument");
     if (c->p.eos == APR_EOS_ADIABATIC && !s->u) return fail(c, APR_ERR_INVALID, "u is required");
     int tok = prof_begin(c, APR_PROF_VJP);
-    int rc = c->p.precision == APR_FP32
-                 ? vjp_t<float>(c, s, rho, omega, rho_bar, h_bar, ax_bar, ay_bar, az_bar, dudt_bar,
-                                xbar, ybar, zbar, mbar)
-                 : vjp_t<double>(c, s, rho, omega, rho_bar, h_bar, ax_bar, ay_bar, az_bar, dudt_bar,
-                                 xbar, ybar, zbar, mbar);
+    const bool f32 = c->p.precision == APR_FP32, wc2 = c->p.kernel == APR_KERNEL_WC2;
+    auto run = f32 ? (wc2 ? vjp_t<float, kWC2> : vjp_t<float, kM4>)
+                   : (wc2 ? vjp_t<double, kWC2> : vjp_t<double, kM4>);
+    int rc = run(c, s, rho, omega, rho_bar, h_bar, ax_bar, ay_bar, az_bar, dudt_bar, xbar, ybar,
+                 zbar, mbar);
     prof_end(c, tok);
     return rc;
 }

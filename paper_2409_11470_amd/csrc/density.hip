@@ -12,11 +12,9 @@
 // taken at.  If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is
 // clamped to [h/2, 2h].
 //
-// M4 kernel, W = f(q)/(pi h^3), q = r/h:
-//   f  = 1 - 3/2 q^2 + 3/4 q^3 (q < 1),  1/4 (2-q)^3 (1 <= q < 2)
-//   3f + q f' = 3 - 15/2 q^2 + 9/2 q^3 (q < 1),  3/2 (2-q)^2 (1-q) (1 <= q < 2)
-// so dW/dh = -(3f + q f')/(pi h^4).  Sums carry the normalised mass 2^-level;
-// m0/pi is applied once in FP64.
+// Kernel (M4 or Wendland C2, support 2h, a template parameter): W = f(q)/(pi h^3),
+// q = r/h, so dW/dh = -(3f + q f')/(pi h^4).  Sums carry the normalised mass
+// 2^-level; m0/pi is applied once in FP64.
 //
 // Pair arithmetic in T (float: cell-relative coordinates, Kahan-compensated
 // sums; double: the same code in FP64).  The Newton update and its
@@ -31,6 +29,7 @@
 // again with the larger radius (bounded: h at most doubles per Newton step,
 // max_iter).
 #include "search.hpp"
+#include "sph_kernel.hpp"
 
 namespace apr {
 
@@ -68,37 +67,8 @@ struct DensArgs {
     int32_t *status;
 };
 
-// f and 3f + q f' of the M4 kernel, branch-free in q (0 <= q < 2), from
-// t = 2 - q and u = max(1 - q, 0):  f = t^3/4 - u^3,  f' = -3/4 t^2 + 3 u^2.
-template <class T>
-__device__ inline void m4_fg(T q, T &f, T &g)
-{
-    T t = T(2) - q;
-    T u = T(1) - q;
-    u = u > T(0) ? u : T(0);
-    T t2 = t * t, u2 = u * u;
-    f = T(0.25) * t2 * t - u2 * u;
-    T df = T(3) * u2 - T(0.75) * t2;
-    g = T(3) * f + q * df;
-}
-
-// ... and 12 f + 8 q f' + q^2 f'' (h^5 pi d2W/dh2), with f'' = 3/2 t - 6 u.
-template <class T>
-__device__ inline void m4_fgk(T q, T &f, T &g, T &k)
-{
-    T t = T(2) - q;
-    T u = T(1) - q;
-    u = u > T(0) ? u : T(0);
-    T t2 = t * t, u2 = u * u;
-    f = T(0.25) * t2 * t - u2 * u;
-    T df = T(3) * u2 - T(0.75) * t2;
-    T ddf = T(1.5) * t - T(6) * u;
-    g = T(3) * f + q * df;
-    k = T(12) * f + q * (T(8) * df + q * ddf);
-}
-
-// Per-lane partial sums of one Newton evaluation.
-template <class T>
+// Per-lane partial sums of one Newton evaluation (kernel K).
+template <class T, int K>
 struct DSum {
     Acc<T> w, d, k;  // sum m f, sum m (3f + q f'), sum m (12 f + 8 q f' + q^2 f'')
     int cnt;       // neighbours in the low 16 bits, those at r = 0 above
@@ -116,8 +86,11 @@ struct DSum {
         T r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < R2) {
             T r = psqrt(r2);
-            T f, g, kk;
-            m4_fgk<T>(r * hinv, f, g, kk);
+            const T q = r * hinv;
+            T f, df, d2f;
+            Kern<K>::template eval<T, 2>(q, f, df, d2f);
+            const T g = T(3) * f + q * df;
+            const T kk = T(12) * f + q * (T(8) * df + q * d2f);
             w.add(m * f);
             d.add(m * g);
             k.add(m * kk);
@@ -193,7 +166,7 @@ __device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
     }
 }
 
-template <class T>
+template <class T, int K>
 __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t cell)
 {
     using V = vec4_t<T>;
@@ -265,7 +238,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     bool lists = false;    // per-target lists valid (single chunk and window only)
     int nc = 0, total = 0, nwin = 1;
     for (int pass = 0; pass <= a.max_iter; ++pass) {
-        DSum<T> S;
+        DSum<T, K> S;
         S.zero();
         const bool wave_busy = __any(!done);
         const bool walking = search || multi;
@@ -512,22 +485,38 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
 // host's estimate of the cell count; a second launch (REST) strides over any
 // cells from `first` on, nearly always none.  Two kernels rather than one
 // loop: a loop around the search body costs it registers.
-template <class T, bool REST>
+template <class T, int K, bool REST>
 __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(DensArgs<T> a,
                                                                               int64_t first)
 {
     const int64_t nc = a.tree.hdr->ncells;
     if (!REST) {
         const int64_t cell = first_cell(blockIdx.x, gridDim.x, nc);
-        if (cell >= 0) density_cell<T>(a, cell);
+        if (cell >= 0) density_cell<T, K>(a, cell);
         return;
     }
     for (int64_t cell = first + blockIdx.x; cell < nc; cell += gridDim.x) {
-        density_cell<T>(a, cell);
+        density_cell<T, K>(a, cell);
         __syncthreads();  // the next cell reuses the LDS
     }
 }
 
+template <class T, int K>
+void launch_density_k(apr_ctx *c, const DensArgs<T> &a, int64_t grid, int tok)
+{
+    hipLaunchKernelGGL((k_density<T, K, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+                       c->stream, a, (int64_t)0);
+    prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
+    hipLaunchKernelGGL((k_density<T, K, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                       c->stream, a, grid);
+}
+
+template <class T>
+void launch_density(apr_ctx *c, const DensArgs<T> &a, int64_t grid, int tok)
+{
+    if (c->p.kernel == APR_KERNEL_WC2) launch_density_k<T, kWC2>(c, a, grid, tok);
+    else launch_density_k<T, kM4>(c, a, grid, tok);
+}
 
 }  // namespace
 
@@ -578,11 +567,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
-        hipLaunchKernelGGL((k_density<float, false>), dim3((unsigned)grid), dim3(kSearchThreads),
-                           0, c->stream, a, (int64_t)0);
-        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
-        hipLaunchKernelGGL((k_density<float, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
-                           c->stream, a, grid);
+        launch_density(c, a, grid, tok);
     } else {
         DensArgs<double> a;
         a.tree = tr;
@@ -601,11 +586,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
-        hipLaunchKernelGGL((k_density<double, false>), dim3((unsigned)grid), dim3(kSearchThreads),
-                           0, c->stream, a, (int64_t)0);
-        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
-        hipLaunchKernelGGL((k_density<double, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
-                           c->stream, a, grid);
+        launch_density(c, a, grid, tok);
     }
     APR_LAUNCHED(c);
     int rc = set_hmax_new(c, hmax_new);  // cells' and tree nodes' h_max for the force search

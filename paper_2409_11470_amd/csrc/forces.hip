@@ -6,12 +6,13 @@
 //   A_ab = (P_a + q^a_ab)/(Omega_a rho_a^2),  B_ab = (P_b + q^b_ab)/(Omega_b rho_b^2)
 //   q^a_ab = -1/2 rho_a vsig_a (v_ab . rhat) if v_ab . rhat < 0 else 0,
 //   vsig_a = alpha c_a + beta |v_ab . rhat|
-//   F_ab(h) = f'(r/h)/(pi h^4) for r < 2h else 0,  f' = -3q + 9/4 q^2 (q < 1),
-//   -3/4 (2-q)^2 (1 <= q < 2)
+//   F_ab(h) = f'(r/h)/(pi h^4) for r < 2h else 0, f' of the M4 or the
+//   Wendland C2 kernel (a template parameter)
 // over pairs b != a with r < 2 max(h_a, h_b); r = 0 pairs add nothing.
 // With Pt = P/(Omega rho^2) and G = 1/(Omega rho) per particle:
 //   A_ab = Pt_a - 1/2 G_a vsig_a (v.rhat) for approaching pairs, else Pt_a.
 #include "gather.hpp"
+#include "sph_kernel.hpp"
 
 namespace apr {
 
@@ -65,18 +66,17 @@ __global__ void k_eos(int64_t n, int eos, double cs0, double q_cs, double r_ref,
     th[i] = b;
 }
 
-// f'(q) of the M4 kernel, branch-free (0 <= q < 2): -3/4 (2-q)^2 + 3 max(1-q, 0)^2.
-template <class T>
-__device__ inline T m4_df(T q)
+// f'(q) of kernel K (0 <= q <= 2)
+template <class T, int K>
+__device__ inline T kern_df(T q)
 {
-    T t = T(2) - q;
-    T u = T(1) - q;
-    u = u > T(0) ? u : T(0);
-    return T(3) * u * u - T(0.75) * t * t;
+    T f, df, d2f;
+    Kern<K>::template eval<T, 1>(q, f, df, d2f);
+    return df;
 }
 
 // The force sum as a gather: staged arrays pm, vh = (v, 1/h), th = (Pt, G, c, 0).
-template <class T>
+template <class T, int K>
 struct ForceOp {
     static constexpr int NS = 3;
     using V = vec4_t<T>;
@@ -109,8 +109,8 @@ struct ForceOp {
         bool inb = r2 * hb2 < T(4);
         T rinv = prsqrt(r2);
         T r = r2 * rinv;
-        T Fa = ina ? m4_df<T>(r * A.hi) * A.hi4 : T(0);
-        T Fb = inb ? m4_df<T>(r * hb) * (hb2 * hb2) : T(0);
+        T Fa = ina ? kern_df<T, K>(r * A.hi) * A.hi4 : T(0);
+        T Fb = inb ? kern_df<T, K>(r * hb) * (hb2 * hb2) : T(0);
         T vdr = ((own[1].x - nb[1].x) * dx + (own[1].y - nb[1].y) * dy +
                  (own[1].z - nb[1].z) * dz) * rinv;
         T Aa = own[2].x, Bb = nb[2].x;
@@ -149,13 +149,51 @@ struct ForceOp {
     }
 };
 
-template <class T, bool REST>
-__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree tr, ForceOp<T> op,
-                                                           CandList pre, int32_t *status,
-                                                           int64_t first)
+template <class T, int K, bool REST>
+__global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree tr,
+                                                                             ForceOp<T, K> op,
+                                                                             CandList pre,
+                                                                             int32_t *status,
+                                                                             int64_t first)
 {
-    gather_pairs<T, ForceOp<T>, FStageCap<T>::value, REST>(tr, op, pre, status, ST_FORCE_DIRECT,
-                                                           first);
+    gather_pairs<T, ForceOp<T, K>, FStageCap<T>::value, REST>(tr, op, pre, status,
+                                                              ST_FORCE_DIRECT, first);
+}
+
+template <class T, int K>
+void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
+                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv)
+{
+    using V = vec4_t<T>;
+    const bool f32 = std::is_same<T, float>::value;
+    ForceOp<T, K> op;
+    op.pm = wsa<V>(c, f32 ? "pm32" : "pm64", (size_t)n);
+    op.vh = wsa<V>(c, f32 ? "vh32" : "vh64", (size_t)n);
+    op.th = wsa<V>(c, f32 ? "th32" : "th64", (size_t)n);
+    op.ax = (T *)ax;
+    op.ay = (T *)ay;
+    op.az = (T *)az;
+    op.dudt = (T *)dudt;
+    op.vsig = (T *)vsig;
+    op.divv = divv;
+    op.m0 = c->p.m0;
+    op.alpha = (T)c->p.av_alpha;
+    op.beta = (T)c->p.av_beta;
+    hipLaunchKernelGGL((k_forces<T, K, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
+                       c->stream, tr, op, pre, c->d_status, (int64_t)0);
+    prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
+    hipLaunchKernelGGL((k_forces<T, K, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                       c->stream, tr, op, pre, c->d_status, grid);
+}
+
+template <class T>
+void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
+                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv)
+{
+    if (c->p.kernel == APR_KERNEL_WC2)
+        launch_forces<T, kWC2>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+    else
+        launch_forces<T, kM4>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
 }
 
 }  // namespace
@@ -205,35 +243,10 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     rc = cand_pre(c, tr, true, 2.0, &pre);
     if (rc) return rc;
     int tok = prof_begin(c, APR_PROF_FORCES);
-    if (p.precision == APR_FP32) {
-        ForceOp<float> op;
-        op.pm = wsa<float4>(c, "pm32", (size_t)n);
-        op.vh = wsa<float4>(c, "vh32", (size_t)n);
-        op.th = wsa<float4>(c, "th32", (size_t)n);
-        op.ax = (float *)ax; op.ay = (float *)ay; op.az = (float *)az;
-        op.dudt = (float *)dudt; op.vsig = (float *)vsig;
-        op.divv = divv;
-        op.m0 = p.m0; op.alpha = (float)p.av_alpha; op.beta = (float)p.av_beta;
-        hipLaunchKernelGGL((k_forces<float, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, pre, c->d_status, (int64_t)0);
-        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
-        hipLaunchKernelGGL((k_forces<float, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, pre, c->d_status, grid);
-    } else {
-        ForceOp<double> op;
-        op.pm = wsa<double4>(c, "pm64", (size_t)n);
-        op.vh = wsa<double4>(c, "vh64", (size_t)n);
-        op.th = wsa<double4>(c, "th64", (size_t)n);
-        op.ax = (double *)ax; op.ay = (double *)ay; op.az = (double *)az;
-        op.dudt = (double *)dudt; op.vsig = (double *)vsig;
-        op.divv = divv;
-        op.m0 = p.m0; op.alpha = p.av_alpha; op.beta = p.av_beta;
-        hipLaunchKernelGGL((k_forces<double, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, pre, c->d_status, (int64_t)0);
-        prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
-        hipLaunchKernelGGL((k_forces<double, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
-                           c->stream, tr, op, pre, c->d_status, grid);
-    }
+    if (p.precision == APR_FP32)
+        launch_forces<float>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+    else
+        launch_forces<double>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
     APR_LAUNCHED(c);
     c->force_n = n;
     c->divv_n = n;

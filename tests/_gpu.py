@@ -15,7 +15,7 @@ def params_for(p, precision, tol=None, **kw):
              hfact=float(p.get("hfact", 1.2)), cs0=float(p.get("cs0", 1.0)),
              q_cs=float(p.get("q_cs", 0.25)), r_ref=float(p.get("r_ref", 1.0)),
              gamma=float(p.get("gamma", 5.0 / 3.0)), av_alpha=float(p.get("alpha", 1.0)),
-             av_beta=float(p.get("beta", 2.0)), max_iter=60,
+             av_beta=float(p.get("beta", 2.0)), max_iter=60, kernel=int(p.get("kernel", 0)),
              tol_h=tol if tol is not None else (1e-6 if precision == "fp32" else 1e-12))
     d.update(kw)
     return A.make_params(**d)
@@ -67,7 +67,8 @@ def oracle_density(st, p, tol=1e-12, targets=None, h_in=None):
     return oracle.density(st["x"], st["y"], st["z"], st["level"], h0, m0=p["m0"],
                           hfact=p.get("hfact", 1.2), tol=tol, max_iter=60,
                           periodic=p.get("periodic", False), lo=p.get("lo", (0, 0, 0)),
-                          hi=p.get("hi", (1, 1, 1)), targets=targets)
+                          hi=p.get("hi", (1, 1, 1)), targets=targets,
+                          kernel=int(p.get("kernel", 0)))
 
 
 def oracle_forces(st, p, h, rho, omega, targets=None):
@@ -77,7 +78,8 @@ def oracle_forces(st, p, h, rho, omega, targets=None):
                          r_ref=p.get("r_ref", 1.0), gamma=p.get("gamma", 5.0 / 3.0),
                          alpha=p.get("alpha", 1.0), beta=p.get("beta", 2.0),
                          periodic=p.get("periodic", False), lo=p.get("lo", (0, 0, 0)),
-                         hi=p.get("hi", (1, 1, 1)), targets=targets)
+                         hi=p.get("hi", (1, 1, 1)), targets=targets,
+                         kernel=int(p.get("kernel", 0)))
 
 
 def sample_balls(st, p, nballs, ntarget, seed, hscale):
@@ -151,7 +153,7 @@ def oracle_balls(st, p, nballs, ntarget, seed, tol=1e-12, forces=True, safety=1.
     loc[Sg] = np.arange(Sg.shape[0])
     sub = {k: st[k][Sg] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level")}
     kw = dict(m0=p["m0"], hfact=p.get("hfact", 1.2), periodic=per, lo=tuple(lo),
-              hi=tuple(lo + L))
+              hi=tuple(lo + L), kernel=int(p.get("kernel", 0)))
     o = oracle.density(sub["x"], sub["y"], sub["z"], sub["level"], sub["h"][loc[Ig]], tol=tol,
                        max_iter=60, targets=loc[Ig], **kw)
     assert np.all(o["h"] <= safety * st["h"][Ig]), "a solved h exceeds its bound"

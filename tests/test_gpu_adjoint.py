@@ -55,7 +55,8 @@ def _oracle_grads(st, p, cot):
                                     hfact=p["hfact"], cs0=p["cs0"], q_cs=p.get("q_cs", 0.25),
                                     r_ref=p.get("r_ref", 1.0), gamma=p["gamma"],
                                     alpha=p["alpha"], beta=p["beta"],
-                                    periodic=p["periodic"], L=L)
+                                    periodic=p["periodic"], L=L,
+                                    kernel=int(p.get("kernel", 0)))
     loss = ((_t(cot["rho"]) * rho).sum() + (_t(cot["h"]) * h).sum()
             + (_t(cot["a"]) * a).sum() + (_t(cot["du"]) * du).sum())
     gx, gm = torch.autograd.grad(loss, (x, m))
