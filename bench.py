@@ -17,7 +17,8 @@ value = interactions per step * steps / wall time of the timed steps.
 
 The same run times the rest of the path on the other workloads ("legs"): the
 refined box (one split pass over 262144 particles, then density + forces +
-adjoint on the 362k-particle result, both forms), the 1M-particle planet disc
+adjoint on the 362k-particle result, both forms), the same box and step with
+the Wendland C2 kernel (h_fact 1.3, FP32 form), the 1M-particle planet disc
 stepped with its refinement zone (every step: cells, density, split/merge,
 forces, sink gravity, leapfrog) and the 8M-particle circumbinary disc (FP32
 density + forces + adjoint).
@@ -56,7 +57,7 @@ FLOP_FORCE_PAIR = 59
 # with the digest of the kernel's sources at the time; reported only while the
 # sources are unchanged.
 MEASURED_TRAFFIC = {
-    "k_density<float, false>": dict(
+    "k_density<float, 0, false>": dict(
         bytes_per_launch=33875673,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
@@ -85,7 +86,8 @@ def make_ctx(A, p, precision, seed=7):
     return A.Context(A.make_params(
         precision=A.APR_FP32 if precision == "fp32" else A.APR_FP64, eos=int(p["eos"]),
         periodic=int(p["periodic"]), box_lo=p["lo"], box_hi=p["hi"], m0=p["m0"],
-        hfact=p["hfact"], gamma=p["gamma"], cs0=p["cs0"], q_cs=p.get("q_cs", 0.25),
+        hfact=p["hfact"], kernel=int(p.get("kernel", 0)), gamma=p["gamma"], cs0=p["cs0"],
+        q_cs=p.get("q_cs", 0.25),
         r_ref=p.get("r_ref", 1.0), av_alpha=p["alpha"], av_beta=p["beta"],
         tol_h=1e-6 if precision == "fp32" else 1e-12, max_iter=60,
         r_sep_factor=p.get("r_sep_factor", 0.2), nn_cap=p.get("nn_cap", 0.0),
@@ -266,6 +268,20 @@ def leg_refine_box(A, torch, W, reps):
     return out
 
 
+def leg_wendland_box(A, torch, W, steps, warmup):
+    """The benchmarked box and step with the Wendland C2 kernel at h_fact 1.3
+    (the kernel of the paper's example applications), FP32 form."""
+    st, p = W.shock_box()
+    p = dict(p, kernel=1, hfact=1.3)
+    r = run_form(A, torch, st, p, "fp32", steps, warmup)
+    out = dict(workload="periodic shock box, 64^3 = 262144 particles, as the headline, "
+                        "Wendland C2 kernel, h_fact 1.3", form="fp32", steps=steps)
+    out.update({k: r[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms",
+                                  "cells_ms", "interactions_per_step", "density_pairs",
+                                  "force_pairs", "density_force_rate", "failures")})
+    return out
+
+
 def leg_circumbinary(A, torch, W, reps):
     """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint."""
     st, p = W.circumbinary_disc()
@@ -339,10 +355,10 @@ def main():
     # roofline of the dominant kernel of the FP32 form (plain VALU arithmetic)
     n = r32["n"]
     if r32["density_ms"] >= r32["forces_ms"]:
-        kern, ms = "k_density<float, false>", r32["density_ms"]
+        kern, ms = "k_density<float, 0, false>", r32["density_ms"]
         flops = FLOP_DENSITY_PAIR * (r32["density_pairs"] + n)
     else:
-        kern, ms = "k_forces<float, false>", r32["forces_ms"]
+        kern, ms = "k_forces<float, 0, false>", r32["forces_ms"]
         flops = FLOP_FORCE_PAIR * r32["force_pairs"]
     achieved = flops / (ms * 1e-3) / 1e12
     traffic = measured_traffic(kern)
@@ -359,6 +375,9 @@ def main():
         log("refined box: split %.2f ms, fp32 adjoint %.3e interactions/s"
             % (legs["refine_box_split_adjoint"]["split_pass_ms"],
                legs["refine_box_split_adjoint"]["fp32"]["adjoint_rate"]))
+        legs["wendland_c2_box"] = leg_wendland_box(A, torch, W, 10, 3)
+        log("wendland c2 box: %.3e interactions/s, %.3f ms/step"
+            % (legs["wendland_c2_box"]["value"], legs["wendland_c2_box"]["ms_per_step"]))
         legs["planet_disc_steps"] = leg_planet_disc(A, torch, W, 10)
         log("planet disc: %.3e interactions/s, %.2f ms/step"
             % (legs["planet_disc_steps"]["value"], legs["planet_disc_steps"]["ms_per_step"]))
