@@ -78,14 +78,14 @@ def lib():
         L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_zone_level.restype = C.c_int32
         L.orc_zone_level.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, _d, _i32,
-                                     _d, _i32, C.c_int32, C.c_int32]
+                                     _d, _i32, _i32, C.c_int32, C.c_int32]
         L.orc_pair_tree.restype = C.c_int64
         L.orc_pair_tree.argtypes = [C.c_int64, _i64, _d, _d, _d, _i64, _d, _d, C.c_int64,
                                     _i64]
         L.orc_split_merge.restype = C.c_int32
         L.orc_split_merge.argtypes = [C.c_int64, C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d,
                                       _i8, _i64, _i64, _d, C.c_int32, _d, _i32, _d, _i32,
-                                      C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      _i32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       C.c_int32, C.c_uint64, C.c_int64, C.c_int32, _d, _d,
                                       C.c_int32, C.c_int32, _i64, _i64, _i64, _i64]
         _LIB = L
@@ -282,6 +282,7 @@ def _zones_arrays(zones):
     zn = np.zeros(max(nz, 1), np.int32)
     zr = np.zeros((max(nz, 1), 8))
     ze = np.zeros((max(nz, 1), 8), np.int32)
+    zs = np.zeros(max(nz, 1), np.int32)
     for k, zd in enumerate(zones):
         zc[k] = zd["c"]
         rr = list(zd["r"])
@@ -289,14 +290,17 @@ def _zones_arrays(zones):
         zn[k] = len(rr)
         zr[k, :len(rr)] = rr
         ze[k, :len(ll)] = ll
-    return nz, zc, zn, zr, ze
+        zs[k] = int(zd.get("shape", 0))
+    return nz, zc, zn, zr, ze, zs
 
 
 def zone_level(x, y, z, zones, background=0, derefine=False):
-    nz, zc, zn, zr, ze = _zones_arrays(zones)
+    """Refinement level at a point; a zone dict may set shape=1 (cylinders
+    along z through c instead of spheres)."""
+    nz, zc, zn, zr, ze, zs = _zones_arrays(zones)
     return int(lib().orc_zone_level(float(x), float(y), float(z), nz, _p(zc, _d),
-                                    _p(zn, _i32), _p(zr, _d), _p(ze, _i32), background,
-                                    int(bool(derefine))))
+                                    _p(zn, _i32), _p(zr, _d), _p(ze, _i32), _p(zs, _i32),
+                                    background, int(bool(derefine))))
 
 
 def pair_tree(cand, x, y, z, ids, lo, hi):
@@ -332,14 +336,15 @@ def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_m
     ids = np.zeros(cap, np.int64)
     ids[:n] = st["id"]
     nid = C.c_int64(int(st["next_id"]))
-    nz, zc, zn, zr, ze = _zones_arrays(zones)
+    nz, zc, zn, zr, ze, zs = _zones_arrays(zones)
     lo, hi = _box(lo, hi)
     dn = None if dnn is None else _f64(dnn)
     n_out, ns, nm, nsp = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
     rc = lib().orc_split_merge(n, cap, *[_p(w[k], _d) for k in ("x", "y", "z", "vx", "vy", "vz",
                                                                  "u", "h")],
                                _p(lev, _i8), _p(ids, _i64), C.byref(nid), _p(dn, _d), nz,
-                               _p(zc, _d), _p(zn, _i32), _p(zr, _d), _p(ze, _i32), background,
+                               _p(zc, _d), _p(zn, _i32), _p(zr, _d), _p(ze, _i32),
+                               _p(zs, _i32), background,
                                int(bool(derefine)), r_sep_factor, nn_cap, split_mode,
                                C.c_uint64(seed & (2**64 - 1)), step, int(bool(periodic)),
                                _p(lo, _d), _p(hi, _d), int(bool(do_split)),

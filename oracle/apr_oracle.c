@@ -459,6 +459,10 @@ static double u53(uint64_t v) { return (double)(v >> 11) * 0x1.0p-53; }
 /* (refinement, background level 0) or by min (derefinement, background     */
 /* l_max) (paper Sec. 2.1, rule 3).  *which is the first zone that gives    */
 /* the combined level from one of its spheres, or -1.                       */
+/* A zone of shape 1 is made of cylinders about the z axis through c        */
+/* instead of spheres: the distance drops its z component.  The paper's     */
+/* sound-wave test refines a circle in the x-y plane of a thin box (its     */
+/* appendix A), which is such a cylinder.                                  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t nz;
@@ -466,9 +470,16 @@ typedef struct {
     const int32_t *nsh;  /* nz */
     const double *r;     /* nz x 8, outer -> inner */
     const int32_t *ell;  /* nz x 8 */
+    const int32_t *shape; /* nz: 0 spheres, 1 cylinders along z */
     int32_t background;
     int32_t derefine;
 } orc_zones;
+
+/* z offset from zone k's centre as its shape counts it */
+static double zone_dz(const orc_zones *Z, int k, double z)
+{
+    return Z->shape[k] == 1 ? 0.0 : z - Z->c[3 * k + 2];
+}
 
 static int zone_level(const orc_zones *Z, double x, double y, double z, int *which)
 {
@@ -477,7 +488,7 @@ static int zone_level(const orc_zones *Z, double x, double y, double z, int *whi
     for (int k = 0; k < Z->nz; ++k) {
         double dx = x - Z->c[3 * k + 0];
         double dy = y - Z->c[3 * k + 1];
-        double dz = z - Z->c[3 * k + 2];
+        double dz = zone_dz(Z, k, z);
         double d2 = dx * dx + dy * dy + dz * dz;
         int lev = -1;
         for (int s = 0; s < Z->nsh[k]; ++s) {
@@ -494,9 +505,9 @@ static int zone_level(const orc_zones *Z, double x, double y, double z, int *whi
 
 int32_t orc_zone_level(double x, double y, double z, int32_t nz, const double *zc,
                        const int32_t *znsh, const double *zr, const int32_t *zell,
-                       int32_t background, int32_t derefine)
+                       const int32_t *zshape, int32_t background, int32_t derefine)
 {
-    orc_zones Z = {nz, zc, znsh, zr, zell, background, derefine};
+    orc_zones Z = {nz, zc, znsh, zr, zell, zshape, background, derefine};
     return zone_level(&Z, x, y, z, NULL);
 }
 
@@ -508,7 +519,8 @@ int32_t orc_zone_level(double x, double y, double z, int32_t nz, const double *z
 /*  - r_sep = r_sep_factor h (0.2 h in the paper), capped at nn_cap times    */
 /*    the nearest-neighbour distance when nn_cap > 0 (paper Sec. 2.2, after  */
 /*    Franchini et al.);                                                    */
-/*  - tangential mode: v = x - zone centre; w0 = unit(v x e_k), k the axis   */
+/*  - tangential mode: v = x - zone centre (z part dropped for a cylinder    */
+/*    zone); w0 = unit(v x e_k), k the axis                                  */
 /*    of smallest |v_k| (ties to the lowest k); w = w0 cos t + (vhat x w0)   */
 /*    sin t with t = 2 pi U, a random rotation about v (paper Sec. 2.2);    */
 /*  - random mode (or no zone centre, or v = 0): w uniform on the sphere    */
@@ -546,7 +558,7 @@ static void split_axis(const orc_zones *Z, int zone, int mode, uint64_t s, doubl
     double U1 = u53(orc_splitmix64(s, 1));
     double U2 = u53(orc_splitmix64(s, 2));
     if (mode == 0 && zone >= 0) {
-        double v[3] = {x - Z->c[3 * zone + 0], y - Z->c[3 * zone + 1], z - Z->c[3 * zone + 2]};
+        double v[3] = {x - Z->c[3 * zone + 0], y - Z->c[3 * zone + 1], zone_dz(Z, zone, z)};
         double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         if (vn > 0.0) {
             int k = 0;
@@ -731,13 +743,13 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
                         double *vy, double *vz, double *u, double *h, int8_t *level,
                         int64_t *id, int64_t *next_id, const double *dnn, int32_t nz,
                         const double *zc, const int32_t *znsh, const double *zr,
-                        const int32_t *zell, int32_t background, int32_t derefine,
-                        double r_sep_factor, double nn_cap, int32_t split_mode, uint64_t seed,
+                        const int32_t *zell, const int32_t *zshape, int32_t background,
+                        int32_t derefine, double r_sep_factor, double nn_cap, int32_t split_mode, uint64_t seed,
                         int64_t step, int32_t periodic, const double *lo, const double *hi,
                         int32_t do_split, int32_t do_merge, int64_t *n_out, int64_t *n_split,
                         int64_t *n_merged, int64_t *n_spare)
 {
-    orc_zones Z = {nz, zc, znsh, zr, zell, background, derefine};
+    orc_zones Z = {nz, zc, znsh, zr, zell, zshape, background, derefine};
     int64_t ns = 0;
     *n_split = 0; *n_merged = 0; *n_spare = 0; *n_out = n;
 

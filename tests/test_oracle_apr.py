@@ -51,6 +51,45 @@ def test_zone_levels_nested_and_strict(orc):
     assert orc.zone_level(3.5, 0, 0, z2, background=3, derefine=True) == 1  # derefine: min
 
 
+def test_cylinder_zone_levels(orc):
+    # shape 1: cylinders along z through c; the level ignores z, strict radius
+    zones = [dict(c=(0.5, 0.5, 7.0), r=(0.3, 0.1), ell=(1, 2), shape=1)]
+    for z in (-100.0, 0.0, 7.0, 55.5):
+        assert orc.zone_level(0.55, 0.5, z, zones) == 2
+        assert orc.zone_level(0.5, 0.75, z, zones) == 1
+        assert orc.zone_level(0.8, 0.5, z, zones) == 0     # on the outer cylinder: outside
+        assert orc.zone_level(0.5, 0.9, z, zones) == 0
+    # in the plane z = c_z a cylinder and a sphere agree
+    sph = [dict(zones[0], shape=0)]
+    rng = np.random.default_rng(5)
+    for x, y in rng.uniform(0.1, 0.9, size=(200, 2)):
+        assert orc.zone_level(x, y, 7.0, zones) == orc.zone_level(x, y, 7.0, sph)
+    assert orc.zone_level(0.55, 0.5, 7.2, sph) == 1 and orc.zone_level(0.55, 0.5, 7.35, sph) == 0
+
+
+def test_split_tangential_to_cylinder(orc):
+    # a thin periodic box with a cylinder zone: children sit at +-r_sep, at a
+    # right angle to the in-plane offset from the axis, whatever their z
+    st, p = W.wave_box(nx=16)
+    zc = np.array(p["zones"][0]["c"])
+    n = st["x"].shape[0]
+    out = orc.split_merge(st, p["zones"], step=1, seed=3, r_sep_factor=0.2, nn_cap=0.0,
+                          split_mode=0, periodic=True, lo=p["lo"], hi=p["hi"], do_merge=False)
+    rxy2 = (st["x"] - zc[0]) ** 2 + (st["y"] - zc[1]) ** 2
+    inside = rxy2 < p["zones"][0]["r"][0] ** 2
+    par = np.nonzero(inside)[0]
+    assert out["n_split"] == par.size > 0
+    assert len(set(np.round(st["z"][par], 9))) > 1       # the zone spans several layers
+    xp = np.array([st["x"][par], st["y"][par], st["z"][par]])
+    d1 = np.array([out["x"][par], out["y"][par], out["z"][par]]) - xp
+    v = np.array([xp[0] - zc[0], xp[1] - zc[1], 0.0 * xp[2]])
+    cosang = np.sum(d1 * v, axis=0) / (np.linalg.norm(d1, axis=0) * np.linalg.norm(v, axis=0))
+    assert np.max(np.abs(cosang)) < 1e-12
+    assert _mass_units(out["level"]) == _mass_units(st["level"])
+    for k in ("x", "y", "z", "vx"):
+        assert _sum_mx(out, k) == _sum_mx(st, k), k
+
+
 def _small_box(nside=16):
     st, p = W.refine_box(nside=nside)
     p = dict(p, m0=1.0 / nside ** 3)

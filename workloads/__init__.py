@@ -141,6 +141,57 @@ def refine_box(nside=64, seed_k=4):
     return st, params
 
 
+def hcp_positions(nx, ny, nz, a):
+    """Hexagonal close-packed lattice of spacing a: nx per row along x, ny rows
+    (spacing a sqrt(3)/2, odd rows shifted a/2), nz layers (spacing
+    a sqrt(2/3), odd layers shifted by (a/2, a sqrt(3)/6)); ny and nz even, so
+    the box (nx a, ny a sqrt(3)/2, nz a sqrt(2/3)) tiles periodically."""
+    dy, dz = a * np.sqrt(3.0) / 2.0, a * np.sqrt(2.0 / 3.0)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x = (i + 0.25 + 0.5 * (j % 2) + 0.5 * (k % 2)) * a
+    y = (j + 0.25 + (k % 2) / 3.0) * dy
+    z = (k + 0.5) * dz
+    L = np.array([nx * a, ny * dy, nz * dz])
+    return np.mod(x.ravel(), L[0]), y.ravel().copy(), z.ravel().copy(), L
+
+
+def wave_box(nx=64, seed_k=6, amp=0.02, noise=1e-4, vx=1e-3, hfact=1.2):
+    """Workload 6, the sound-wave box of the paper's appendix A: a thin
+    periodic box of width 1 in x and about 1 in y, hcp lattice with nx
+    particles across (64 x 74 x 12 = 56832 at nx = 64), stretched along x so
+    that rho = 1 + amp sin(2 pi x); adiabatic gamma = 5/3 with unperturbed
+    sound speed 1, u perturbed with the same amplitude scaled by P0/rho0;
+    v = (vx, 0, 0); x and y moved by U(-noise, noise).  Refinement: one
+    cylinder along z of radius 0.1 about (0.5, 0.5) at level 1, tangential
+    split at r_sep = 0.2 h with the nearest-neighbour cap 0.35."""
+    rng = _rng(seed_k)
+    a = 1.0 / nx
+    ny = 2 * int(round(nx / np.sqrt(3.0)))
+    nz = 2 * max(1, int(round(12 * nx / 128.0)))
+    x0, y, z, L = hcp_positions(nx, ny, nz, a)
+    L[0] = 1.0
+    # stretch: the mass left of x is x + amp/(2 pi) (1 - cos 2 pi x) = x0
+    x = x0.copy()
+    for _ in range(50):
+        g = x + amp / (2 * np.pi) * (1.0 - np.cos(2 * np.pi * x)) - x0
+        x -= g / (1.0 + amp * np.sin(2 * np.pi * x))
+    n = x.shape[0]
+    x = np.mod(x + rng.uniform(-noise, noise, n), 1.0)
+    y = np.mod(y + rng.uniform(-noise, noise, n) * L[1], L[1])
+    gamma, cs0, rho0 = 5.0 / 3.0, 1.0, 1.0
+    P0 = rho0 * cs0 * cs0 / gamma
+    rho = rho0 + amp * np.sin(2 * np.pi * x)
+    u = P0 / ((gamma - 1.0) * rho0) + amp * (P0 / rho0) * np.sin(2 * np.pi * x)
+    m = rho0 * L[0] * L[1] * L[2] / n
+    h = hfact * (m / rho) ** (1.0 / 3.0)
+    st = _state(x, y, z, np.full(n, vx), np.zeros(n), np.zeros(n), u, h, np.zeros(n, np.int8))
+    params = dict(m0=m, periodic=True, lo=(0.0, 0.0, 0.0), hi=tuple(float(v) for v in L),
+                  eos=2, gamma=gamma, cs0=cs0, alpha=1.0, beta=2.0, hfact=hfact,
+                  zones=[dict(c=(0.5, 0.5, 0.5 * L[2]), r=(0.1,), ell=(1,), shape=1)],
+                  r_sep_factor=0.2, nn_cap=0.35, split_mode=0, amp=amp)
+    return st, params
+
+
 def circumbinary_disc(n0=6_550_000, seed_k=5):
     """Workload 5: circumbinary disc about two unit masses at separation 1 on
     a circular orbit (Omega_b = sqrt 2), R in [2, 20], Sigma ~ R^-1, H/R = 0.05
