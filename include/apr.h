@@ -74,11 +74,17 @@ typedef struct {
  * centre, radii r[0] > r[1] > ... (outer to inner) with levels ell[k].  The
  * level at a point is that of the innermost sphere with |x - c|^2 < r^2
  * (strict), or the background level outside them.  Several zones combine by
- * max (refinement) or by min (params.derefine != 0; paper Sec. 2.1, rule 3). */
+ * max (refinement) or by min (params.derefine != 0; paper Sec. 2.1, rule 3).
+ * shape = APR_ZONE_CYLINDER makes them cylinders along z through c: the
+ * distance leaves out z, and the tangential split axis uses the offset from
+ * the axis (the circular region of the paper's sound-wave test in a thin box,
+ * appendix A). */
+enum { APR_ZONE_SPHERE = 0, APR_ZONE_CYLINDER = 1 };
 typedef struct {
     double c[3];
     int32_t n;       /* number of spheres, 1..8 */
     int32_t ell[8];
+    int32_t shape;   /* APR_ZONE_SPHERE or APR_ZONE_CYLINDER */
     double r[8];
 } apr_zone;
 

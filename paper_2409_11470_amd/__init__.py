@@ -9,6 +9,7 @@ from ._abi import (  # noqa: F401
     APR_OK, APR_ERR_INVALID, APR_ERR_CAPACITY, APR_ERR_NOCONVERGE, APR_ERR_HIP,
     APR_ERR_OVERFLOW, APR_ERR_RANGE, APR_FP64, APR_FP32, APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL,
     APR_EOS_ADIABATIC, APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM, APR_KERNEL_M4, APR_KERNEL_WC2,
+    APR_ZONE_SPHERE, APR_ZONE_CYLINDER,
     APR_PROF_DENSITY,
     APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP, APR_PROF_CAND, AprError, lib, lib_path,
     Params, Zone, Sink, CState, apr_default_params)

@@ -9,6 +9,7 @@ APR_FP64, APR_FP32 = 0, 1
 APR_EOS_ISOTHERMAL, APR_EOS_LOCALLY_ISOTHERMAL, APR_EOS_ADIABATIC = 0, 1, 2
 APR_SPLIT_TANGENTIAL, APR_SPLIT_RANDOM = 0, 1
 APR_KERNEL_M4, APR_KERNEL_WC2 = 0, 1
+APR_ZONE_SPHERE, APR_ZONE_CYLINDER = 0, 1
 (APR_PROF_DENSITY, APR_PROF_FORCES, APR_PROF_CELLS, APR_PROF_SPLITMERGE, APR_PROF_VJP,
  APR_PROF_CAND, APR_PROF_N) = (0, 1, 2, 3, 4, 5, 6)
 
@@ -45,7 +46,7 @@ class CState(C.Structure):
 
 class Zone(C.Structure):
     _fields_ = [("c", C.c_double * 3), ("n", C.c_int32), ("ell", C.c_int32 * 8),
-                ("r", C.c_double * 8)]
+                ("shape", C.c_int32), ("r", C.c_double * 8)]
 
 
 class Sink(C.Structure):

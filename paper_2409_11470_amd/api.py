@@ -45,7 +45,8 @@ def make_params(**kw):
 
 
 def make_zones(zones):
-    """ctypes array of apr_zone from dicts {c: (x, y, z), r: radii outer->inner, ell: levels}."""
+    """ctypes array of apr_zone from dicts {c: (x, y, z), r: radii outer->inner,
+    ell: levels, shape: 0 spheres (default) or 1 cylinders along z}."""
     arr = (Zone * max(1, len(zones)))()
     for k, z in enumerate(zones):
         arr[k].c[:] = [float(v) for v in z["c"]]
@@ -53,6 +54,7 @@ def make_zones(zones):
         if not 1 <= len(r) <= 8 or len(e) != len(r):
             raise ValueError("a zone has 1..8 spheres")
         arr[k].n = len(r)
+        arr[k].shape = int(z.get("shape", 0))
         for i in range(len(r)):
             arr[k].r[i] = float(r[i])
             arr[k].ell[i] = int(e[i])

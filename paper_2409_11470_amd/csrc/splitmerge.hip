@@ -33,18 +33,26 @@ struct Zones {
     int nz, bg, derefine;
     double c[kMaxZones][3];
     int nsh[kMaxZones];
+    int cyl[kMaxZones];  // 1: cylinders along z through c (z left out)
     double r[kMaxZones][8];
     int ell[kMaxZones][8];
 };
 
-// Level of a point: innermost sphere of each zone (strict), combined by max
-// (or min when derefining); *which = first zone giving the combined level.
+// z offset from zone k's centre as the zone's shape counts it
+__device__ inline double zone_dz(const Zones &Z, int k, double z)
+{
+    return Z.cyl[k] ? 0.0 : z - Z.c[k][2];
+}
+
+// Level of a point: innermost sphere (or cylinder) of each zone (strict),
+// combined by max (or min when derefining); *which = first zone giving the
+// combined level.
 __device__ int zone_level(const Zones &Z, double x, double y, double z, int *which)
 {
 #pragma clang fp contract(off)
     int best = Z.bg, w = -1;
     for (int k = 0; k < Z.nz; ++k) {
-        double dx = x - Z.c[k][0], dy = y - Z.c[k][1], dz = z - Z.c[k][2];
+        double dx = x - Z.c[k][0], dy = y - Z.c[k][1], dz = zone_dz(Z, k, z);
         double d2 = dx * dx + dy * dy + dz * dz;
         int lev = -1;
         for (int s = 0; s < Z.nsh[k]; ++s) {
@@ -81,7 +89,8 @@ __device__ inline uint64_t stream_state(uint64_t seed, int64_t step, int64_t id)
 
 __device__ inline double u53(uint64_t v) { return (double)(v >> 11) * 0x1.0p-53; }
 
-// Split axis: tangential to zone `zone` (rotated about x - c by 2 pi U1), or
+// Split axis: tangential to zone `zone` (rotated about x - c, z left out for
+// a cylinder zone, by 2 pi U1), or
 // uniform on the sphere (cos theta = 2 U1 - 1, phi = 2 pi U2).
 __device__ void split_axis(const Zones &Z, int zone, int mode, uint64_t s, double x, double y,
                            double z, double w[3])
@@ -90,7 +99,7 @@ __device__ void split_axis(const Zones &Z, int zone, int mode, uint64_t s, doubl
     const double pi = 3.14159265358979323846;
     double U1 = u53(sm64(s, 1)), U2 = u53(sm64(s, 2));
     if (mode == APR_SPLIT_TANGENTIAL && zone >= 0) {
-        double v[3] = {x - Z.c[zone][0], y - Z.c[zone][1], z - Z.c[zone][2]};
+        double v[3] = {x - Z.c[zone][0], y - Z.c[zone][1], zone_dz(Z, zone, z)};
         double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         if (vn > 0.0) {
             int k = 0;
@@ -647,6 +656,9 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     Z.derefine = P.derefine;
     for (int k = 0; k < nzones; ++k) {
         for (int d = 0; d < 3; ++d) Z.c[k][d] = zones[k].c[d];
+        if (zones[k].shape != APR_ZONE_SPHERE && zones[k].shape != APR_ZONE_CYLINDER)
+            return fail(c, APR_ERR_INVALID, "zone shape");
+        Z.cyl[k] = zones[k].shape == APR_ZONE_CYLINDER;
         Z.nsh[k] = zones[k].n;
         for (int sh = 0; sh < zones[k].n; ++sh) {
             Z.r[k][sh] = zones[k].r[sh];
@@ -699,13 +711,16 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                 return fail(c, APR_ERR_INVALID,
                             "nn_cap > 0 needs apr_density on the current state first");
             }
+            // the nearest-neighbour distances of the n parents, as the last
+            // density pass wrote them: asked for by n, not by the capacity, so
+            // that a capacity grown since then cannot reallocate (and lose) them
             if (P.precision == APR_FP32) {
-                const float *dnn = cap_nn ? wsa<float>(c, "dnn32", (size_t)cap) : nullptr;
+                const float *dnn = cap_nn ? wsa<float>(c, "dnn32", (size_t)n) : nullptr;
                 hipLaunchKernelGGL(k_split_apply<float>, dim3(grid(n)), dim3(256), 0, c->stream,
                                    n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
                                    P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);
             } else {
-                const double *dnn = cap_nn ? wsa<double>(c, "dnn64", (size_t)cap) : nullptr;
+                const double *dnn = cap_nn ? wsa<double>(c, "dnn64", (size_t)n) : nullptr;
                 hipLaunchKernelGGL(k_split_apply<double>, dim3(grid(n)), dim3(256), 0, c->stream,
                                    n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
                                    P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);

@@ -155,7 +155,7 @@ def hcp_positions(nx, ny, nz, a):
     return np.mod(x.ravel(), L[0]), y.ravel().copy(), z.ravel().copy(), L
 
 
-def wave_box(nx=64, seed_k=6, amp=0.02, noise=1e-4, vx=1e-3, hfact=1.2):
+def wave_box(nx=64, nz=12, seed_k=6, amp=0.02, noise=1e-4, vx=1e-3, hfact=1.2):
     """Workload 6, the sound-wave box of the paper's appendix A: a thin
     periodic box of width 1 in x and about 1 in y, hcp lattice with nx
     particles across (64 x 74 x 12 = 56832 at nx = 64), stretched along x so
@@ -163,11 +163,12 @@ def wave_box(nx=64, seed_k=6, amp=0.02, noise=1e-4, vx=1e-3, hfact=1.2):
     sound speed 1, u perturbed with the same amplitude scaled by P0/rho0;
     v = (vx, 0, 0); x and y moved by U(-noise, noise).  Refinement: one
     cylinder along z of radius 0.1 about (0.5, 0.5) at level 1, tangential
-    split at r_sep = 0.2 h with the nearest-neighbour cap 0.35."""
+    split at r_sep = 0.2 h with the nearest-neighbour cap 0.35.  nz (even) is
+    the number of layers: 12 in the paper; the box stays at least 8 h thick, as
+    periodic supports need, for any nx."""
     rng = _rng(seed_k)
     a = 1.0 / nx
     ny = 2 * int(round(nx / np.sqrt(3.0)))
-    nz = 2 * max(1, int(round(12 * nx / 128.0)))
     x0, y, z, L = hcp_positions(nx, ny, nz, a)
     L[0] = 1.0
     # stretch: the mass left of x is x + amp/(2 pi) (1 - cos 2 pi x) = x0
