@@ -18,7 +18,9 @@ value = interactions per step * steps / wall time of the timed steps.
 The same run times the rest of the path on the other workloads ("legs"): the
 refined box (one split pass over 262144 particles, then density + forces +
 adjoint on the 362k-particle result, both forms), the same box and step with
-the Wendland C2 kernel (h_fact 1.3, FP32 form), the 1M-particle planet disc
+the Wendland C2 kernel (h_fact 1.3, FP32 form), the sound-wave box of the
+paper's appendix A (run to t = 2 with and without its refinement zone; the
+density blip at the zone boundary), the 1M-particle planet disc
 stepped with its refinement zone (every step: cells, density, split/merge,
 forces, sink gravity, leapfrog) and the 8M-particle circumbinary disc (FP32
 density + forces + adjoint).
@@ -282,6 +284,68 @@ def leg_wendland_box(A, torch, W, steps, warmup):
     return out
 
 
+def _wave_run(A, torch, st, p, zones_on, t_split=0.5, t_end=2.0):
+    """The sound-wave box stepped to t_end (dt = 0.3 min(h / vsig), taken again
+    after the split), zone active from t_split; returns the final state with
+    its density, the step count and the wall time of the steps."""
+    ctx = make_ctx(A, p, "fp32", seed=5)
+    ds = A.DeviceState.from_numpy(st, capacity=2 * st["x"].shape[0])
+    A.apr_accel(ctx, ds)
+    dt = A.apr_timestep(ctx, ds, 0.3)
+    torch.cuda.synchronize()
+    t, k, split_done, t0 = 0.0, 0, False, time.perf_counter()
+    while t < t_end - 1e-12:
+        zones = p["zones"] if (zones_on and t >= t_split) else []
+        step = min(dt, t_end - t)
+        A.apr_step(ctx, ds, zones, [], step, k)
+        t += step
+        k += 1
+        if zones and not split_done:
+            split_done = True
+            dt = A.apr_timestep(ctx, ds, 0.3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    A.apr_sync_status(ctx)
+    A.apr_build_cells(ctx, ds)
+    rho = torch.zeros(ds.n, dtype=torch.float32, device="cuda")
+    om = torch.zeros_like(rho)
+    A.apr_density(ctx, ds, rho, om)
+    A.apr_sync_status(ctx)
+    out = ds.to_numpy()
+    out["rho"] = rho.double().cpu().numpy()
+    ctx.close()
+    return out, k, wall
+
+
+def _blip(a, b, nbins=50):
+    import numpy as np
+
+    def prof(r):
+        sel = (r["y"] > 0.4) & (r["y"] < 0.6)
+        i = np.minimum((r["x"][sel] * nbins).astype(int), nbins - 1)
+        return (np.bincount(i, weights=r["rho"][sel], minlength=nbins)
+                / np.maximum(np.bincount(i, minlength=nbins), 1))
+    return float(np.max(np.abs(prof(a) - prof(b))))
+
+
+def leg_wave_box(A, torch, W):
+    """The sound-wave box of the paper's appendix A (56832 particles, cylinder
+    zone r = 0.1 at level 1 from t = 0.5, to t = 2), FP32 form, with and
+    without the zone, for the M4 and the Wendland C2 kernel: wall time per
+    step of the refined run and the density blip (largest difference of the
+    binned 0.4 < y < 0.6 cross-section density, over the initial mean 1)."""
+    out = dict(workload="sound-wave box, 64 x 74 x 12 hcp lattice, A = 0.02, cylinder zone "
+                        "r = 0.1, level 1 from t = 0.5 to t = 2, FP32 form")
+    for name, kw in (("m4", dict(kernel=0, hfact=1.2)), ("wc2", dict(kernel=1, hfact=1.3))):
+        st, p = W.wave_box(hfact=kw["hfact"])
+        p = dict(p, **kw)
+        ref, _, _ = _wave_run(A, torch, st, p, False)
+        apr, steps, wall = _wave_run(A, torch, st, p, True)
+        out[name] = dict(steps=steps, ms_per_step=1e3 * wall / steps, n_final=int(apr["x"].shape[0]),
+                         blip=_blip(apr, ref))
+    return out
+
+
 def leg_circumbinary(A, torch, W, reps):
     """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint."""
     st, p = W.circumbinary_disc()
@@ -378,6 +442,10 @@ def main():
         legs["wendland_c2_box"] = leg_wendland_box(A, torch, W, 10, 3)
         log("wendland c2 box: %.3e interactions/s, %.3f ms/step"
             % (legs["wendland_c2_box"]["value"], legs["wendland_c2_box"]["ms_per_step"]))
+        legs["wave_box_blip"] = leg_wave_box(A, torch, W)
+        log("wave box: blip %.4f (M4), %.4f (Wendland C2), %.3f ms/step"
+            % (legs["wave_box_blip"]["m4"]["blip"], legs["wave_box_blip"]["wc2"]["blip"],
+               legs["wave_box_blip"]["m4"]["ms_per_step"]))
         legs["planet_disc_steps"] = leg_planet_disc(A, torch, W, 10)
         log("planet disc: %.3e interactions/s, %.2f ms/step"
             % (legs["planet_disc_steps"]["value"], legs["planet_disc_steps"]["ms_per_step"]))
