@@ -60,7 +60,8 @@ typedef struct apr_ctx apr_ctx;
 typedef struct {
     int64_t n;        /* particles in use */
     int64_t capacity; /* particles every array has room for */
-    int64_t next_id;  /* id given to the next particle a split creates (host value) */
+    int64_t next_id;  /* id given to the next particle a split creates (host value);
+                         must exceed every id in the state, so that ids stay unique */
     double *x, *y, *z;
     double *vx, *vy, *vz;
     double *u;        /* specific thermal energy (adiabatic EOS) */

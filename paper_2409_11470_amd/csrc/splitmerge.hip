@@ -312,8 +312,7 @@ struct Node {
     unsigned long long sum;
     uint32_t kc, keq;
     unsigned long long amin_c, amax_c, amin_c1, amax_c1;
-    int32_t ax, cut, kp, all_eq;
-    unsigned long long moved;
+    int32_t ax, kp;  // axis and left count, stored for the passes after the one that finds them
 };
 
 struct TreeArgs {
@@ -343,7 +342,6 @@ __global__ void k_tree_init(TreeArgs a)
     nd.amax_c = 0;
     nd.amin_c1 = ~0ull;
     nd.amax_c1 = 0;
-    nd.moved = ~0ull;
 }
 
 // True when every active lane of the wavefront works on the same node (the
@@ -390,15 +388,14 @@ __global__ void k_tree_minmax(TreeArgs a)
     }
 }
 
-__global__ void k_tree_axis(TreeArgs a)
+// Axis of the node's largest integer extent (ties to the lower axis), from
+// its completed min / max.
+__device__ inline int node_axis(const Node &nd)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
-    Node &nd = a.node[i];
     int ax = 0;
     for (int k = 1; k < 3; ++k)
         if (nd.mx[k] - nd.mn[k] > nd.mx[ax] - nd.mn[ax]) ax = k;
-    nd.ax = ax;
+    return ax;
 }
 
 __device__ inline unsigned long long umin64(unsigned long long a, unsigned long long b)
@@ -414,13 +411,21 @@ __device__ inline unsigned long long uadd64(unsigned long long a, unsigned long 
     return a + b;
 }
 
+// Sum of the coordinates along the node's axis.  Every element takes the axis
+// from the node's min / max itself; the node's first element stores it for
+// the later passes (no element reads it here).
 __global__ void k_tree_sum(TreeArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool act = i < a.m && active(a, i);
     int32_t L = act ? a.lo[i] : -1;
     int first = 0;
-    unsigned long long v = act ? (unsigned long long)a.q[a.node[L].ax][a.es[i]] : 0ull;
+    unsigned long long v = 0ull;
+    if (act) {
+        const int ax = node_axis(a.node[L]);
+        if (i == L) a.node[L].ax = ax;
+        v = (unsigned long long)a.q[ax][a.es[i]];
+    }
     if (wave_one_node(act, L, &first)) {
         v = wave_reduce(v, uadd64);
         if (__lane_id() == first) atomicAdd(&a.node[L].sum, v);
@@ -479,12 +484,19 @@ __global__ void k_tree_count(TreeArgs a)
     else atomicMin(&nd.amin_c1, key);
 }
 
-__global__ void k_tree_decide(TreeArgs a)
+// The node's cut from its completed statistics: the centroid c (floor of the
+// integer mean) with kc elements below it, moved up one step when none is;
+// kp elements go left.  An odd kc moves the element nearest the plane (by
+// (coordinate, id)) from the larger side; all-equal coordinates split by
+// position.
+struct Cut {
+    int32_t cut, kp, all_eq;
+    unsigned long long moved;
+};
+
+__device__ inline Cut node_cut(const Node &nd, int64_t n)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
-    Node &nd = a.node[i];
-    int64_t n = a.hi[i] - i;
+    Cut r;
     int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
     int64_t k = nd.kc;
     unsigned long long amin = nd.amin_c, amax = nd.amax_c;
@@ -494,23 +506,26 @@ __global__ void k_tree_decide(TreeArgs a)
         amin = nd.amin_c1;
         amax = nd.amax_c1;
     }
-    nd.cut = (int32_t)c;
-    nd.all_eq = 0;
-    nd.moved = ~0ull;
+    r.cut = (int32_t)c;
+    r.all_eq = 0;
+    r.moved = ~0ull;
     if (k == n) {
-        nd.all_eq = 1;
-        nd.kp = (int32_t)(2 * (n / 4));
+        r.all_eq = 1;
+        r.kp = (int32_t)(2 * (n / 4));
     } else if (k % 2 == 0) {
-        nd.kp = (int32_t)k;
+        r.kp = (int32_t)k;
     } else if (k < n - k) {
-        nd.kp = (int32_t)(k + 1);
-        nd.moved = amin;
+        r.kp = (int32_t)(k + 1);
+        r.moved = amin;
     } else {
-        nd.kp = (int32_t)(k - 1);
-        nd.moved = amax;
+        r.kp = (int32_t)(k - 1);
+        r.moved = amax;
     }
+    return r;
 }
 
+// Side of every element.  Each takes the node's cut itself; the node's first
+// element stores kp for the partition (no element reads it here).
 __global__ void k_tree_left(TreeArgs a, uint32_t *left)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -520,17 +535,18 @@ __global__ void k_tree_left(TreeArgs a, uint32_t *left)
         return;
     }
     int32_t L = a.lo[i];
-    const Node &nd = a.node[L];
+    const Cut cu = node_cut(a.node[L], a.hi[i] - L);
+    if (i == L) a.node[L].kp = cu.kp;
     uint32_t p = a.es[i];
     bool l;
-    if (nd.all_eq) {
-        l = (i - L) < nd.kp;
+    if (cu.all_eq) {
+        l = (i - L) < cu.kp;
     } else {
-        int64_t v = a.q[nd.ax][p];
-        l = v < nd.cut;
+        int64_t v = a.q[a.node[L].ax][p];
+        l = v < cu.cut;
         unsigned long long key = ((unsigned long long)v << kIdBits) |
                                  ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
-        if (key == nd.moved) l = !l;
+        if (key == cu.moved) l = !l;
     }
     left[i] = l ? 1u : 0u;
 }
@@ -757,6 +773,12 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
         double sc[3];
         for (int k = 0; k < 3; ++k) sc[k] = kQuant / b.L[k];
         bool high_ids = s->next_id > (int64_t)0xffffffffLL;
+        // every id is below next_id: the low-word sort needs only its bit length
+        int id_bits = 32;
+        if (!high_ids) {
+            id_bits = 1;
+            while (id_bits < 32 && (((int64_t)1 << id_bits) < s->next_id)) ++id_bits;
+        }
         for (int l = lmax; l >= 1; --l) {
             hipLaunchKernelGGL(k_cand_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
                                changed, removed, l, flag);
@@ -775,7 +797,7 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
                                s->id, 0, keys);
             APR_LAUNCHED(c);
-            rc = radix_sort_u32(c, keys, cand, nc, 32);
+            rc = radix_sort_u32(c, keys, cand, nc, id_bits);
             if (rc) return rc;
             if (high_ids) {
                 hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
@@ -792,40 +814,49 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             hipLaunchKernelGGL(k_tree_root, dim3(grid(m)), dim3(256), 0, c->stream, m, lo[0],
                                hi[0]);
             APR_LAUNCHED(c);
+            // Depths run in batches between host checks of `more` (set by
+            // the last partition when a node still holds more than two
+            // elements): first about log2 m + 2 of them (a balanced tree's
+            // depth), then 4 at a time.  A depth after the tree is complete
+            // changes nothing: no node is active, so every element keeps its
+            // place.
             int cur = 0;
-            for (int depth = 0; m > 2 && depth < 4096; ++depth) {
-                TreeArgs ta;
-                ta.m = m;
-                ta.es = es[cur];
-                ta.lo = lo[cur];
-                ta.hi = hi[cur];
-                for (int k = 0; k < 3; ++k) ta.q[k] = q[k];
-                ta.id = s->id;
-                ta.node = node;
-                unsigned g = grid(m);
-                hipLaunchKernelGGL(k_tree_init, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_minmax, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_axis, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_sum, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_decide, dim3(g), dim3(256), 0, c->stream, ta);
-                hipLaunchKernelGGL(k_tree_left, dim3(g), dim3(256), 0, c->stream, ta, flag);
-                APR_LAUNCHED(c);
-                rc = exclusive_scan_u32(c, flag, scan, m, nullptr);
-                if (rc) return rc;
-                APR_HIP(c, hipMemsetAsync(more, 0, 4, c->stream));
-                hipLaunchKernelGGL(k_tree_partition, dim3(g), dim3(256), 0, c->stream, ta, flag,
-                                   scan, es[1 - cur], lo[1 - cur], hi[1 - cur], more);
-                APR_LAUNCHED(c);
-                cur = 1 - cur;
+            int depth = 0, batch = 2;
+            for (int64_t mm = m; mm > 1; mm >>= 1) ++batch;
+            while (m > 2) {
+                for (int b2 = 0; b2 < batch; ++b2, ++depth) {
+                    TreeArgs ta;
+                    ta.m = m;
+                    ta.es = es[cur];
+                    ta.lo = lo[cur];
+                    ta.hi = hi[cur];
+                    for (int k = 0; k < 3; ++k) ta.q[k] = q[k];
+                    ta.id = s->id;
+                    ta.node = node;
+                    unsigned g = grid(m);
+                    hipLaunchKernelGGL(k_tree_init, dim3(g), dim3(256), 0, c->stream, ta);
+                    hipLaunchKernelGGL(k_tree_minmax, dim3(g), dim3(256), 0, c->stream, ta);
+                    hipLaunchKernelGGL(k_tree_sum, dim3(g), dim3(256), 0, c->stream, ta);
+                    hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, c->stream, ta);
+                    hipLaunchKernelGGL(k_tree_left, dim3(g), dim3(256), 0, c->stream, ta, flag);
+                    APR_LAUNCHED(c);
+                    rc = exclusive_scan_u32(c, flag, scan, m, nullptr);
+                    if (rc) return rc;
+                    APR_HIP(c, hipMemsetAsync(more, 0, 4, c->stream));
+                    hipLaunchKernelGGL(k_tree_partition, dim3(g), dim3(256), 0, c->stream, ta,
+                                       flag, scan, es[1 - cur], lo[1 - cur], hi[1 - cur], more);
+                    APR_LAUNCHED(c);
+                    cur = 1 - cur;
+                }
                 int32_t hm = 0;
                 APR_HIP(c, hipMemcpyAsync(&hm, more, 4, hipMemcpyDeviceToHost, c->stream));
                 APR_HIP(c, hipStreamSynchronize(c->stream));
                 if (!hm) break;
-                if (depth == 4095) {
+                if (depth >= 4096) {
                     prof_end(c, tok);
                     return fail(c, APR_ERR_INVALID, "pairing tree deeper than 4096 levels");
                 }
+                batch = 4;
             }
             hipLaunchKernelGGL(k_merge_pairs, dim3(grid(m / 2)), dim3(256), 0, c->stream, m / 2,
                                es[cur], A, Z, l, changed, removed, mcount);
