@@ -66,6 +66,9 @@ def lib():
                                  C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_double, C.c_int32, _d, _d,
                                  C.c_int64, _i64, _d, _d, _d, _d, _d, _d, _d, C.c_int32]
+        L.orc_interp.restype = None
+        L.orc_interp.argtypes = [C.c_int64, _d, _d, _d, C.c_int64, _d, _d, _d, _d, _d, _d, _d,
+                                 C.c_int32, C.c_int32, _d, _d, _d, _d, _d]
         L.orc_kick.restype = None
         L.orc_kick.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, C.c_double]
         L.orc_drift.restype = None
@@ -359,3 +362,81 @@ def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_m
     out["next_id"] = nid.value
     out["n_split"], out["n_merged"], out["n_spare"] = ns.value, nm.value, nsp.value
     return out
+
+
+# -------------------------------------------------------------------- relaxing
+def interp(tx, ty, tz, rx, ry, rz, rh, q, *, kernel=KERNEL_M4, periodic=False, lo=(0, 0, 0),
+           hi=(1, 1, 1)):
+    """The reference set's SPH interpolant sum_b q_b W(|x - x_b|, h_b) at the
+    points (tx, ty, tz); q is [3, nr] (q_b = (m_b / rho_b) A_b)."""
+    tx, ty, tz = _f64(tx), _f64(ty), _f64(tz)
+    rx, ry, rz, rh = _f64(rx), _f64(ry), _f64(rz), _f64(rh)
+    q = [_f64(q[k]) for k in range(3)]
+    lo, hi = _box(lo, hi)
+    nt, nr = tx.shape[0], rx.shape[0]
+    out = [np.empty(nt) for _ in range(3)]
+    lib().orc_interp(nt, _p(tx, _d), _p(ty, _d), _p(tz, _d), nr, _p(rx, _d), _p(ry, _d),
+                     _p(rz, _d), _p(rh, _d), *[_p(a, _d) for a in q], int(kernel),
+                     int(bool(periodic)), _p(lo, _d), _p(hi, _d), *[_p(a, _d) for a in out])
+    return np.array(out)
+
+
+_eos_fn = eos  # relax() takes the EOS kind under the name eos
+
+
+def relax(st, ref, ref_rho, ref_a, *, m0, eos, hfact=1.2, kernel=KERNEL_M4, cs0=1.0, q_cs=0.25,
+          r_ref=1.0, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, lo=(0, 0, 0),
+          hi=(1, 1, 1), max_shuffles=50, ke_frac=0.005, tol=1e-12):
+    """Relaxing (paper Sec. 2.4) of the particles a split/merge pass introduced.
+
+    st: the new set (dict of arrays, changed in place: x, y, z, h); ref: the
+    reference set before the pass, with its converged densities ref_rho and
+    accelerations ref_a [3, n_ref].  The shuffled particles are those with an id
+    the reference does not hold (id >= ref next_id) or whose level differs
+    from the reference's for the same id.  Each shuffle:
+      1. a_new: hydro accelerations of the new set (density with its h-rho
+         solve, then forces) at the current positions;
+      2. a_ref: the reference accelerations interpolated at the same points;
+      3. dx = 0.5 dt^2 (a_new - a_ref), dt = 0.3 h / c_s of the particle, its
+         length capped at h; positions shift (periodic wrap);
+      4. KE = sum |dx| / dt^2 over the shuffled particles.
+    Repeats until KE <= ke_frac KE of the first shuffle, or max_shuffles.
+    Returns (number of shuffles, list of KE)."""
+    box = dict(periodic=periodic, lo=lo, hi=hi)
+    lvl = {int(i): int(l) for i, l in zip(ref["id"], ref["level"])}
+    nid = int(ref["next_id"])
+    mask = np.array([int(i) >= nid or lvl.get(int(i), -1) != int(l)
+                     for i, l in zip(st["id"], st["level"])])
+    mref = m0 * 2.0 ** -ref["level"].astype(np.float64)
+    q = (mref / ref_rho) * np.asarray(ref_a)
+    lo_a, hi_a = np.asarray(lo, float), np.asarray(hi, float)
+    L = hi_a - lo_a
+    kes = []
+    for k in range(max_shuffles):
+        d = density(st["x"], st["y"], st["z"], st["level"], st["h"], m0=m0, hfact=hfact, tol=tol,
+                    max_iter=60, kernel=kernel, **box)
+        st["h"] = d["h"]
+        f = forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st.get("u"),
+                   st["level"], d["h"], d["rho"], d["omega"], m0=m0, eos=eos, cs0=cs0, q_cs=q_cs,
+                   r_ref=r_ref, gamma=gamma, alpha=alpha, beta=beta, kernel=kernel, **box)
+        aref = interp(st["x"], st["y"], st["z"], ref["x"], ref["y"], ref["z"], ref["h"], q,
+                      kernel=kernel, **box)
+        _, c = _eos_fn(st["x"], st["y"], d["rho"], st.get("u"), eos=eos, cs0=cs0, q_cs=q_cs,
+                       r_ref=r_ref, gamma=gamma)
+        anew = np.array([f["ax"], f["ay"], f["az"]])
+        dt = 0.3 * d["h"] / c
+        dx = 0.5 * dt * dt * (anew - aref)
+        ln = np.sqrt((dx * dx).sum(0))
+        big = ln > d["h"]
+        dx[:, big] *= d["h"][big] / ln[big]
+        ln = np.minimum(ln, d["h"])
+        dx[:, ~mask] = 0.0
+        for a, key in enumerate(("x", "y", "z")):
+            v = st[key] + dx[a]
+            if periodic:  # one image back into [lo, hi), as the drift does
+                v = np.where(v >= hi_a[a], v - L[a], np.where(v < lo_a[a], v + L[a], v))
+            st[key] = v
+        kes.append(float(np.sum((ln / (dt * dt))[mask])))
+        if kes[-1] <= ke_frac * kes[0]:
+            break
+    return len(kes), kes

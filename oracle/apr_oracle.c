@@ -369,6 +369,42 @@ void orc_forces(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Interpolation of a field carried by a reference particle set, for the   */
+/* relaxing of Sec. 2.4 (the reference accelerations at the positions of    */
+/* the new particles).  Reading: the reference set's own SPH interpolant,   */
+/*   A(x) = sum_b (m_b / rho_b) A_b W(|x - x_b|, h_b),                      */
+/* over the b with |x - x_b|^2 < (2 h_b)^2 (strict), periodic minimum image. */
+/* The caller passes q_b = (m_b / rho_b) A_b per component.                 */
+/* ------------------------------------------------------------------------ */
+void orc_interp(int64_t nt, const double *tx, const double *ty, const double *tz,
+                int64_t nr, const double *rx, const double *ry, const double *rz,
+                const double *rh, const double *q0, const double *q1, const double *q2,
+                int32_t kernel, int32_t periodic, const double *lo, const double *hi,
+                double *o0, double *o1, double *o2)
+{
+    double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nt; ++i) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int64_t b = 0; b < nr; ++b) {
+            double dx = sep(tx[i], rx[b], periodic, L[0]);
+            double dy = sep(ty[i], ry[b], periodic, L[1]);
+            double dz = sep(tz[i], rz[b], periodic, L[2]);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double R = 2.0 * rh[b];
+            if (!(r2 < R * R)) continue;
+            double w = orc_wk(kernel, sqrt(r2), rh[b]);
+            s0 += q0[b] * w;
+            s1 += q1[b] * w;
+            s2 += q2[b] * w;
+        }
+        o0[i] = s0;
+        o1[i] = s1;
+        o2[i] = s2;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time integration (not described by the paper; the standard kick-drift-   */
 /* kick leapfrog) and the point-mass gravity of sink particles.             */
 /* ------------------------------------------------------------------------ */
