@@ -196,6 +196,35 @@ int apr_vjp(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega
             const void *az_bar, const void *dudt_bar, void *xbar, void *ybar, void *zbar,
             void *mbar);
 
+/* Relaxing (paper Sec. 2.4) of the particles a split/merge pass introduced:
+ * those of s whose id is not below ref->next_id, or whose level differs from
+ * the level ref gives the same id.  Each shuffle computes the hydro
+ * accelerations a_new of s (cells, apr_density, apr_forces on ctx), the
+ * reference accelerations interpolated at the same points by the reference
+ * set's own SPH interpolant
+ *   a_ref(x) = sum_b (m_b / rho_b) a_b W(|x - x_b|, h_b)   (r < 2 h_b),
+ * and moves each introduced particle by dx = 0.5 dt^2 (a_new - a_ref), dt =
+ * 0.3 h / c_s of the particle, with |dx| capped at h (periodic wrap).
+ * KE = sum |dx| / dt^2 over the moved particles; the shuffles stop once KE <=
+ * ke_frac * KE of the first shuffle (the paper: 0.005) or after max_shuffles
+ * (the paper: 50, at most 1000).  The interpolation and the shift are FP64.
+ *   ref_ctx   a context with the same precision, kernel, box and m0 whose
+ *             cells were built on ref (apr_build_cells), then apr_density
+ *             and apr_forces on ref: ref_rho, ref_ax, ref_ay, ref_az [ref->n]
+ *             are their outputs (context precision) in ref's order;
+ *   ref       the reference set (the state before the pass; ids below
+ *             ref->next_id, at most 2^31 - 1);
+ *   s         the new set; its positions and h change, its cells are rebuilt
+ *             (it is reordered like apr_build_cells) and are stale on return.
+ * *n_shuffles, *ke_first, *ke_last (each may be NULL) receive the number of
+ * shuffles and the first and last KE.  Synchronises once per shuffle.
+ * Returns APR_ERR_INVALID for mismatched contexts, ref cells not built on
+ * ref, or bad limits. */
+int apr_relax(apr_ctx *ctx, apr_state *s, apr_ctx *ref_ctx, const apr_state *ref,
+              const void *ref_rho, const void *ref_ax, const void *ref_ay, const void *ref_az,
+              int32_t max_shuffles, double ke_frac, int32_t *n_shuffles, double *ke_first,
+              double *ke_last);
+
 /* Neighbour lists for a given h (device, [n]), with the FP64 predicate
  * r_ab^2 < (2 h_a)^2 (mode 0) or r_ab^2 < (2 max(h_a, h_b))^2 (mode 1), b != a,
  * evaluated on absolute positions with the minimum-image convention and no

@@ -218,6 +218,20 @@ def apr_vjp(ctx, st, rho, omega, rho_bar=None, h_bar=None, ax_bar=None, ay_bar=N
     return tuple(out)
 
 
+def apr_relax(ctx, st, ref_ctx, ref, ref_rho, ref_ax, ref_ay, ref_az, max_shuffles=50,
+              ke_frac=0.005):
+    """Relaxing (paper Sec. 2.4) of the particles of st that a split/merge pass
+    introduced, against the reference state ref (the state before the pass,
+    with cells built in ref_ctx and ref_rho, ref_a* from apr_density and
+    apr_forces there).  Returns (shuffles, first KE, last KE)."""
+    cs, rcs = st.cstate(), ref.cstate()
+    ns, k0, k1 = C.c_int32(), C.c_double(), C.c_double()
+    ctx.check(lib().apr_relax(ctx.ptr, C.byref(cs), ref_ctx.ptr, C.byref(rcs), _ptr(ref_rho),
+                              _ptr(ref_ax), _ptr(ref_ay), _ptr(ref_az), int(max_shuffles),
+                              float(ke_frac), C.byref(ns), C.byref(k0), C.byref(k1)))
+    return ns.value, k0.value, k1.value
+
+
 def apr_neighbours(ctx, st, h, mode=0, count_only=False):
     """Neighbour slots per particle for the given h (device float64 [n]).
     Returns (offsets [n+1], list) as device int64 tensors, or only the total

@@ -238,6 +238,33 @@ int apr_vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
                zbar, mbar);
 }
 
+int apr_relax(apr_ctx *c, apr_state *s, apr_ctx *rc, const apr_state *ref, const void *ref_rho,
+              const void *ref_ax, const void *ref_ay, const void *ref_az, int32_t max_shuffles,
+              double ke_frac, int32_t *n_shuffles, double *ke_first, double *ke_last)
+{
+    int r = check_state(c, s, true);
+    if (r) return r;
+    if (!rc || rc == c) return fail(c, APR_ERR_INVALID, "a separate reference context is needed");
+    r = check_state(rc, ref, false);
+    if (r) return fail(c, APR_ERR_INVALID, "reference state: " + rc->err);
+    if (!ref_rho || !ref_ax || !ref_ay || !ref_az)
+        return fail(c, APR_ERR_INVALID, "reference rho and accelerations are required");
+    const apr_params &p = c->p, &q = rc->p;
+    bool same = p.precision == q.precision && p.kernel == q.kernel && p.m0 == q.m0 &&
+                p.periodic == q.periodic;
+    for (int k = 0; k < 3; ++k)
+        same = same && p.box_lo[k] == q.box_lo[k] && p.box_hi[k] == q.box_hi[k];
+    if (!same) return fail(c, APR_ERR_INVALID, "reference context: other precision, kernel, box or m0");
+    if (rc->cells_n != ref->n) return fail(c, APR_ERR_INVALID, "build the reference cells first");
+    if (ref->next_id < 1 || ref->next_id > (int64_t)INT32_MAX)
+        return fail(c, APR_ERR_INVALID, "reference next_id out of range");
+    if (max_shuffles < 1 || max_shuffles > 1000 || !(ke_frac >= 0.0))
+        return fail(c, APR_ERR_INVALID, "max_shuffles in 1..1000, ke_frac >= 0");
+    if (p.eos == APR_EOS_ADIABATIC && !s->u) return fail(c, APR_ERR_INVALID, "u is required");
+    return relax(c, s, rc, ref, ref_rho, ref_ax, ref_ay, ref_az, max_shuffles, ke_frac,
+                 n_shuffles, ke_first, ke_last);
+}
+
 int apr_neighbours(apr_ctx *c, const apr_state *s, const double *h, int32_t mode,
                    int64_t *counts, int64_t *offsets, int64_t *list, int64_t cap,
                    int64_t *total)

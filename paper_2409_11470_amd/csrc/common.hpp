@@ -251,6 +251,11 @@ int vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, cons
         const void *h_bar, const void *ax_bar, const void *ay_bar, const void *az_bar,
         const void *dudt_bar, void *xbar, void *ybar, void *zbar, void *mbar);
 
+// relax.hip
+int relax(apr_ctx *c, apr_state *s, apr_ctx *rc, const apr_state *ref, const void *ref_rho,
+          const void *ref_ax, const void *ref_ay, const void *ref_az, int32_t max_shuffles,
+          double ke_frac, int32_t *n_shuffles, double *ke_first, double *ke_last);
+
 // neighbours.hip
 int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_t *counts,
                int64_t *offsets, int64_t *list, int64_t cap, int64_t *total);

@@ -1,0 +1,122 @@
+"""Relaxing (paper Sec. 2.4) on the GPU (apr_relax) against the oracle's.
+
+Both sides start from the same seeded input: the reference set is the
+sound-wave box (workload 6, nx = 16, 3456 particles) and the new set is one
+split pass of it with the cylinder zone (108 children), made by the oracle's
+split.  Each side solves the reference set's density and forces itself, then
+shuffles.  FP64 form: the number of shuffles, the first and last KE (1e-9
+relative) and every position per id (1e-9 of the box); FP32 form: five
+shuffles, positions within 2e-3 of the largest displacement."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2409_11470_amd as A
+import workloads as W
+from _gpu import params_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(kernel=0, hfact=1.2):
+    st, p = W.wave_box(nx=16, hfact=hfact)
+    p = dict(p, kernel=kernel, hfact=hfact)
+    box = dict(periodic=True, lo=p["lo"], hi=p["hi"])
+    new = oracle.split_merge(st, p["zones"], step=1, seed=7, r_sep_factor=0.2, nn_cap=0.0,
+                             split_mode=0, do_merge=False, **box)
+    assert new["n_split"] > 50
+    return st, new, p, box
+
+
+def _oracle(st, new, p, box, **kw):
+    d = oracle.density(st["x"], st["y"], st["z"], st["level"], st["h"], m0=p["m0"], tol=1e-12,
+                       max_iter=60, hfact=p["hfact"], kernel=p["kernel"], **box)
+    ref = dict(st, h=d["h"])
+    f = oracle.forces(ref["x"], ref["y"], ref["z"], ref["vx"], ref["vy"], ref["vz"], ref["u"],
+                      ref["level"], d["h"], d["rho"], d["omega"], m0=p["m0"], eos=2,
+                      gamma=p["gamma"], kernel=p["kernel"], **box)
+    s = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in new.items()}
+    ns, kes = oracle.relax(s, ref, d["rho"], np.array([f["ax"], f["ay"], f["az"]]), m0=p["m0"],
+                           eos=2, gamma=p["gamma"], hfact=p["hfact"], kernel=p["kernel"], **box,
+                           **kw)
+    return s, ns, kes
+
+
+def _gpu(st, new, p, prec, max_shuffles, ke_frac):
+    par = params_for(p, prec)
+    rctx, ctx = A.Context(par), A.Context(par)
+    dr = A.DeviceState.from_numpy(st)
+    A.apr_build_cells(rctx, dr)
+    dt = rctx.dtype
+    n = dr.n
+    rho, om = (torch.zeros(n, dtype=dt, device="cuda") for _ in range(2))
+    A.apr_density(rctx, dr, rho, om)
+    a = [torch.zeros(n, dtype=dt, device="cuda") for _ in range(4)]
+    A.apr_forces(rctx, dr, rho, om, *a)
+    A.apr_sync_status(rctx)
+    ds = A.DeviceState.from_numpy(new)
+    ns, k0, k1 = A.apr_relax(ctx, ds, rctx, dr, rho, a[0], a[1], a[2], max_shuffles, ke_frac)
+    A.apr_sync_status(ctx)
+    g = ds.to_numpy()
+    order = np.argsort(g["id"])
+    return {k: (v[order] if isinstance(v, np.ndarray) else v) for k, v in g.items()}, ns, k0, k1
+
+
+def _by_id(s):
+    order = np.argsort(s["id"])
+    return {k: (v[order] if isinstance(v, np.ndarray) else v) for k, v in s.items()}
+
+
+@pytest.mark.parametrize("kernel,hfact", [(0, 1.2), (1, 1.3)])
+def test_relax_fp64_matches_oracle(kernel, hfact):
+    st, new, p, box = _inputs(kernel, hfact)
+    o, ns_o, kes = _oracle(st, new, p, box)
+    g, ns_g, k0, k1 = _gpu(st, new, p, "fp64", 50, 0.005)
+    o = _by_id(o)
+    assert ns_g == ns_o
+    assert abs(k0 / kes[0] - 1) < 1e-9 and abs(k1 / kes[-1] - 1) < 1e-9
+    assert np.array_equal(g["id"], o["id"])
+    L = np.asarray(p["hi"], float)
+    for a, k in enumerate(("x", "y", "z")):
+        d = g[k] - o[k]
+        d -= L[a] * np.round(d / L[a])
+        assert np.max(np.abs(d)) < 1e-9, k
+    # something moved, and only the split particles
+    moved = np.sqrt(sum((o[k] - _by_id(new)[k]) ** 2 for k in ("x", "y", "z"))) > 0
+    assert moved.sum() == 2 * new["n_split"]
+
+
+def test_relax_fp32_five_shuffles():
+    st, new, p, box = _inputs()
+    o, ns_o, kes = _oracle(st, new, p, box, max_shuffles=5, ke_frac=0.0)
+    g, ns_g, k0, k1 = _gpu(st, new, p, "fp32", 5, 0.0)
+    o, n0 = _by_id(o), _by_id(new)
+    assert ns_g == ns_o == 5
+    assert abs(k0 / kes[0] - 1) < 1e-3
+    L = np.asarray(p["hi"], float)
+    disp = np.sqrt(sum((o[k] - n0[k]) ** 2 for k in ("x", "y", "z")))
+    for a, k in enumerate(("x", "y", "z")):
+        d = g[k] - o[k]
+        d -= L[a] * np.round(d / L[a])
+        assert np.max(np.abs(d)) < 2e-3 * disp.max(), k
+
+
+def test_relax_rejects_bad_arguments():
+    st, new, p, box = _inputs()
+    par = params_for(p, "fp64")
+    ctx, rctx = A.Context(par), A.Context(par)
+    dr = A.DeviceState.from_numpy(st)
+    ds = A.DeviceState.from_numpy(new)
+    z = torch.zeros(dr.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(A.AprError):   # reference cells not built
+        A.apr_relax(ctx, ds, rctx, dr, z, z, z, z)
+    A.apr_build_cells(rctx, dr)
+    with pytest.raises(A.AprError):   # the same context twice
+        A.apr_relax(ctx, ds, ctx, dr, z, z, z, z)
+    other = A.Context(params_for(dict(p, kernel=1), "fp64"))
+    A.apr_build_cells(other, dr)
+    with pytest.raises(A.AprError):   # another kernel
+        A.apr_relax(ctx, ds, other, dr, z, z, z, z)
+    with pytest.raises(A.AprError):   # no shuffles asked for
+        A.apr_relax(ctx, ds, rctx, dr, z, z, z, z, max_shuffles=0)
