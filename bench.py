@@ -20,7 +20,8 @@ refined box (one split pass over 262144 particles, then density + forces +
 adjoint on the 362k-particle result, both forms), the same box and step with
 the Wendland C2 kernel (h_fact 1.3, FP32 form), the sound-wave box of the
 paper's appendix A (run to t = 2 with and without its refinement zone; the
-density blip at the zone boundary), the 1M-particle planet disc
+density blip at the zone boundary), relaxing after that box's split, the
+1M-particle planet disc
 stepped with its refinement zone (every step: cells, density, split/merge,
 forces, sink gravity, leapfrog) and the 8M-particle circumbinary disc (FP32
 density + forces + adjoint).
@@ -346,6 +347,39 @@ def leg_wave_box(A, torch, W):
     return out
 
 
+def leg_relax(A, torch, W):
+    """Relaxing (Sec. 2.4) after the sound-wave box's split at t = 0 (56832
+    particles, 1758 split), FP32 form: the paper's limits (50 shuffles, KE
+    down to 0.5 %); wall time per shuffle (cells, density, forces,
+    interpolation from the reference set, shift)."""
+    st, p = W.wave_box()
+    p = dict(p, nn_cap=0.0)  # the split context has no density pass of its own
+    par = make_ctx(A, p, "fp32", seed=5).params
+    rctx, ctx = A.Context(par), A.Context(par)
+    dr = A.DeviceState.from_numpy(st)
+    A.apr_build_cells(rctx, dr)
+    n = dr.n
+    rho, om = (torch.zeros(n, device="cuda") for _ in range(2))
+    A.apr_density(rctx, dr, rho, om)
+    a = [torch.zeros(n, device="cuda") for _ in range(4)]
+    A.apr_forces(rctx, dr, rho, om, *a)
+    A.apr_sync_status(rctx)
+    ds = dr.clone()
+    ds.grow(2 * n)
+    ns, _, _ = A.apr_split_merge(ctx, ds, p["zones"], 1, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k, ke0, ke1 = A.apr_relax(ctx, ds, rctx, dr, rho, a[0], a[1], a[2], 50, 0.005)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    A.apr_sync_status(ctx)
+    rctx.close()
+    ctx.close()
+    return dict(workload="sound-wave box, 56832 particles, relaxing after its split at t = 0",
+                n_split=ns, shuffles=k, ke_ratio=ke1 / ke0 if ke0 > 0 else 0.0,
+                ms_per_shuffle=1e3 * wall / max(k, 1))
+
+
 def leg_circumbinary(A, torch, W, reps):
     """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint."""
     st, p = W.circumbinary_disc()
@@ -446,6 +480,10 @@ def main():
         log("wave box: blip %.4f (M4), %.4f (Wendland C2), %.3f ms/step"
             % (legs["wave_box_blip"]["m4"]["blip"], legs["wave_box_blip"]["wc2"]["blip"],
                legs["wave_box_blip"]["m4"]["ms_per_step"]))
+        legs["relax_wave_box"] = leg_relax(A, torch, W)
+        log("relax: %d shuffles, KE ratio %.3f, %.3f ms per shuffle"
+            % (legs["relax_wave_box"]["shuffles"], legs["relax_wave_box"]["ke_ratio"],
+               legs["relax_wave_box"]["ms_per_shuffle"]))
         legs["planet_disc_steps"] = leg_planet_disc(A, torch, W, 10)
         log("planet disc: %.3e interactions/s, %.2f ms/step"
             % (legs["planet_disc_steps"]["value"], legs["planet_disc_steps"]["ms_per_step"]))
