@@ -1,0 +1,68 @@
+"""Degenerate inputs through the C ABI.
+
+- An empty state (n = 0): every entry point that takes a state returns
+  APR_ERR_INVALID (a bad n / capacity), and the context stays usable.
+- Coincident particles: pairs at r = 0 count in the density (W(0)), add
+  nothing to the forces, and give a nearest-neighbour distance of 0; the GPU
+  agrees with the oracle per particle (FP64 form)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2409_11470_amd as A
+import workloads as W
+from _gpu import gpu_density, gpu_forces, oracle_density, oracle_forces, params_for
+
+pytestmark = pytest.mark.gpu
+
+
+def test_empty_state_rejected_and_context_usable():
+    st, p = W.lattice_box(nside=16)
+    ctx = A.Context(params_for(p, "fp64"))
+    empty = A.DeviceState(8)
+    assert empty.n == 0
+    z = torch.zeros(8, dtype=torch.float64, device="cuda")
+    calls = [
+        lambda: A.apr_build_cells(ctx, empty),
+        lambda: A.apr_density(ctx, empty, z, z),
+        lambda: A.apr_forces(ctx, empty, z, z, z, z, z, z),
+        lambda: A.apr_split_merge(ctx, empty, [], 0),
+        lambda: A.apr_step(ctx, empty, [], [], 1e-3, 0),
+        lambda: A.apr_accel(ctx, empty),
+        lambda: A.apr_timestep(ctx, empty),
+    ]
+    for call in calls:
+        with pytest.raises(A.AprError) as e:
+            call()
+        assert e.value.code == A.APR_ERR_INVALID
+    # the same context then works on a real state
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_build_cells(ctx, ds)
+    rho, om = (torch.zeros(ds.n, dtype=torch.float64, device="cuda") for _ in range(2))
+    A.apr_density(ctx, ds, rho, om)
+    assert A.apr_sync_status(ctx) == 0
+    o = oracle_density(st, p)
+    g = np.empty(ds.n)
+    g[ds["id"].cpu().numpy()] = rho.cpu().numpy()
+    assert np.max(np.abs(g / o["rho"] - 1)) < 1e-9
+
+
+def test_coincident_particles():
+    st, dx = W.random_cluster(300, seed_k=77, levels=(0, 1), vscale=0.3)
+    # particle 1 and 2 sit exactly on particle 0
+    for k in ("x", "y", "z"):
+        st[k][1] = st[k][0]
+        st[k][2] = st[k][0]
+    p = dict(m0=1.0, eos=2, periodic=False, lo=(-1, -1, -1), hi=(2, 2, 2))
+    g, ctx, ds, (rho, om) = gpu_density(st, p, "fp64")
+    o = oracle_density(st, p)
+    assert g["failures"] == o["failures"] == 0
+    for k in ("h", "rho", "omega"):
+        assert np.max(np.abs(g[k] - o[k]) / np.abs(o[k])) < 1e-9, k
+    assert np.array_equal(g["nneigh"], o["nneigh"])
+    assert o["dnn"][0] == o["dnn"][1] == o["dnn"][2] == 0.0
+    gf = gpu_forces(ctx, ds, rho, om)
+    of = oracle_forces(st, p, o["h"], o["rho"], o["omega"])
+    da = np.sqrt(sum((gf[k] - of[k]) ** 2 for k in ("ax", "ay", "az")))
+    assert np.max(da / of["anorm"]) < 1e-9
+    assert np.max(np.abs(gf["dudt"] - of["dudt"]) / of["unorm"]) < 1e-9
