@@ -70,14 +70,16 @@ struct DensArgs {
 // Per-lane partial sums of one Newton evaluation (kernel K).
 template <class T, int K>
 struct DSum {
-    Acc<T> w, d, k;  // sum m f, sum m (3f + q f'), sum m (12 f + 8 q f' + q^2 f'')
+    Acc<T> w, d;  // sum m f, sum m (3f + q f'), compensated
+    T k;          // sum m (12 f + 8 q f' + q^2 f''): only Halley's correction of the
+                  // Newton step uses it, so a plain sum suffices (one register fewer)
     int cnt;       // neighbours in the low 16 bits, those at r = 0 above
     T dmin;
     __device__ void zero()
     {
         w.zero();
         d.zero();
-        k.zero();
+        k = T(0);
         cnt = 0;
         dmin = T(3.0e38);
     }
@@ -93,7 +95,7 @@ struct DSum {
             const T kk = T(12) * f + q * (T(8) * df + q * d2f);
             w.add(m * f);
             d.add(m * g);
-            k.add(m * kk);
+            k += m * kk;
             bool zero = !(r2 > T(0));
             cnt += zero ? 0x10001 : 1;
             T rr = zero ? T(3.0e38) : r;
@@ -104,7 +106,7 @@ struct DSum {
     {
         w.reduce16();
         d.reduce16();
-        k.reduce16();
+        k = wsum16(k);
         cnt = wsum16(cnt);
         dmin = wmin16(dmin);
     }
@@ -367,7 +369,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         bool pending = false;
         S.w.template reduce<kLanes>();
         S.d.template reduce<kLanes>();
-        S.k.template reduce<kLanes>();
+        S.k = sum4(S.k);
         int cnt4 = sum4(S.cnt);
         int nn = cnt4 & 0xffff, nzero = cnt4 >> 16;
         T dmin = min4(S.dmin);
@@ -382,7 +384,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
             double hn;
             if (dF > 0.0) {
-                const double d2rho = (a.m0 / kPi) * S.k.value() * hi3 * hi * hi;
+                const double d2rho = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
                 const double d2F = d2rho - 12.0 * rhoh * hi * hi;
                 const double x = F * d2F / (2.0 * dF * dF);
                 hn = hh - F / (fabs(x) < 0.5 ? dF * (1.0 - x) : dF);
