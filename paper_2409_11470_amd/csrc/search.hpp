@@ -38,9 +38,10 @@ constexpr int kLanes = 4;        // lanes per target (one target per lane group 
 constexpr int kTCap = 128;       // per-target candidate list (u16 LDS indices)
 // Workgroups per CU the density and force kernels are compiled for: the FP32
 // kernels fit 4 (LDS <= 40 KB, <= 128 VGPRs) to hide the latency of the
-// candidate loads and LDS walks; the FP64 ones need more registers.
+// candidate loads and LDS walks; the FP64 ones fit 3 (<= 168 VGPRs, a few
+// spills), which hides more latency than 2 without spills does.
 template <class T>
-constexpr int kBlocksPerCU = sizeof(T) == 4 ? 4 : 2;
+constexpr int kBlocksPerCU = sizeof(T) == 4 ? 4 : 3;
 
 // Orders LDS traffic between the lanes of one wavefront (a compiler and
 // memory fence at wavefront scope; the wavefront runs in lockstep).
