@@ -21,6 +21,7 @@ _d = C.POINTER(C.c_double)
 _i8 = C.POINTER(C.c_int8)
 _i32 = C.POINTER(C.c_int32)
 _i64 = C.POINTER(C.c_int64)
+_u8 = C.POINTER(C.c_uint8)
 
 
 def lib():
@@ -90,7 +91,8 @@ def lib():
                                       _i8, _i64, _i64, _d, C.c_int32, _d, _i32, _d, _i32,
                                       _i32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                       C.c_int32, C.c_uint64, C.c_int64, C.c_int32, _d, _d,
-                                      C.c_int32, C.c_int32, _i64, _i64, _i64, _i64]
+                                      C.c_int32, C.c_int32, _i64, _i64, _i64, _i64, _u8, _i64,
+                                      _u8]
         _LIB = L
     return _LIB
 
@@ -321,12 +323,15 @@ def pair_tree(cand, x, y, z, ids, lo, hi):
 
 def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_mode=0,
                 background=0, derefine=False, periodic=False, lo=(0, 0, 0), hi=(1, 1, 1),
-                dnn=None, cap=None, do_split=True, do_merge=True):
+                dnn=None, cap=None, do_split=True, do_merge=True, active=None):
     """One split/merge pass on a dict of numpy SoA arrays.
 
     st holds x, y, z, vx, vy, vz, u, h (float64), level (int8), id (int64) and
     next_id (int).  Returns a new dict (arrays trimmed to the new n) plus the
-    counts n_split, n_merged, n_spare."""
+    counts n_split, n_merged, n_spare, origin (each particle's slot before the
+    pass; an appended child's is its parent's) and changed (made by a split or
+    kept by a merge).  active (bool [n], optional): only those particles split
+    or pair for merging (individual timesteps, paper Sec. 2.5)."""
     n = st["x"].shape[0]
     cap = cap if cap is not None else 2 * n + 2
     w = {}
@@ -342,6 +347,9 @@ def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_m
     nz, zc, zn, zr, ze, zs = _zones_arrays(zones)
     lo, hi = _box(lo, hi)
     dn = None if dnn is None else _f64(dnn)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    origin = np.zeros(cap, np.int64)
+    changed = np.zeros(cap, np.uint8)
     n_out, ns, nm, nsp = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
     rc = lib().orc_split_merge(n, cap, *[_p(w[k], _d) for k in ("x", "y", "z", "vx", "vy", "vz",
                                                                  "u", "h")],
@@ -352,7 +360,8 @@ def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_m
                                C.c_uint64(seed & (2**64 - 1)), step, int(bool(periodic)),
                                _p(lo, _d), _p(hi, _d), int(bool(do_split)),
                                int(bool(do_merge)), C.byref(n_out), C.byref(ns), C.byref(nm),
-                               C.byref(nsp))
+                               C.byref(nsp), None if act is None else act.ctypes.data_as(_u8),
+                               _p(origin, _i64), changed.ctypes.data_as(_u8))
     if rc != 0:
         raise RuntimeError("oracle split_merge: capacity %d too small, need %d" % (cap, ns.value))
     m = n_out.value
@@ -361,6 +370,8 @@ def split_merge(st, zones, *, step, seed, r_sep_factor=0.2, nn_cap=0.35, split_m
     out["id"] = ids[:m].copy()
     out["next_id"] = nid.value
     out["n_split"], out["n_merged"], out["n_spare"] = ns.value, nm.value, nsp.value
+    out["origin"] = origin[:m].copy()     # slot before the pass (children: the parent's)
+    out["changed"] = changed[:m].astype(bool)
     return out
 
 
@@ -440,3 +451,112 @@ def relax(st, ref, ref_rho, ref_a, *, m0, eos, hfact=1.2, kernel=KERNEL_M4, cs0=
         if kes[-1] <= ke_frac * kes[0]:
             break
     return len(kes), kes
+
+
+# ------------------------------------------------------- individual timesteps
+def courant_bin(h, vsig, *, dt_max, c_cfl, max_bin):
+    """Timestep bin from the Courant limit dt_C = c_cfl h / vsig: the smallest
+    k >= 0 with dt_max 2^-k <= dt_C, at most max_bin (an integer search, so
+    that the decision is exact)."""
+    dtc = c_cfl * np.asarray(h, float) / np.asarray(vsig, float)
+    k = np.zeros(dtc.shape[0], np.int8)
+    for b in range(max_bin):
+        k += (k == b) & (np.ldexp(dt_max, -b) > dtc)
+    return k
+
+
+_PERSIST = ("rho", "omega", "ax", "ay", "az", "dudt", "vsig", "dnn", "bin")
+
+
+def accel_bins(st, *, m0, eos, hfact=1.2, kernel=KERNEL_M4, cs0=1.0, q_cs=0.25, r_ref=1.0,
+               gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, lo=(0, 0, 0),
+               hi=(1, 1, 1), sinks=(), G=1.0, targets=None, tol=1e-12):
+    """Density (h-rho solve), forces and sink gravity for the targets (all if
+    None), stored in st: h, rho, omega, dnn, ax, ay, az, dudt, vsig.  The
+    other particles keep their stored values, which their neighbours use."""
+    n = st["x"].shape[0]
+    idx = np.arange(n) if targets is None else np.asarray(targets, np.int64)
+    if idx.size == 0:
+        return
+    box = dict(periodic=periodic, lo=lo, hi=hi)
+    d = density(st["x"], st["y"], st["z"], st["level"], st["h"][idx], m0=m0, hfact=hfact,
+                tol=tol, max_iter=60, kernel=kernel, targets=idx, **box)
+    for k in ("rho", "omega", "dnn"):
+        if k not in st:
+            st[k] = np.ones(n)
+    st["h"][idx], st["rho"][idx], st["omega"][idx], st["dnn"][idx] = (
+        d["h"], d["rho"], d["omega"], d["dnn"])
+    f = forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st.get("u"),
+               st["level"], st["h"], st["rho"], st["omega"], m0=m0, eos=eos, cs0=cs0,
+               q_cs=q_cs, r_ref=r_ref, gamma=gamma, alpha=alpha, beta=beta, kernel=kernel,
+               targets=idx, **box)
+    if sinks:
+        sink_gravity(st["x"][idx], st["y"][idx], st["z"][idx], [s_["x"] for s_ in sinks],
+                     [s_["m"] for s_ in sinks], [s_.get("eps", 0.0) for s_ in sinks], G,
+                     f["ax"], f["ay"], f["az"])
+    for k in ("ax", "ay", "az", "dudt", "vsig"):
+        if k not in st:
+            st[k] = np.zeros(n)
+        st[k][idx] = f[k]
+
+
+def step_bins(st, *, zones, dt_max, step, max_bin, c_cfl=0.3, seed=0, r_sep_factor=0.2,
+              nn_cap=0.35, split_mode=0, **phys):
+    """One step of length dt_max with individual timesteps (paper Sec. 2.5).
+
+    st holds the state and, per particle, bin (int8) and the stored rho, omega,
+    dnn, ax, ay, az, dudt, vsig of its last evaluation (accel_bins).  Bin k
+    steps with dt_max 2^-k; K = max bin, 2^K substeps of dt_max 2^-K.  In
+    substep s a particle whose step starts (s a multiple of 2^(K-k)) takes its
+    opening half kick (v, and u if adiabatic, with its own dt); every
+    particle drifts; the particles whose step ends ((s+1) a multiple of
+    2^(K-k)) are active: the split/merge pass examines only them (random key
+    step 4096 + s), density, forces and sink gravity are taken for them (and
+    for what the pass made), they take their closing half kick, and their bin
+    follows the Courant limit, clamped to K, lengthened only where the longer
+    step starts at this boundary; what the pass made or kept takes bin K.
+    Returns the new state dict."""
+    box = dict(periodic=phys.get("periodic", False), lo=phys.get("lo", (0, 0, 0)),
+               hi=phys.get("hi", (1, 1, 1)))
+    adiab = phys["eos"] == EOS_ADIABATIC
+    st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    K = int(st["bin"].max())
+    nsub = 1 << K
+    delta = np.ldexp(dt_max, -K)
+    for s in range(nsub):
+        b = st["bin"].astype(np.int64)
+        stride = np.left_shift(1, K - b)
+        dta = np.ldexp(dt_max, -b)
+        op = (s % stride) == 0
+        for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az")) + ((("u", "dudt"),) if adiab else ()):
+            st[v][op] += 0.5 * dta[op] * st[a][op]
+        drift(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], delta, **box)
+        act = ((s + 1) % stride) == 0
+        if zones:
+            out = split_merge(st, zones, step=step * 4096 + s, seed=seed,
+                              r_sep_factor=r_sep_factor, nn_cap=nn_cap, split_mode=split_mode,
+                              dnn=st["dnn"], active=act, **box)
+            o = out["origin"]
+            new = {k: out[k] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level", "id",
+                                       "next_id")}
+            for k in _PERSIST:
+                new[k] = st[k][o].copy()
+            act = act[o] | out["changed"]
+            made = out["changed"]
+            st = new
+        else:
+            made = np.zeros(st["x"].shape[0], bool)
+        idx = np.nonzero(act)[0]
+        accel_bins(st, targets=idx, **phys)
+        b = st["bin"].astype(np.int64)
+        dta = np.ldexp(dt_max, -b)
+        for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az")) + ((("u", "dudt"),) if adiab else ()):
+            st[v][act] += 0.5 * dta[act] * st[a][act]
+        kc = courant_bin(st["h"], st["vsig"], dt_max=dt_max, c_cfl=c_cfl, max_bin=K).astype(
+            np.int64)
+        for i in idx:
+            k = K if made[i] else int(kc[i])
+            while (s + 1) % (1 << (K - k)):
+                k += 1
+            st["bin"][i] = k
+    return st

@@ -771,6 +771,12 @@ int64_t orc_pair_tree(int64_t nc, const int64_t *cand, const double *x, const do
 /* below l: the lower id is kept at the centre of mass with the mean        */
 /* velocity and mean u (mass is equal), level l - 1 and h 2^(1/3); the other */
 /* is removed.  Survivors keep their order.                                 */
+/* With individual timesteps (paper Sec. 2.5) only the particles with      */
+/* active[a] != 0 are examined for splitting or paired for merging (active */
+/* NULL: all).  origin (room for cap, may be NULL) receives, per slot after */
+/* the pass, the slot the particle held before it (an appended child: its  */
+/* parent's); changed_out (room for cap, may be NULL) flags the particles  */
+/* a split made or a merge kept.                                           */
 /* Arrays must have room for `cap` particles.  Returns 0, or 2 if the        */
 /* splits need more than cap (then nothing is changed and *n_split holds the */
 /* number of particles needed).                                             */
@@ -783,7 +789,8 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
                         int32_t derefine, double r_sep_factor, double nn_cap, int32_t split_mode, uint64_t seed,
                         int64_t step, int32_t periodic, const double *lo, const double *hi,
                         int32_t do_split, int32_t do_merge, int64_t *n_out, int64_t *n_split,
-                        int64_t *n_merged, int64_t *n_spare)
+                        int64_t *n_merged, int64_t *n_spare, const unsigned char *active,
+                        int64_t *origin, unsigned char *changed_out)
 {
     orc_zones Z = {nz, zc, znsh, zr, zell, zshape, background, derefine};
     int64_t ns = 0;
@@ -792,13 +799,16 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
     unsigned char *changed = (unsigned char *)calloc((size_t)(cap > 0 ? cap : 1), 1);
     int *zone_of = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
     unsigned char *do_sp = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    const int64_t n0 = n;
+    if (origin)
+        for (int64_t a = 0; a < n; ++a) origin[a] = a;
 
     if (do_split) {
         for (int64_t a = 0; a < n; ++a) {
             int w;
             int lz = zone_level(&Z, x[a], y[a], z[a], &w);
             zone_of[a] = w;
-            if (level[a] < lz) { do_sp[a] = 1; ns += 1; }
+            if (level[a] < lz && (!active || active[a])) { do_sp[a] = 1; ns += 1; }
         }
         if (n + ns > cap) {
             *n_split = n + ns;
@@ -831,6 +841,7 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
             level[slot] = level[a];
             id[slot] = *next_id + (slot - n);
             changed[a] = 1; changed[slot] = 1;
+            if (origin) origin[slot] = a;
             slot += 1;
         }
         *next_id += ns;
@@ -848,7 +859,9 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
         for (int l = lmax; l >= 1; --l) {
             int64_t nc = 0;
             for (int64_t a = 0; a < n; ++a)
-                if (level[a] == l && !changed[a] && !removed[a]) cand[nc++] = a;
+                if (level[a] == l && !changed[a] && !removed[a] &&
+                    (a >= n0 || !active || active[a]))
+                    cand[nc++] = a;
             if (nc % 2) *n_spare += 1;
             int64_t np = orc_pair_tree(nc, cand, x, y, z, id, lo, hi, n, pairs);
             for (int64_t k = 0; k < np; ++k) {
@@ -878,6 +891,8 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
                 x[w] = x[a]; y[w] = y[a]; z[w] = z[a];
                 vx[w] = vx[a]; vy[w] = vy[a]; vz[w] = vz[a];
                 u[w] = u[a]; h[w] = h[a]; level[w] = level[a]; id[w] = id[a];
+                changed[w] = changed[a];
+                if (origin) origin[w] = origin[a];
             }
             w += 1;
         }
@@ -885,6 +900,8 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
         free(removed); free(cand); free(pairs);
     }
     *n_out = n;
+    if (changed_out)
+        for (int64_t a = 0; a < n; ++a) changed_out[a] = changed[a];
     free(changed); free(zone_of); free(do_sp);
     return 0;
 }
