@@ -671,6 +671,12 @@ static int cmp_id(const void *pa, const void *pb)
     return (g_tree->id[p] > g_tree->id[q]) - (g_tree->id[p] < g_tree->id[q]);
 }
 
+static int cmp_i64(const void *pa, const void *pb)
+{
+    int64_t p = *(const int64_t *)pa, q = *(const int64_t *)pb;
+    return (p > q) - (p < q);
+}
+
 /* idx[0..n) in ascending id order; appends the leaf pairs to pairs */
 static void pair_tree(const tree_ctx *T, int64_t *idx, int64_t n, int64_t *pairs,
                       int64_t *npairs)
@@ -763,6 +769,9 @@ int64_t orc_pair_tree(int64_t nc, const int64_t *cand, const double *x, const do
 /* One split/merge pass over all particles (paper Sec. 2.5 and Fig. 2:      */
 /* split from the lowest level up, then merge from the highest level down;  */
 /* a particle changes level at most once per pass).                         */
+/* Split: each child is appended after the survivors; the children are     */
+/* numbered next_id, next_id + 1, ... in ascending order of their parents'  */
+/* ids, so the numbering does not depend on the order of the arrays.       */
 /* Merge (paper Sec. 2.3), for l = l_max .. 1: the candidates are the level- */
 /* l particles not changed earlier in this pass, in ascending id order; if  */
 /* their number is odd the highest id is left out until the next pass (the  */
@@ -815,9 +824,17 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
             free(changed); free(zone_of); free(do_sp);
             return 2;
         }
+        /* the children are numbered in the order of their parents' ids */
+        int64_t *pid = (int64_t *)malloc((size_t)(ns > 0 ? ns : 1) * sizeof(int64_t));
+        int64_t np = 0;
+        for (int64_t a = 0; a < n; ++a)
+            if (do_sp[a]) pid[np++] = id[a];
+        qsort(pid, (size_t)np, sizeof(int64_t), cmp_i64);
         int64_t slot = n;
         for (int64_t a = 0; a < n; ++a) {
             if (!do_sp[a]) continue;
+            const int64_t *at = (const int64_t *)bsearch(&id[a], pid, (size_t)np, sizeof(int64_t),
+                                                         cmp_i64);
             uint64_t s = stream_state(seed, step, id[a]);
             double w[3];
             split_axis(&Z, zone_of[a], split_mode, s, x[a], y[a], z[a], w);
@@ -839,11 +856,12 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
             h[a] = hc; h[slot] = hc;
             level[a] = (int8_t)(level[a] + 1);
             level[slot] = level[a];
-            id[slot] = *next_id + (slot - n);
+            id[slot] = *next_id + (at - pid);
             changed[a] = 1; changed[slot] = 1;
             if (origin) origin[slot] = a;
             slot += 1;
         }
+        free(pid);
         *next_id += ns;
         n = n + ns;
         *n_split = ns;

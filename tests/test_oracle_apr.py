@@ -172,6 +172,28 @@ def test_split_reproducible_and_seeded(orc):
     assert np.array_equal(a["x"], b["x"]) and not np.array_equal(a["x"], c["x"])
 
 
+def test_pass_independent_of_array_order(orc):
+    # children are numbered by their parents' ids, merges pair by id and
+    # position: a permuted copy of the state gives the same particles per id
+    st, p = _small_box(10)
+    n = st["x"].shape[0]
+    st["level"] = np.random.default_rng(2).integers(0, 2, n).astype(np.int8)
+    a = orc.split_merge(st, p["zones"], step=1, seed=3, periodic=True, **BOX)
+    assert a["n_split"] > 20 and a["n_merged"] > 20
+    perm = np.random.default_rng(5).permutation(n)
+    sp = {k: (v[perm] if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    b = orc.split_merge(sp, p["zones"], step=1, seed=3, periodic=True, **BOX)
+    oa, ob = np.argsort(a["id"]), np.argsort(b["id"])
+    assert np.array_equal(a["id"][oa], b["id"][ob])
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level"):
+        assert np.array_equal(a[k][oa], b[k][ob]), k
+    # the children's ids follow their parents' ids
+    kids = a["id"] >= n
+    parent_id = st["id"][a["origin"][kids]]
+    assert np.array_equal(np.argsort(parent_id), np.argsort(a["id"][kids]))
+    assert np.array_equal(np.sort(a["id"][kids]), np.arange(n, n + kids.sum()))
+
+
 def test_capacity_error(orc):
     st, p = _small_box(10)
     with pytest.raises(RuntimeError):
