@@ -513,8 +513,9 @@ def step_bins(st, *, zones, dt_max, step, max_bin, c_cfl=0.3, seed=0, r_sep_fact
     2^(K-k)) are active: the split/merge pass examines only them (random key
     step 4096 + s), density, forces and sink gravity are taken for them (and
     for what the pass made), they take their closing half kick, and their bin
-    follows the Courant limit, clamped to K, lengthened only where the longer
-    step starts at this boundary; what the pass made or kept takes bin K.
+    follows the Courant limit, clamped to K within the step (the substep grid
+    is fixed) and to max_bin at its end, lengthened only where the longer step
+    starts at this boundary; what the pass made or kept takes bin K.
     Returns the new state dict."""
     box = dict(periodic=phys.get("periodic", False), lo=phys.get("lo", (0, 0, 0)),
                hi=phys.get("hi", (1, 1, 1)))
@@ -552,11 +553,12 @@ def step_bins(st, *, zones, dt_max, step, max_bin, c_cfl=0.3, seed=0, r_sep_fact
         dta = np.ldexp(dt_max, -b)
         for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az")) + ((("u", "dudt"),) if adiab else ()):
             st[v][act] += 0.5 * dta[act] * st[a][act]
-        kc = courant_bin(st["h"], st["vsig"], dt_max=dt_max, c_cfl=c_cfl, max_bin=K).astype(
-            np.int64)
+        last = s + 1 == nsub
+        kc = courant_bin(st["h"], st["vsig"], dt_max=dt_max, c_cfl=c_cfl,
+                         max_bin=max_bin if last else K).astype(np.int64)
         for i in idx:
             k = K if made[i] else int(kc[i])
-            while (s + 1) % (1 << (K - k)):
+            while not last and (s + 1) % (1 << (K - k)):
                 k += 1
             st["bin"][i] = k
     return st

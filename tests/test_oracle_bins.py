@@ -126,3 +126,21 @@ def test_pass_examines_active_particles_only(orc):
     assert m_act["n_merged"] == act.sum() // 2
     gone = np.setdiff1d(lv["id"], m_act["id"])
     assert np.all(act[gone])
+
+
+def test_bins_refine_past_k_only_at_the_step_end(orc):
+    # every particle starts in bin 0 (K = 0, one substep) while the Courant
+    # limit asks for bin 2: at the end of the step, where every particle is
+    # synchronised, the bin follows the limit up to max_bin
+    st, p = W.lattice_box(nside=10)
+    st = dict(st, u=np.zeros_like(st["x"]))
+    p = dict(p, m0=1e-3)
+    phys = _phys(p)
+    orc.accel_bins(st, **phys)
+    dtc = 0.3 * st["h"] / st["vsig"]
+    dtm = 3.9 * dtc.min()
+    st["bin"] = np.zeros(st["x"].shape[0], np.int8)
+    a = orc.step_bins(st, zones=[], dt_max=dtm, step=0, max_bin=4, **phys)
+    assert np.all(a["bin"] == 2)
+    b = orc.step_bins(st, zones=[], dt_max=dtm, step=0, max_bin=1, **phys)
+    assert np.all(b["bin"] == 1)
