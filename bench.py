@@ -422,6 +422,55 @@ def leg_planet_disc(A, torch, W, steps):
                 value=inter * steps / wall)
 
 
+def leg_planet_disc_bins(A, torch, W, nsub=64, max_bin=6):
+    """Individual timesteps (Sec. 2.5) on the 1M-particle planet disc with its
+    refinement zone and sink: the same time advanced twice, by `nsub` global
+    steps of the smallest Courant step dt_g, and by one step of dt_max =
+    nsub dt_g with per-particle bins (2^K substeps, K <= max_bin).  Each run
+    starts from the same state, after one untimed step of its own kind."""
+    import numpy as np
+    st, p = W.planet_disc()
+    n = st["x"].shape[0]
+    out = dict(workload="planet disc, 1M particles, refinement sphere r = 1 at (5, 0, 0), "
+                        "random split r_sep = 0.5 h, sink at the origin",
+               form="fp32", n=n)
+    ctx = make_ctx(A, p, "fp32", seed=3)
+    ds = A.DeviceState.from_numpy(st, capacity=3 * n + 64)
+    A.apr_accel(ctx, ds, p["sinks"])
+    dtg = A.apr_timestep(ctx, ds)
+    dt_max = nsub * dtg
+    A.apr_step(ctx, ds, p["zones"], p["sinks"], dtg, 0)
+    A.apr_sync_status(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nsub):
+        A.apr_step(ctx, ds, p["zones"], p["sinks"], dtg, 1 + k)
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - t0
+    A.apr_sync_status(ctx)
+    ctx.close()
+    del ds
+    ctx = make_ctx(A, p, "fp32", seed=3)
+    ds = A.DeviceState.from_numpy(st, capacity=3 * n + 64)
+    A.apr_bins_init(ctx, ds, dt_max, 0.3, max_bin, p["sinks"])
+    A.apr_step_bins(ctx, ds, p["zones"], p["sinks"], dt_max, 0, 0.3, max_bin)
+    A.apr_sync_status(ctx)
+    hist = np.bincount(ds["bin"].cpu().numpy().astype(np.int64), minlength=max_bin + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ns = A.apr_step_bins(ctx, ds, p["zones"], p["sinks"], dt_max, 1, 0.3, max_bin)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    A.apr_sync_status(ctx)
+    # particle updates: every particle is active 2^bin times per dt_max
+    upd = float(np.sum(hist * (2.0 ** np.arange(hist.size))))
+    ctx.close()
+    out.update(dt_global=dtg, dt_max=dt_max, substeps=ns, bins=hist.tolist(),
+               active_fraction=float(upd / (hist.sum() * ns)), global_ms=1e3 * wall_g,
+               bins_ms=1e3 * wall_b, speedup=wall_g / wall_b)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +537,11 @@ def main():
         log("planet disc: %.3e interactions/s, %.2f ms/step"
             % (legs["planet_disc_steps"]["value"], legs["planet_disc_steps"]["ms_per_step"]))
         torch.cuda.empty_cache()
+        legs["planet_disc_bins"] = leg_planet_disc_bins(A, torch, W)
+        log("planet disc over %d dt_g: global %.1f ms, bins %.1f ms (x%.2f), bins %s"
+            % (legs["planet_disc_bins"]["substeps"], legs["planet_disc_bins"]["global_ms"],
+               legs["planet_disc_bins"]["bins_ms"], legs["planet_disc_bins"]["speedup"],
+               legs["planet_disc_bins"]["bins"]))
         legs["circumbinary_forward_adjoint"] = leg_circumbinary(A, torch, W, 3)
         log("circumbinary: fp32 forward+adjoint %.3e interactions/s"
             % legs["circumbinary_forward_adjoint"]["fp32"]["forward_adjoint_rate"])

@@ -196,6 +196,35 @@ int apr_vjp(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega
             const void *az_bar, const void *dudt_bar, void *xbar, void *ybar, void *zbar,
             void *mbar);
 
+/* Individual timesteps (paper Sec. 2.5).  bin [capacity] (device, int8,
+ * caller-owned) holds each particle's timestep bin k: its step is dt_max 2^-k.
+ * apr_bins_init takes density, forces and sink gravity for every particle
+ * (like apr_accel), keeps each particle's rho, Omega, vsig and nearest
+ * distance in the context, and sets every bin from the Courant limit: the
+ * smallest k in 0..max_bin with dt_max 2^-k <= c_cfl h / vsig.
+ * apr_step_bins advances the state by dt_max in 2^K substeps of dt_max 2^-K
+ * (K the largest bin).  In substep s a particle whose step starts (s a
+ * multiple of 2^(K-k)) takes its opening half kick with its own dt; all
+ * particles drift; those whose step ends ((s+1) a multiple of 2^(K-k)) are
+ * active: the split/merge pass examines only them (random key step*4096 + s),
+ * density, forces and sink gravity are taken for them and for what the pass
+ * made (the others keep h, rho, Omega and a from their last turn, which their
+ * neighbours use), and they take their closing half kick; an active
+ * particle's bin then follows the Courant limit, clamped to K within the step
+ * and to max_bin at its end, and lengthens only where the longer step starts
+ * at this boundary; particles a split made or a merge kept take bin K.  The
+ * state and bin are reordered together (cell order); *n_substeps gets 2^K.
+ * The state needs ax, ay, az, dudt and u, and room for the splits of all
+ * substeps (APR_ERR_CAPACITY leaves the step half done).  Any other call that
+ * reorders the state (apr_build_cells, apr_step, apr_split_merge, apr_relax)
+ * voids the stored values: apr_step_bins then returns APR_ERR_INVALID until
+ * apr_bins_init runs again.  Synchronises once per substep with zones. */
+int apr_bins_init(apr_ctx *ctx, apr_state *s, int8_t *bin, const apr_sink *sinks,
+                  int32_t nsinks, double dt_max, double c_cfl, int32_t max_bin);
+int apr_step_bins(apr_ctx *ctx, apr_state *s, int8_t *bin, const apr_zone *zones,
+                  int32_t nzones, const apr_sink *sinks, int32_t nsinks, double dt_max,
+                  double c_cfl, int32_t max_bin, int64_t step, int32_t *n_substeps);
+
 /* Relaxing (paper Sec. 2.4) of the particles a split/merge pass introduced:
  * those of s whose id is not below ref->next_id, or whose level differs from
  * the level ref gives the same id.  Each shuffle computes the hydro
@@ -244,8 +273,9 @@ int apr_neighbours(apr_ctx *ctx, const apr_state *s, const double *h, int32_t mo
  * tangential to the zone (rotated about x - c by a random angle) or random;
  * r_sep = r_sep_factor h, capped at nn_cap * (nearest-neighbour distance from
  * the last apr_density) when nn_cap > 0.  The parent slot keeps the + child;
- * the - children are appended in ascending parent slot, with ids next_id,
- * next_id + 1, ...
+ * the - children are appended in ascending parent slot and numbered next_id,
+ * next_id + 1, ... in ascending parent id (so the ids, and every later pass,
+ * do not depend on the order of the arrays).
  * Random stream: s = F(seed ^ F(id ^ F(step))), F(v) the first SplitMix64
  * output from state v; rotation angle 2 pi U1 (tangential) or axis from
  * (U1, U2) (random), Uk = (k-th SplitMix64 output from s >> 11) 2^-53.

@@ -82,6 +82,11 @@ def lib():
     L.apr_density.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp]
     L.apr_forces.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.apr_vjp.argtypes = [_vp, C.POINTER(CState)] + [_vp] * 12
+    L.apr_bins_init.argtypes = [_vp, C.POINTER(CState), _vp, C.POINTER(Sink), C.c_int32,
+                                C.c_double, C.c_double, C.c_int32]
+    L.apr_step_bins.argtypes = [_vp, C.POINTER(CState), _vp, C.POINTER(Zone), C.c_int32,
+                                C.POINTER(Sink), C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                C.c_int64, C.POINTER(C.c_int32)]
     L.apr_relax.argtypes = [_vp, C.POINTER(CState), _vp, C.POINTER(CState), _vp, _vp, _vp, _vp,
                             C.c_int32, C.c_double, C.POINTER(C.c_int32),
                             C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -99,7 +104,8 @@ def lib():
     L.apr_profile_read.argtypes = [_vp, C.POINTER(C.c_double), _i64p, C.c_int]
     for f in ("apr_ctx_create", "apr_ctx_destroy", "apr_ctx_set_stream", "apr_set_cell_grid",
               "apr_build_cells",
-              "apr_density", "apr_forces", "apr_vjp", "apr_relax", "apr_neighbours",
+              "apr_density", "apr_forces", "apr_vjp", "apr_relax", "apr_bins_init",
+              "apr_step_bins", "apr_neighbours",
               "apr_split_merge", "apr_step",
               "apr_accel", "apr_timestep", "apr_sync_status", "apr_profile_enable",
               "apr_profile_read", "apr_counters"):

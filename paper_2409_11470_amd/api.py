@@ -121,6 +121,7 @@ class DeviceState:
                   for k in _DFIELDS}
         self.t["level"] = torch.zeros(self.capacity, dtype=torch.int8, device=device)
         self.t["id"] = torch.zeros(self.capacity, dtype=torch.int64, device=device)
+        self.t["bin"] = torch.zeros(self.capacity, dtype=torch.int8, device=device)  # timestep bins
 
     @classmethod
     def from_numpy(cls, st, capacity=None, device="cuda"):
@@ -216,6 +217,32 @@ def apr_vjp(ctx, st, rho, omega, rho_bar=None, h_bar=None, ax_bar=None, ay_bar=N
                             _ptr(h_bar), _ptr(ax_bar), _ptr(ay_bar), _ptr(az_bar),
                             _ptr(dudt_bar), *[_ptr(t) for t in out]))
     return tuple(out)
+
+
+def apr_bins_init(ctx, st, dt_max, c_cfl=0.3, max_bin=8, sinks=()):
+    """Individual timesteps: accelerations of every particle and its Courant
+    bin (st["bin"])."""
+    sarr, ns = make_sinks(list(sinks))
+    cs = st.cstate()
+    ctx.check(lib().apr_bins_init(ctx.ptr, C.byref(cs), _ptr(st.t["bin"]), sarr, ns,
+                                  float(dt_max), float(c_cfl), int(max_bin)))
+
+
+def apr_step_bins(ctx, st, zones, sinks, dt_max, step, c_cfl=0.3, max_bin=8):
+    """One step of dt_max with individual timesteps; returns the number of
+    substeps.  With zones the state first gets room for two splits per
+    particle."""
+    zarr, nz = make_zones(zones)
+    sarr, ns = make_sinks(list(sinks))
+    if nz > 0:
+        st.grow(3 * st.n + 64)
+    cs = st.cstate()
+    nsub = C.c_int32()
+    ctx.check(lib().apr_step_bins(ctx.ptr, C.byref(cs), _ptr(st.t["bin"]), zarr, nz, sarr, ns,
+                                  float(dt_max), float(c_cfl), int(max_bin), int(step),
+                                  C.byref(nsub)))
+    st.absorb(cs)
+    return nsub.value
 
 
 def apr_relax(ctx, st, ref_ctx, ref, ref_rho, ref_ax, ref_ay, ref_az, max_shuffles=50,

@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libapr.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["abi.cpp", "sort.hip", "cells.hip", "density.hip", "forces.hip", "neighbours.hip",
-           "integrate.hip", "splitmerge.hip", "adjoint.hip", "candidates.hip", "relax.hip"]
+           "integrate.hip", "splitmerge.hip", "adjoint.hip", "candidates.hip", "relax.hip",
+           "bins.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -49,6 +49,31 @@ void *ws(apr_ctx *c, const char *name, size_t bytes)
     return b.p;
 }
 
+void *ws_keep(apr_ctx *c, const char *name, size_t bytes, size_t keep)
+{
+    for (auto &b : c->bufs) {
+        if (b.name != name) continue;
+        if (b.bytes >= bytes) return b.p;
+        // growing: the first `keep` bytes move to the new buffer
+        void *np = nullptr;
+        size_t nb = bytes + bytes / 4;
+        if (hipMalloc(&np, nb) != hipSuccess) {
+            c->err = std::string("workspace allocation failed: ") + name;
+            return nullptr;
+        }
+        if (keep > 0 &&
+            hipMemcpyAsync(np, b.p, std::min(keep, b.bytes), hipMemcpyDeviceToDevice,
+                           c->stream) != hipSuccess)
+            return nullptr;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return nullptr;
+        if (hipFree(b.p) != hipSuccess) return nullptr;
+        b.p = np;
+        b.bytes = nb;
+        return b.p;
+    }
+    return ws(c, name, bytes);
+}
+
 int prof_begin(apr_ctx *c, int idx)
 {
     if (!c->prof) return -1;
@@ -236,6 +261,45 @@ int apr_vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     if (rc) return rc;
     return vjp(c, s, rho, omega, rho_bar, h_bar, ax_bar, ay_bar, az_bar, dudt_bar, xbar, ybar,
                zbar, mbar);
+}
+
+static int check_bins(apr_ctx *c, const int8_t *bin, double dt_max, double c_cfl, int32_t max_bin,
+                      const apr_sink *sinks, int32_t nsinks)
+{
+    if (!bin) return fail(c, APR_ERR_INVALID, "bin array required");
+    if (!(dt_max > 0.0) || !(c_cfl > 0.0)) return fail(c, APR_ERR_INVALID, "dt_max, c_cfl > 0");
+    if (max_bin < 0 || max_bin > 20) return fail(c, APR_ERR_INVALID, "max_bin in 0..20");
+    if (nsinks < 0 || (nsinks > 0 && !sinks)) return fail(c, APR_ERR_INVALID, "sinks");
+    return APR_OK;
+}
+
+int apr_bins_init(apr_ctx *c, apr_state *s, int8_t *bin, const apr_sink *sinks, int32_t nsinks,
+                  double dt_max, double c_cfl, int32_t max_bin)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    rc = check_bins(c, bin, dt_max, c_cfl, max_bin, sinks, nsinks);
+    if (rc) return rc;
+    if (!s->ax || !s->ay || !s->az || !s->dudt || !s->u)
+        return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt and u");
+    return bins_init(c, s, bin, sinks, nsinks, dt_max, c_cfl, max_bin);
+}
+
+int apr_step_bins(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, int32_t nzones,
+                  const apr_sink *sinks, int32_t nsinks, double dt_max, double c_cfl,
+                  int32_t max_bin, int64_t step, int32_t *n_substeps)
+{
+    int rc = check_state(c, s, true);
+    if (rc) return rc;
+    rc = check_bins(c, bin, dt_max, c_cfl, max_bin, sinks, nsinks);
+    if (rc) return rc;
+    if (!s->ax || !s->ay || !s->az || !s->dudt || !s->u)
+        return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt and u");
+    if (nzones < 0 || (nzones > 0 && !zones)) return fail(c, APR_ERR_INVALID, "zones");
+    for (int k = 0; k < nzones; ++k)
+        if (zones[k].n < 1 || zones[k].n > 8) return fail(c, APR_ERR_INVALID, "zone spheres");
+    return step_bins(c, s, bin, zones, nzones, sinks, nsinks, dt_max, c_cfl, max_bin, step,
+                     n_substeps);
 }
 
 int apr_relax(apr_ctx *c, apr_state *s, apr_ctx *rc, const apr_state *ref, const void *ref_rho,

@@ -49,6 +49,7 @@ struct ForceVJP {
     const V *pm, *vh, *th, *cot;
     T alpha, beta;
     T *out[9];  // xbar[3], mbar, Ptbar, Gbar, cbar, hbar, S2
+    const uint8_t *act = nullptr;  // every target
     __device__ V load(int k, int64_t i) const
     {
         return k == 0 ? pm[i] : (k == 1 ? vh[i] : (k == 2 ? th[i] : cot[i]));
@@ -135,6 +136,7 @@ struct DensVJP {
     const double *xb[3], *mb;
     double scx, scm;   // m0/pi, 1/pi
     T *xbar[3], *mbar;
+    const uint8_t *act = nullptr;  // every target
     __device__ V load(int k, int64_t i) const { return k == 0 ? pm[i] : dv[i]; }
     struct Acc {
         apr::Acc<T> a[4];

@@ -543,6 +543,7 @@ static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_a
 
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
 {
+    if (!c->in_bins) c->bins_n = -1;  // a reorder the stored per-particle values miss
     // the last velocity divergence moves with the particles into "divv_prev"
     // (for the h predictor's extrapolation); "divv" is stale afterwards
     const bool dv = c->divv_n == s->n;

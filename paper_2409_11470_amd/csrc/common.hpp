@@ -93,6 +93,11 @@ struct apr_ctx {
     int64_t divv_prev_n = -1;      // the one before it, carried through the last cell build's
                                    // permutation, is in "divv_prev" (else -1)
     double dt_last = 0.0;          // dt of the last step (the spacing of those two)
+    // individual timesteps: each particle's last rho, Omega, vsig and nearest
+    // distance ("bn_*" workspace, the context precision) follow the state
+    // while only apr_bins_init / apr_step_bins reorder it
+    int64_t bins_n = -1;           // n they are valid for (else -1)
+    bool in_bins = false;          // set while the step driver itself reorders
     // kernel timing: pairs of events per index, summed at read time
     bool prof = false;
     struct EvPair {
@@ -108,6 +113,8 @@ namespace apr {
 
 // Grow-only named device workspace.  Contents are not kept across growth.
 void *ws(apr_ctx *c, const char *name, size_t bytes);
+// The same, but a growing buffer keeps its first `keep` bytes.
+void *ws_keep(apr_ctx *c, const char *name, size_t bytes, size_t keep);
 template <class T>
 T *wsa(apr_ctx *c, const char *name, size_t count)
 {
@@ -237,11 +244,17 @@ const int32_t *cell_start(apr_ctx *c);
 Geo *cell_level(apr_ctx *c, int lev);
 
 // density.hip / forces.hip
-int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters);
+// active (optional, [n], state order): only those targets are solved; the
+// others keep h, rho and Omega (individual timesteps).
+int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters,
+            const uint8_t *active = nullptr);
 // hmax_fresh: the cells' h_max already hold the state's h (a density pass on
 // this state just ran), so the refit from h is skipped.
+// active (optional): only those targets get their sums (outputs of the
+// others untouched).
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh = false);
+           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh = false,
+           const uint8_t *active = nullptr);
 // EOS pack of forces.hip: vh = (v, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0)
 // into the workspace buffers vh32/th32 (FP32) or vh64/th64 (FP64).
 int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega);
@@ -250,6 +263,13 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 int vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, const void *rho_bar,
         const void *h_bar, const void *ax_bar, const void *ay_bar, const void *az_bar,
         const void *dudt_bar, void *xbar, void *ybar, void *zbar, void *mbar);
+
+// bins.hip (individual timesteps)
+int bins_init(apr_ctx *c, apr_state *s, int8_t *bin, const apr_sink *sinks, int nsinks,
+              double dt_max, double c_cfl, int max_bin);
+int step_bins(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, int nzones,
+              const apr_sink *sinks, int nsinks, double dt_max, double c_cfl, int max_bin,
+              int64_t step, int32_t *nsub);
 
 // relax.hip
 int relax(apr_ctx *c, apr_state *s, apr_ctx *rc, const apr_state *ref, const void *ref_rho,
@@ -264,12 +284,20 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
 int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt);  // kick by dtk, then drift
 // kick_dt != 0: also v += kick_dt a (and u) with the new accelerations
 int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
-                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt = 0.0);
+                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt = 0.0,
+               const uint8_t *active = nullptr, const int8_t *bin = nullptr,
+               double dt_max = 0.0);
 int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, double *dt);
 
 // splitmerge.hip
+// Individual timesteps: active (optional, [n]) restricts the pass to those
+// particles; origin (optional, room for capacity) receives each slot's slot
+// before the pass (an appended child: its parent's); made (optional, room for
+// capacity) flags what a split made or a merge kept.
 int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
-                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare);
+                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare,
+                const uint8_t *active = nullptr, int64_t *origin = nullptr,
+                uint8_t *made = nullptr);
 
 // kernel timing: prof_begin returns a token for prof_end (-1 when disabled)
 int prof_begin(apr_ctx *c, int idx);

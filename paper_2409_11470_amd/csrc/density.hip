@@ -65,6 +65,7 @@ struct DensArgs {
     double hlim;          // periodic boxes: h must stay below this (0: no limit)
     int max_iter;
     int32_t *status;
+    const uint8_t *active;  // targets to solve (null: all); the others keep h, rho, Omega
 };
 
 // Per-lane partial sums of one Newton evaluation (kernel K).
@@ -168,7 +169,9 @@ __device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
     }
 }
 
-template <class T, int K>
+// ACT: only the targets a.active flags are solved (individual timesteps); a
+// separate instantiation, so that the full pass carries none of it.
+template <class T, int K, bool ACT>
 __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t cell)
 {
     using V = vec4_t<T>;
@@ -197,7 +200,20 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     const int cnt = tr.cs[cell + 1] - s0;
     const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
     const int t = 16 * w + (lane >> 2);   // this lane's target (4 lanes each)
-    const bool valid = t < cnt;
+    const bool mine = t < cnt;
+    const bool valid = mine && (!ACT || a.active[s0 + t] != 0);
+    if (ACT && !__syncthreads_or(valid)) {
+        // nothing to solve here: the cell's h_max from the stored h
+        double m = wave_max64(mine ? a.h[s0 + t] : 0.0);
+        if (lane_id() == 0) s_red[threadIdx.x / kWave] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double hm = 0.0;
+            for (int k = 0; k < kWaves; ++k) hm = fmax(hm, s_red[k]);
+            a.hmax_new[cell] = f_up(hm);
+        }
+        return;
+    }
 
     double h = valid ? a.h[s0 + t] : 0.0;
     float Rt = 0.0f;  // reach of this target's list (2 sigma h, a 10% margin)
@@ -471,7 +487,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     }
     // ---- new h_max of the cell for the force search
     {
-        double m = wave_max64(valid ? h : 0.0);
+        double m = wave_max64(valid ? h : (ACT && t < cnt ? a.h[s0 + t] : 0.0));
         __syncthreads();
         if (lane == 0) s_red[w] = m;
         __syncthreads();
@@ -487,30 +503,37 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
 // host's estimate of the cell count; a second launch (REST) strides over any
 // cells from `first` on, nearly always none.  Two kernels rather than one
 // loop: a loop around the search body costs it registers.
-template <class T, int K, bool REST>
+template <class T, int K, bool REST, bool ACT>
 __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_density(DensArgs<T> a,
                                                                               int64_t first)
 {
     const int64_t nc = a.tree.hdr->ncells;
     if (!REST) {
         const int64_t cell = first_cell(blockIdx.x, gridDim.x, nc);
-        if (cell >= 0) density_cell<T, K>(a, cell);
+        if (cell >= 0) density_cell<T, K, ACT>(a, cell);
         return;
     }
     for (int64_t cell = first + blockIdx.x; cell < nc; cell += gridDim.x) {
-        density_cell<T, K>(a, cell);
+        density_cell<T, K, ACT>(a, cell);
         __syncthreads();  // the next cell reuses the LDS
     }
+}
+
+template <class T, int K, bool ACT>
+void launch_density_a(apr_ctx *c, const DensArgs<T> &a, int64_t grid, int tok)
+{
+    hipLaunchKernelGGL((k_density<T, K, false, ACT>), dim3((unsigned)grid), dim3(kSearchThreads),
+                       0, c->stream, a, (int64_t)0);
+    prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
+    hipLaunchKernelGGL((k_density<T, K, true, ACT>), dim3(kRestGrid), dim3(kSearchThreads), 0,
+                       c->stream, a, grid);
 }
 
 template <class T, int K>
 void launch_density_k(apr_ctx *c, const DensArgs<T> &a, int64_t grid, int tok)
 {
-    hipLaunchKernelGGL((k_density<T, K, false>), dim3((unsigned)grid), dim3(kSearchThreads), 0,
-                       c->stream, a, (int64_t)0);
-    prof_end(c, tok);  // the timed pass: the REST launch is nearly always empty
-    hipLaunchKernelGGL((k_density<T, K, true>), dim3(kRestGrid), dim3(kSearchThreads), 0,
-                       c->stream, a, grid);
+    if (a.active) launch_density_a<T, K, true>(c, a, grid, tok);
+    else launch_density_a<T, K, false>(c, a, grid, tok);
 }
 
 template <class T>
@@ -533,7 +556,8 @@ Tree make_tree(apr_ctx *c)
     return t;
 }
 
-int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters)
+int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, int32_t *iters,
+            const uint8_t *active)
 {
     if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "apr_build_cells first");
     if (!rho || !omega) return fail(c, APR_ERR_INVALID, "rho and omega are required");
@@ -569,6 +593,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
+        a.active = active;
         launch_density(c, a, grid, tok);
     } else {
         DensArgs<double> a;
@@ -588,6 +613,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
+        a.active = active;
         launch_density(c, a, grid, tok);
     }
     APR_LAUNCHED(c);

@@ -83,6 +83,7 @@ struct ForceOp {
     const V *pm, *vh, *th;
     T *ax, *ay, *az, *dudt, *vsig;
     float *divv;
+    const uint8_t *act = nullptr;
     double m0;
     T alpha, beta;
     __device__ V load(int k, int64_t i) const { return k == 0 ? pm[i] : (k == 1 ? vh[i] : th[i]); }
@@ -162,7 +163,8 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree
 
 template <class T, int K>
 void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
-                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv)
+                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv,
+                   const uint8_t *active)
 {
     using V = vec4_t<T>;
     const bool f32 = std::is_same<T, float>::value;
@@ -176,6 +178,7 @@ void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, i
     op.dudt = (T *)dudt;
     op.vsig = (T *)vsig;
     op.divv = divv;
+    op.act = active;
     op.m0 = c->p.m0;
     op.alpha = (T)c->p.av_alpha;
     op.beta = (T)c->p.av_beta;
@@ -188,12 +191,13 @@ void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, i
 
 template <class T>
 void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
-                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv)
+                   int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv,
+                   const uint8_t *active)
 {
     if (c->p.kernel == APR_KERNEL_WC2)
-        launch_forces<T, kWC2>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+        launch_forces<T, kWC2>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
     else
-        launch_forces<T, kM4>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+        launch_forces<T, kM4>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
 }
 
 }  // namespace
@@ -222,7 +226,7 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 }
 
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh)
+           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh, const uint8_t *active)
 {
     if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "apr_build_cells first");
     if (!rho || !omega || !ax || !ay || !az || !dudt)
@@ -244,9 +248,9 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     if (rc) return rc;
     int tok = prof_begin(c, APR_PROF_FORCES);
     if (p.precision == APR_FP32)
-        launch_forces<float>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+        launch_forces<float>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
     else
-        launch_forces<double>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv);
+        launch_forces<double>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
     APR_LAUNCHED(c);
     c->force_n = n;
     c->divv_n = n;

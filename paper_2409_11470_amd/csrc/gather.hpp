@@ -17,6 +17,7 @@
 //   struct Acc;                         per-lane partial sums of one target
 //   void init(Acc &, const V *own) const;
 //   void pair(Acc &, const V *own, T dx, T dy, T dz, T r2, const V *nb) const;
+//   const uint8_t *act;                 targets to sum for (null: all)
 //   void finish(Acc &, int64_t i, const V *own, bool write) const;
 //     finish reduces over the target's 4 lanes (all lanes call it) and, if
 //     write, stores the target's results.
@@ -46,7 +47,10 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     const int cnt = tr.cs[cell + 1] - s0;
     const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
     const int t = 16 * w + (lane >> 2);  // this lane's target (4 lanes each)
-    const bool valid = t < cnt;
+    // op.act (optional): only those targets get their sums; a cell without
+    // one is left at once
+    const bool valid = t < cnt && (!op.act || op.act[s0 + t] != 0);
+    if (op.act && !__syncthreads_or(valid)) return;
     uint16_t *mylist = tls[t < kCell ? t : 0];
     const double R = 2.0 * (double)tg.hmax;  // targets' own supports
 

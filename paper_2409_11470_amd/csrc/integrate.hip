@@ -54,15 +54,20 @@ struct Sinks {
 };
 
 // With vx non-null it also applies the step's closing half-kick with the new
-// accelerations, v += kdt a, u += kdt du/dt.
+// accelerations, v += kdt a, u += kdt du/dt.  Individual timesteps: only the
+// particles act flags (if given) are touched, and with bin given the
+// half-kick is each particle's own, kdt = dt_max 2^-bin / 2.
 template <class T>
 __global__ void k_total_accel(int64_t n, const double *x, const double *y, const double *z,
                               const T *hax, const T *hay, const T *haz, const T *hdu, Sinks S,
                               double *ax, double *ay, double *az, double *dudt, double kdt,
-                              double *vx, double *vy, double *vz, double *u)
+                              double *vx, double *vy, double *vz, double *u, const uint8_t *act,
+                              const int8_t *bin, double dt_max)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (act && !act[i]) return;
+    if (bin) kdt = 0.5 * ldexp(dt_max, -(int)bin[i]);
     double gx = (double)hax[i], gy = (double)hay[i], gz = (double)haz[i];
     for (int s = 0; s < S.n; ++s) {
         double dx = x[i] - S.x[s][0], dy = y[i] - S.x[s][1], dz = z[i] - S.x[s][2];
@@ -140,7 +145,8 @@ int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt)
 }
 
 int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
-                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt)
+                const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt,
+                const uint8_t *active, const int8_t *bin, double dt_max)
 {
     if (nsinks < 0 || nsinks > kMaxSinks) return fail(c, APR_ERR_INVALID, "too many sinks");
     if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
@@ -155,19 +161,19 @@ int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const 
     }
     int64_t n = s->n;
     unsigned g = (unsigned)ceil_div(n, 256);
-    const bool k = kick_dt != 0.0;
+    const bool k = kick_dt != 0.0 || bin;
     double *u = k && c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
     double *vx = k ? s->vx : nullptr, *vy = k ? s->vy : nullptr, *vz = k ? s->vz : nullptr;
     if (c->p.precision == APR_FP32)
         hipLaunchKernelGGL(k_total_accel<float>, dim3(g), dim3(256), 0, c->stream, n, s->x, s->y,
                            s->z, (const float *)ax, (const float *)ay, (const float *)az,
                            (const float *)dudt, S, s->ax, s->ay, s->az, s->dudt, kick_dt, vx, vy,
-                           vz, u);
+                           vz, u, active, bin, dt_max);
     else
         hipLaunchKernelGGL(k_total_accel<double>, dim3(g), dim3(256), 0, c->stream, n, s->x,
                            s->y, s->z, (const double *)ax, (const double *)ay,
                            (const double *)az, (const double *)dudt, S, s->ax, s->ay, s->az,
-                           s->dudt, kick_dt, vx, vy, vz, u);
+                           s->dudt, kick_dt, vx, vy, vz, u, active, bin, dt_max);
     APR_LAUNCHED(c);
     return APR_OK;
 }

@@ -2,7 +2,9 @@
 // order: split from the lowest level up, merge from the highest level down, a
 // particle changes level at most once per pass).
 //
-// Split: a per-particle zone test and one scan place the new children; the
+// Split: a per-particle zone test and one scan place the new children, which
+// are numbered in the order of their parents' ids (a radix sort of the
+// splitting parents), so the result does not depend on the array order; the
 // child axis, offset and the exact-centre-of-mass coordinate pair are
 // computed in FP64 with no contraction, so positions match a plain FP64
 // evaluation except for the last-place differences of sin/cos.
@@ -165,13 +167,14 @@ struct SArr {
     int64_t *id;
 };
 
-__global__ void k_split_flags(int64_t n, SArr s, Zones Z, uint32_t *flag, int8_t *zone_of)
+__global__ void k_split_flags(int64_t n, SArr s, Zones Z, const uint8_t *active, uint32_t *flag,
+                              int8_t *zone_of)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int w;
     int lz = zone_level(Z, s.x[i], s.y[i], s.z[i], &w);
-    flag[i] = s.level[i] < lz ? 1u : 0u;
+    flag[i] = (s.level[i] < lz && (!active || active[i])) ? 1u : 0u;
     zone_of[i] = (int8_t)w;
 }
 
@@ -179,7 +182,8 @@ template <class D>
 __global__ void k_split_apply(int64_t n, SArr s, Zones Z, Box b, const uint32_t *flag,
                               const uint32_t *rank, const int8_t *zone_of, const D *dnn,
                               double r_sep_factor, double nn_cap, int mode, uint64_t seed,
-                              int64_t step, int64_t next_id, uint8_t *changed)
+                              int64_t step, int64_t next_id, const uint32_t *idrank,
+                              uint8_t *changed, int64_t *origin)
 {
 #pragma clang fp contract(off)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,9 +220,16 @@ __global__ void k_split_apply(int64_t n, SArr s, Zones Z, Box b, const uint32_t 
     int8_t lv = (int8_t)(s.level[i] + 1);
     s.level[i] = lv;
     s.level[slot] = lv;
-    s.id[slot] = next_id + (int64_t)rank[i];
+    s.id[slot] = next_id + (int64_t)idrank[i];
     changed[i] = 1;
     changed[slot] = 1;
+    if (origin) origin[slot] = i;
+}
+
+__global__ void k_iota64(int64_t *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
 }
 
 __global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
@@ -260,12 +271,17 @@ __global__ __launch_bounds__(256) void k_max_level(int64_t n, const int8_t *leve
     }
 }
 
+// merge candidates of level l: not changed in this pass, not removed, and
+// (individual timesteps) active; slots >= n0 are this pass's children
 __global__ void k_cand_flags(int64_t n, const int8_t *level, const uint8_t *changed,
-                             const uint8_t *removed, int l, uint32_t *flag)
+                             const uint8_t *removed, int l, const uint8_t *active, int64_t n0,
+                             uint32_t *flag)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    flag[i] = (level[i] == l && !changed[i] && !removed[i]) ? 1u : 0u;
+    flag[i] = (level[i] == l && !changed[i] && !removed[i] && (!active || i >= n0 || active[i]))
+                  ? 1u
+                  : 0u;
 }
 
 __global__ void k_compact_idx(int64_t n, const uint32_t *flag, const uint32_t *pos,
@@ -282,6 +298,13 @@ __global__ void k_id_keys(int64_t m, const uint32_t *slot, const int64_t *id, in
     if (i >= m) return;
     uint64_t v = (uint64_t)id[slot[i]];
     key[i] = high ? (uint32_t)(v >> 32) : (uint32_t)v;
+}
+
+// idrank[slot[r]] = r: each listed slot's place in the sorted list
+__global__ void k_rank_of(int64_t m, const uint32_t *slot, uint32_t *idrank)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m) idrank[slot[r]] = (uint32_t)r;
 }
 
 __device__ inline int32_t quantise(double v, double lo, double s)
@@ -628,6 +651,8 @@ struct CompactArgs {
     int nd;
     int8_t *lev, *levt;
     int64_t *id, *idt;
+    int64_t *org, *orgt;   // optional: slots before the pass
+    uint8_t *chg, *chgt;   // the pass's changed flags (kept for the caller)
     const uint32_t *keep, *pos;
     int64_t n;
 };
@@ -640,6 +665,8 @@ __global__ void k_compact_gather(CompactArgs a)
     for (int k = 0; k < a.nd; ++k) a.dt[k][j] = a.d[k][i];
     a.levt[j] = a.lev[i];
     a.idt[j] = a.id[i];
+    if (a.org) a.orgt[j] = a.org[i];
+    a.chgt[j] = a.chg[i];
 }
 
 __global__ void k_compact_back(CompactArgs a, int64_t m)
@@ -649,14 +676,38 @@ __global__ void k_compact_back(CompactArgs a, int64_t m)
     for (int k = 0; k < a.nd; ++k) a.d[k][i] = a.dt[k][i];
     a.lev[i] = a.levt[i];
     a.id[i] = a.idt[i];
+    if (a.org) a.org[i] = a.orgt[i];
+    a.chg[i] = a.chgt[i];
 }
 
 unsigned grid(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 256); }
 
+// slot[0..m) into ascending id order: a stable LSD radix sort on the low 32
+// bits of the id, then on the high 32 when ids reach that far.  Every id is
+// below next_id, so the low-word sort needs only next_id's bit length.
+int sort_slots_by_id(apr_ctx *c, uint32_t *slot, uint32_t *keys, int64_t m, const int64_t *id,
+                     int64_t next_id)
+{
+    const bool high_ids = next_id > (int64_t)0xffffffffLL;
+    int id_bits = 32;
+    if (!high_ids) {
+        id_bits = 1;
+        while (id_bits < 32 && (((int64_t)1 << id_bits) < next_id)) ++id_bits;
+    }
+    hipLaunchKernelGGL(k_id_keys, dim3(grid(m)), dim3(256), 0, c->stream, m, slot, id, 0, keys);
+    APR_LAUNCHED(c);
+    int rc = radix_sort_u32(c, keys, slot, m, id_bits);
+    if (rc || !high_ids) return rc;
+    hipLaunchKernelGGL(k_id_keys, dim3(grid(m)), dim3(256), 0, c->stream, m, slot, id, 1, keys);
+    APR_LAUNCHED(c);
+    return radix_sort_u32(c, keys, slot, m, 32);
+}
+
 }  // namespace
 
 int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
-                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare)
+                int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare,
+                const uint8_t *active, int64_t *origin, uint8_t *made)
 {
     const apr_params &P = c->p;
     if (nzones > kMaxZones) return fail(c, APR_ERR_INVALID, "at most 8 zones");
@@ -703,12 +754,15 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                        cap);
     hipLaunchKernelGGL(k_fill_u8, dim3(grid(cap)), dim3(256), 0, c->stream, removed, (uint8_t)0,
                        cap);
+    if (origin)
+        hipLaunchKernelGGL(k_iota64, dim3(grid(n)), dim3(256), 0, c->stream, origin, n);
     APR_LAUNCHED(c);
+    const int64_t n0 = n;
     uint32_t h32 = 0;
 
     if (do_split) {
-        hipLaunchKernelGGL(k_split_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, A, Z, flag,
-                           zone_of);
+        hipLaunchKernelGGL(k_split_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, A, Z, active,
+                           flag, zone_of);
         APR_LAUNCHED(c);
         int rc = exclusive_scan_u32(c, flag, scan, n, tot);
         if (rc) return rc;
@@ -727,6 +781,19 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                 return fail(c, APR_ERR_INVALID,
                             "nn_cap > 0 needs apr_density on the current state first");
             }
+            // the children are numbered in the order of their parents' ids
+            uint32_t *pslot = wsa<uint32_t>(c, "sm_cand", (size_t)n);
+            uint32_t *pkey = wsa<uint32_t>(c, "sm_keys", (size_t)n);
+            uint32_t *idrank = wsa<uint32_t>(c, "sm_idrank", (size_t)n);
+            if (!pslot || !pkey || !idrank) return fail(c, APR_ERR_HIP, "split workspace");
+            hipLaunchKernelGGL(k_compact_idx, dim3(grid(n)), dim3(256), 0, c->stream, n, flag,
+                               scan, pslot);
+            APR_LAUNCHED(c);
+            rc = sort_slots_by_id(c, pslot, pkey, ns, s->id, s->next_id);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_rank_of, dim3(grid(ns)), dim3(256), 0, c->stream, ns, pslot,
+                               idrank);
+            APR_LAUNCHED(c);
             // the nearest-neighbour distances of the n parents, as the last
             // density pass wrote them: asked for by n, not by the capacity, so
             // that a capacity grown since then cannot reallocate (and lose) them
@@ -734,12 +801,14 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                 const float *dnn = cap_nn ? wsa<float>(c, "dnn32", (size_t)n) : nullptr;
                 hipLaunchKernelGGL(k_split_apply<float>, dim3(grid(n)), dim3(256), 0, c->stream,
                                    n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
-                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);
+                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, idrank,
+                                   changed, origin);
             } else {
                 const double *dnn = cap_nn ? wsa<double>(c, "dnn64", (size_t)n) : nullptr;
                 hipLaunchKernelGGL(k_split_apply<double>, dim3(grid(n)), dim3(256), 0, c->stream,
                                    n, A, Z, b, flag, scan, zone_of, dnn, P.r_sep_factor,
-                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, changed);
+                                   P.nn_cap, P.split_mode, P.seed, step, s->next_id, idrank,
+                                   changed, origin);
             }
             APR_LAUNCHED(c);
             n += ns;
@@ -772,16 +841,9 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             return fail(c, APR_ERR_HIP, "merge workspace");
         double sc[3];
         for (int k = 0; k < 3; ++k) sc[k] = kQuant / b.L[k];
-        bool high_ids = s->next_id > (int64_t)0xffffffffLL;
-        // every id is below next_id: the low-word sort needs only its bit length
-        int id_bits = 32;
-        if (!high_ids) {
-            id_bits = 1;
-            while (id_bits < 32 && (((int64_t)1 << id_bits) < s->next_id)) ++id_bits;
-        }
         for (int l = lmax; l >= 1; --l) {
             hipLaunchKernelGGL(k_cand_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
-                               changed, removed, l, flag);
+                               changed, removed, l, active, n0, flag);
             APR_LAUNCHED(c);
             int rc = exclusive_scan_u32(c, flag, scan, n, tot);
             if (rc) return rc;
@@ -793,19 +855,8 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             if (m < 2) continue;
             hipLaunchKernelGGL(k_compact_idx, dim3(grid(n)), dim3(256), 0, c->stream, n, flag,
                                scan, cand);
-            // ascending id (stable LSD: low 32 bits, then high)
-            hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
-                               s->id, 0, keys);
-            APR_LAUNCHED(c);
-            rc = radix_sort_u32(c, keys, cand, nc, id_bits);
+            rc = sort_slots_by_id(c, cand, keys, nc, s->id, s->next_id);
             if (rc) return rc;
-            if (high_ids) {
-                hipLaunchKernelGGL(k_id_keys, dim3(grid(nc)), dim3(256), 0, c->stream, nc, cand,
-                                   s->id, 1, keys);
-                APR_LAUNCHED(c);
-                rc = radix_sort_u32(c, keys, cand, nc, 32);
-                if (rc) return rc;
-            }
             // the highest id (last) sits out when nc is odd; tree over the first m
             hipLaunchKernelGGL(k_quant, dim3(grid(m)), dim3(256), 0, c->stream, m, cand, A, b,
                                sc[0], sc[1], sc[2], q[0], q[1], q[2]);
@@ -890,6 +941,12 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             ca.levt = wsa<int8_t>(c, "pt_lev", (size_t)n);
             ca.id = s->id;
             ca.idt = wsa<int64_t>(c, "pt_id", (size_t)n);
+            ca.org = origin;
+            ca.orgt = origin ? wsa<int64_t>(c, "pt_org", (size_t)n) : nullptr;
+            ca.chg = changed;
+            ca.chgt = wsa<uint8_t>(c, "pt_chg", (size_t)n);
+            if (!ca.levt || !ca.idt || !ca.chgt || (origin && !ca.orgt))
+                return fail(c, APR_ERR_HIP, "compaction workspace");
             ca.keep = flag;
             ca.pos = scan;
             ca.n = n;
@@ -901,9 +958,12 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             s->n = n;
         }
     }
+    if (made && n > 0)
+        APR_HIP(c, hipMemcpyAsync(made, changed, (size_t)n, hipMemcpyDeviceToDevice, c->stream));
     prof_end(c, tok);
     APR_HIP(c, hipStreamSynchronize(c->stream));
     if (*n_split + *n_merged > 0) {  // the particle set changed: cells are stale
+        if (!c->in_bins) c->bins_n = -1;
         c->cells_n = -1;
         c->divv_n = -1;
         c->divv_prev_n = -1;
