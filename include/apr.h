@@ -218,7 +218,10 @@ int apr_vjp(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega
  * substeps (APR_ERR_CAPACITY leaves the step half done).  Any other call that
  * reorders the state (apr_build_cells, apr_step, apr_split_merge, apr_relax)
  * voids the stored values: apr_step_bins then returns APR_ERR_INVALID until
- * apr_bins_init runs again.  Synchronises once per substep with zones. */
+ * apr_bins_init runs again.  Synchronises once per substep with zones.
+ * Errors (APR_ERR_INVALID, nothing changed): an empty state, a missing bin
+ * array, dt_max or c_cfl not > 0, max_bin outside 0..20, a negative bin or
+ * one above max_bin in bin. */
 int apr_bins_init(apr_ctx *ctx, apr_state *s, int8_t *bin, const apr_sink *sinks,
                   int32_t nsinks, double dt_max, double c_cfl, int32_t max_bin);
 int apr_step_bins(apr_ctx *ctx, apr_state *s, int8_t *bin, const apr_zone *zones,

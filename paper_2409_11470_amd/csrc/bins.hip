@@ -43,10 +43,12 @@ __global__ void k_bins_init(int64_t n, const double *h, const T *vs, double dt_m
     if (i < n) bin[i] = (int8_t)courant_k<T>(h[i], vs[i], dt_max, c_cfl, kmax);
 }
 
+// out[0]: the largest bin; out[1]: 1 if any bin is negative
 __global__ void k_max_bin(int64_t n, const int8_t *bin, int32_t *out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int v = i < n ? bin[i] : 0;
+    if (v < 0) atomicOr(out + 1, 1);
     for (int o = kWave / 2; o > 0; o >>= 1) {
         const int t = __shfl_xor(v, o, kWave);
         v = v > t ? v : t;
@@ -206,10 +208,27 @@ int bins_init_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_sink *sinks, in
     return APR_OK;
 }
 
+// *K = the largest bin; every bin must lie in 0..max_bin
+int bin_range(apr_ctx *c, const apr_state *s, const int8_t *bin, int max_bin, int32_t *K)
+{
+    int32_t *kmax_dev = wsa<int32_t>(c, "bn_kmax", 2);
+    if (!kmax_dev) return fail(c, APR_ERR_HIP, "timestep-bin workspace");
+    int32_t kb[2] = {0, 0};
+    APR_HIP(c, hipMemsetAsync(kmax_dev, 0, 8, c->stream));
+    hipLaunchKernelGGL(k_max_bin, dim3(g256(s->n)), dim3(256), 0, c->stream, s->n, bin, kmax_dev);
+    APR_LAUNCHED(c);
+    APR_HIP(c, hipMemcpyAsync(kb, kmax_dev, 8, hipMemcpyDeviceToHost, c->stream));
+    APR_HIP(c, hipStreamSynchronize(c->stream));
+    if (kb[1]) return fail(c, APR_ERR_INVALID, "a negative bin");
+    if (kb[0] > max_bin) return fail(c, APR_ERR_INVALID, "a bin above max_bin");
+    *K = kb[0];
+    return APR_OK;
+}
+
 template <class T>
 int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, int nzones,
                 const apr_sink *sinks, int nsinks, double dt_max, double c_cfl, int max_bin,
-                int64_t step, int32_t *nsub_out)
+                int32_t K, int64_t step, int32_t *nsub_out)
 {
     const int64_t cap = s->capacity;
     Stored<T> b;
@@ -218,16 +237,7 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
     uint8_t *act = wsa<uint8_t>(c, "bn_act", (size_t)cap);
     uint8_t *made = wsa<uint8_t>(c, "bn_made", (size_t)cap);
     int64_t *idx = wsa<int64_t>(c, "bn_idx", (size_t)cap);
-    int32_t *kmax_dev = wsa<int32_t>(c, "bn_kmax", 1);
-    if (!act || !made || !idx || !kmax_dev) return fail(c, APR_ERR_HIP, "timestep-bin workspace");
-    // K: the largest bin now
-    int32_t K = 0;
-    APR_HIP(c, hipMemsetAsync(kmax_dev, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_max_bin, dim3(g256(s->n)), dim3(256), 0, c->stream, s->n, bin, kmax_dev);
-    APR_LAUNCHED(c);
-    APR_HIP(c, hipMemcpyAsync(&K, kmax_dev, 4, hipMemcpyDeviceToHost, c->stream));
-    APR_HIP(c, hipStreamSynchronize(c->stream));
-    if (K < 0 || K > max_bin) return fail(c, APR_ERR_INVALID, "a bin above max_bin");
+    if (!act || !made || !idx) return fail(c, APR_ERR_HIP, "timestep-bin workspace");
     const int64_t nsub = (int64_t)1 << K;
     const double delta = ldexp(dt_max, -K);
     const Box box = make_box(c->p);
@@ -305,14 +315,16 @@ int step_bins(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, int 
 {
     if (c->bins_n != s->n)
         return fail(c, APR_ERR_INVALID, "apr_bins_init first (or the state was reordered since)");
-    int rc;
+    int32_t K = 0;
+    int rc = bin_range(c, s, bin, max_bin, &K);   // changes nothing on failure
+    if (rc) return rc;
     {
         InBins guard(c);
         rc = c->p.precision == APR_FP32
                  ? step_bins_t<float>(c, s, bin, zones, nzones, sinks, nsinks, dt_max, c_cfl,
-                                      max_bin, step, nsub)
+                                      max_bin, K, step, nsub)
                  : step_bins_t<double>(c, s, bin, zones, nzones, sinks, nsinks, dt_max, c_cfl,
-                                       max_bin, step, nsub);
+                                       max_bin, K, step, nsub);
     }
     c->bins_n = rc ? -1 : s->n;
     return rc;

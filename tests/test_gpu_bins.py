@@ -21,10 +21,10 @@ SPLIT = dict(r_sep_factor=0.5, nn_cap=0.0, split_mode=1)
 
 
 def _phys(p):
-    return dict(m0=p["m0"], eos=p["eos"], cs0=p["cs0"], q_cs=p.get("q_cs", 0.25),
-                r_ref=p.get("r_ref", 1.0), gamma=p["gamma"], alpha=p["alpha"], beta=p["beta"],
-                hfact=p["hfact"], sinks=p["sinks"], periodic=p["periodic"], lo=p["lo"],
-                hi=p["hi"])
+    return dict(m0=p["m0"], eos=p["eos"], cs0=p.get("cs0", 1.0), q_cs=p.get("q_cs", 0.25),
+                r_ref=p.get("r_ref", 1.0), gamma=p.get("gamma", 5.0 / 3.0),
+                alpha=p.get("alpha", 1.0), beta=p.get("beta", 2.0), hfact=p.get("hfact", 1.2),
+                sinks=p.get("sinks", []), periodic=p["periodic"], lo=p["lo"], hi=p["hi"])
 
 
 def _by_id(g):
@@ -61,6 +61,83 @@ def test_disc_steps_match_oracle():
     for k in ("x", "y", "z", "vx", "vy", "vz", "h", "u"):
         sc = max(np.max(np.abs(o[k])), 1e-30)
         assert np.max(np.abs(g[k] - o[k])) / sc < 1e-9, k
+
+
+def _compare(g, o):
+    g, o = _by_id(g), _by_id(o)
+    assert np.array_equal(g["id"], o["id"])
+    for k in ("level", "bin"):
+        assert np.array_equal(g[k], o[k]), k
+    L = np.asarray(o["hi"], float) - np.asarray(o["lo"], float) if "hi" in o else None
+    for k in ("x", "y", "z", "vx", "vy", "vz", "h", "u"):
+        d = g[k] - o[k]
+        if L is not None and k in ("x", "y", "z"):
+            w = L["xyz".index(k)]
+            d -= w * np.round(d / w)          # periodic images
+        sc = max(np.max(np.abs(o[k])), 1e-30)
+        assert np.max(np.abs(d)) / sc < 1e-9, k
+
+
+def test_wave_box_periodic_adiabatic():
+    """The sound-wave box (periodic, adiabatic, cylinder zone), dt_max about
+    twice the median Courant step: bins 1 and 2 (4 substeps), the u kicks and
+    the periodic drift of the substeps, splits of active particles in the
+    zone.  Two steps, per id against the oracle."""
+    st, p = W.wave_box(nx=16)
+    phys = _phys(p)
+    o = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    oracle.accel_bins(o, **phys)
+    dtc = 0.3 * o["h"] / o["vsig"]
+    dtm = 2.0 * float(np.median(dtc)) * 1.000123
+    o["bin"] = oracle.courant_bin(o["h"], o["vsig"], dt_max=dtm, c_cfl=0.3, max_bin=MAXB)
+    b0 = np.bincount(o["bin"])
+    assert b0.size == 3 and b0[1] > 100 and b0[2] > 100
+    for step in range(2):
+        o = oracle.step_bins(o, zones=p["zones"], dt_max=dtm, step=step, max_bin=MAXB, seed=3,
+                             **SPLIT, **phys)
+    ctx = A.Context(params_for(p, "fp64", seed=3, **SPLIT))
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_bins_init(ctx, ds, dtm, 0.3, MAXB)
+    assert np.array_equal(np.bincount(ds["bin"].cpu().numpy()), b0)
+    for step in range(2):
+        k = int(ds["bin"].max())        # a step's end may refine past it
+        assert A.apr_step_bins(ctx, ds, p["zones"], [], dtm, step, 0.3, MAXB) == 1 << k
+        assert step > 0 or k == 2
+    A.apr_sync_status(ctx)
+    g = ds.to_numpy()
+    assert int((g["id"] >= st["x"].shape[0]).sum()) > 10
+    o["lo"], o["hi"] = p["lo"], p["hi"]
+    _compare(g, o)
+
+
+def test_argument_errors():
+    st, p = W.planet_disc(n=2000)
+    ctx = A.Context(params_for(p, "fp64", seed=3, **SPLIT))
+    empty = A.DeviceState(8)
+    bad = [lambda: A.apr_bins_init(ctx, empty, DT, 0.3, MAXB),
+           lambda: A.apr_step_bins(ctx, empty, [], [], DT, 0, 0.3, MAXB)]
+    ds = A.DeviceState.from_numpy(st)
+    bad += [lambda: A.apr_bins_init(ctx, ds, 0.0, 0.3, MAXB),
+            lambda: A.apr_bins_init(ctx, ds, DT, -1.0, MAXB),
+            lambda: A.apr_bins_init(ctx, ds, DT, 0.3, 21)]
+    for call in bad:
+        with pytest.raises(A.AprError) as e:
+            call()
+        assert e.value.code == A.APR_ERR_INVALID
+    A.apr_bins_init(ctx, ds, DT, 0.3, MAXB, p["sinks"])
+    kmax = int(ds["bin"].max())
+    assert kmax >= 2
+    # a bin above the max_bin of the call, then a negative bin: rejected
+    with pytest.raises(A.AprError) as e:
+        A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 0, 0.3, kmax - 1)
+    assert e.value.code == A.APR_ERR_INVALID
+    saved = ds["bin"][0].item()
+    ds["bin"][0] = -1
+    with pytest.raises(A.AprError) as e:
+        A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 0, 0.3, MAXB)
+    assert e.value.code == A.APR_ERR_INVALID
+    ds["bin"][0] = saved
+    assert A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 0, 0.3, MAXB) == 1 << kmax
 
 
 def test_reorder_voids_the_stored_values():
