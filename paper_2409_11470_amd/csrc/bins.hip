@@ -99,13 +99,6 @@ __global__ void k_act(int64_t n, const int8_t *bin, int K, int64_t s, uint8_t *a
     made[i] = 0;
 }
 
-template <class A>
-__global__ void k_take(int64_t n, const int64_t *idx, const A *src, A *dst)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[idx[i]];
-}
-
 __global__ void k_or_made(int64_t n, uint8_t *act, const uint8_t *made)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,18 +123,6 @@ __global__ void k_rebin(int64_t n, const uint8_t *act, const uint8_t *made, int8
     if (!last)
         while ((s + 1) % ((int64_t)1 << (K - k))) ++k;
     bin[i] = (int8_t)k;
-}
-
-// arr[0..n) <- arr[idx[0..n)] through a workspace copy
-template <class A>
-int remap(apr_ctx *c, A *arr, const int64_t *idx, int64_t n, const char *tmp)
-{
-    A *t = wsa<A>(c, tmp, (size_t)n);
-    if (!t) return fail(c, APR_ERR_HIP, "timestep-bin workspace");
-    hipLaunchKernelGGL(k_take<A>, dim3(g256(n)), dim3(256), 0, c->stream, n, idx, arr, t);
-    APR_LAUNCHED(c);
-    APR_HIP(c, hipMemcpyAsync(arr, t, (size_t)n * sizeof(A), hipMemcpyDeviceToDevice, c->stream));
-    return APR_OK;
 }
 
 template <class T>
@@ -171,16 +152,65 @@ T *dnn_ws(apr_ctx *c, int64_t n)
     return wsa<T>(c, sizeof(T) == 4 ? "dnn32" : "dnn64", (size_t)n);
 }
 
+// Up to 8 per-particle arrays (elements of 1, 4 or 8 bytes) permuted together:
+// one gather into workspace copies, one copy back.
+struct Remap {
+    char *a[8], *t[8];
+    int es[8];
+    int na;
+};
+
+template <class E>
+__device__ inline void mv(char *dst, int64_t i, const char *src, int64_t j)
+{
+    reinterpret_cast<E *>(dst)[i] = reinterpret_cast<const E *>(src)[j];
+}
+
+__global__ void k_take_all(int64_t n, const int64_t *idx, Remap r)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = idx[i];
+    for (int k = 0; k < r.na; ++k) {
+        if (r.es[k] == 1) mv<uint8_t>(r.t[k], i, r.a[k], j);
+        else if (r.es[k] == 4) mv<uint32_t>(r.t[k], i, r.a[k], j);
+        else mv<uint64_t>(r.t[k], i, r.a[k], j);
+    }
+}
+
+__global__ void k_put_all(int64_t n, Remap r)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < r.na; ++k) {
+        if (r.es[k] == 1) mv<uint8_t>(r.a[k], i, r.t[k], i);
+        else if (r.es[k] == 4) mv<uint32_t>(r.a[k], i, r.t[k], i);
+        else mv<uint64_t>(r.a[k], i, r.t[k], i);
+    }
+}
+
 template <class T>
 int remap_all(apr_ctx *c, int8_t *bin, const Stored<T> &b, uint8_t *act, uint8_t *made,
               const int64_t *idx, int64_t n)
 {
-    int rc = remap<int8_t>(c, bin, idx, n, "bn_t8");
-    if (!rc) rc = remap<uint8_t>(c, act, idx, n, "bn_tu8");
-    if (!rc && made) rc = remap<uint8_t>(c, made, idx, n, "bn_tu8");
+    static const char *nm[8] = {"bn_r0", "bn_r1", "bn_r2", "bn_r3",
+                                "bn_r4", "bn_r5", "bn_r6", "bn_r7"};
+    Remap r;
+    r.na = 0;
+    auto add = [&](void *p, int es) {
+        r.a[r.na] = (char *)p;
+        r.t[r.na] = (char *)ws(c, nm[r.na], (size_t)n * es + 256);
+        r.es[r.na] = es;
+        return r.t[r.na++] != nullptr;
+    };
+    bool ok = add(bin, 1) && add(act, 1) && (!made || add(made, 1));
     T *arr[4] = {b.rho, b.om, b.vs, b.dnn};
-    for (int k = 0; k < 4 && !rc; ++k) rc = remap<T>(c, arr[k], idx, n, "bn_tT");
-    return rc;
+    for (int k = 0; k < 4 && ok; ++k) ok = add(arr[k], (int)sizeof(T));
+    if (!ok) return fail(c, APR_ERR_HIP, "timestep-bin workspace");
+    hipLaunchKernelGGL(k_take_all, dim3(g256(n)), dim3(256), 0, c->stream, n, idx, r);
+    hipLaunchKernelGGL(k_put_all, dim3(g256(n)), dim3(256), 0, c->stream, n, r);
+    APR_LAUNCHED(c);
+    return APR_OK;
 }
 
 template <class T>

@@ -10,9 +10,13 @@ namespace apr {
 
 namespace {
 
+static_assert(kCell <= kWave, "one lane per target of a cell");
+
+// act (optional): a cell none of whose targets is active gets an empty list
+// and no walk (the search kernels leave such a cell before reading it)
 template <bool SYM>
-__global__ __launch_bounds__(kWave) void k_cand_pre(Tree tr, double rfac, int32_t *cand,
-                                                    int32_t *ncand, int64_t cap)
+__global__ __launch_bounds__(kWave) void k_cand_pre(Tree tr, double rfac, const uint8_t *act,
+                                                    int32_t *cand, int32_t *ncand, int64_t cap)
 {
     __shared__ int32_t A[kCandCap];
     __shared__ Walk W;
@@ -20,6 +24,14 @@ __global__ __launch_bounds__(kWave) void k_cand_pre(Tree tr, double rfac, int32_
     const int64_t nc = min((int64_t)tr.hdr->ncells, cap);
     for (int64_t cell = first_cell(blockIdx.x, gridDim.x, nc); cell >= 0 && cell < nc;
          cell += gridDim.x) {
+        if (act) {
+            const int32_t s0 = tr.cs[cell];
+            const int cnt = tr.cs[cell + 1] - s0;  // at most kCell = one lane per target
+            if (!__any(lane < cnt && act[s0 + lane] != 0)) {
+                if (lane == 0) ncand[cell] = 0;
+                continue;
+            }
+        }
         const Geo tg = tr.lev[0][cell];
         const double R = rfac * (double)tg.hmax;
         walk_init(tr, tg, R, SYM, &W);
@@ -33,7 +45,8 @@ __global__ __launch_bounds__(kWave) void k_cand_pre(Tree tr, double rfac, int32_
 
 }  // namespace
 
-int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out)
+int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out,
+             const uint8_t *active)
 {
     // lists for the cells the host expects (the launch grid of the search
     // kernels); any cells beyond walk in the search kernel
@@ -44,10 +57,10 @@ int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out)
     int tok = prof_begin(c, APR_PROF_CAND);
     if (sym)
         hipLaunchKernelGGL(k_cand_pre<true>, dim3((unsigned)grid), dim3(kWave), 0, c->stream, tr,
-                           rfac, cand, ncand, cap);
+                           rfac, active, cand, ncand, cap);
     else
         hipLaunchKernelGGL(k_cand_pre<false>, dim3((unsigned)grid), dim3(kWave), 0, c->stream,
-                           tr, rfac, cand, ncand, cap);
+                           tr, rfac, active, cand, ncand, cap);
     prof_end(c, tok);
     APR_LAUNCHED(c);
     out->cand = cand;

@@ -572,7 +572,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         for (int k = 0; k < 3; ++k) hlim = fmin(hlim, 0.125 * (c->p.box_hi[k] - c->p.box_lo[k]));
     }
     CandList pre;
-    int rc0 = cand_pre(c, tr, false, 2.0 * (double)kSigma, &pre);
+    int rc0 = cand_pre(c, tr, false, 2.0 * (double)kSigma, &pre, active);
     if (rc0) return rc0;
     int tok = prof_begin(c, APR_PROF_DENSITY);
     if (c->p.precision == APR_FP32) {

@@ -244,7 +244,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     float *divv = wsa<float>(c, "divv", (size_t)n);
     if (!divv) return fail(c, APR_ERR_HIP, "workspace");
     CandList pre;
-    rc = cand_pre(c, tr, true, 2.0, &pre);
+    rc = cand_pre(c, tr, true, 2.0, &pre, active);
     if (rc) return rc;
     int tok = prof_begin(c, APR_PROF_FORCES);
     if (p.precision == APR_FP32)

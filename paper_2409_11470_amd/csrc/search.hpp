@@ -173,7 +173,8 @@ struct CandList {
     double rfac = 0.0;
     int64_t cap = 0;
 };
-int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out);
+int cand_pre(apr_ctx *c, const Tree &tr, bool sym, double rfac, CandList *out,
+             const uint8_t *active = nullptr);
 
 // In-place exclusive prefix sum of cnt[0..n) by one wavefront; returns the total.
 __device__ inline int wave_excl_scan_lds(int32_t *cnt, int n)
