@@ -404,15 +404,29 @@ int apr_step(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzones,
     if (!s->ax || !s->ay || !s->az || !s->dudt)
         return fail(c, APR_ERR_INVALID, "state needs ax, ay, az, dudt");
     if (nsinks > 0 && !sinks) return fail(c, APR_ERR_INVALID, "sinks");
-    rc = kick_drift(c, s, 0.5 * dt, dt);  // opening half-kick and drift, one pass
+    if (nzones < 0 || (nzones > 0 && !zones)) return fail(c, APR_ERR_INVALID, "zones");
+    for (int k = 0; k < nzones; ++k)
+        if (zones[k].n < 1 || zones[k].n > 8) return fail(c, APR_ERR_INVALID, "zone spheres");
+    if (nzones > 0 && !s->u) return fail(c, APR_ERR_INVALID, "state needs u");
+    // opening half-kick and drift, one pass; with zones the h prediction waits
+    // for the refinement pass, which splits and merges with the h of the last
+    // density pass
+    double *hfac = nullptr;
+    rc = kick_drift(c, s, 0.5 * dt, dt, nzones > 0 ? &hfac : nullptr);
     if (rc) return rc;
     if (nzones > 0) {
         // the refinement pass opens the step (before this step's density); its
         // nearest-neighbour cap uses the distances of the last density pass,
         // still in the current particle order
         int64_t ns = 0, nm = 0, nsp = 0;
-        rc = apr_split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp);
+        int64_t *origin = hfac ? wsa<int64_t>(c, "step_origin", (size_t)s->capacity) : nullptr;
+        if (hfac && !origin) return fail(c, APR_ERR_HIP, "step workspace");
+        rc = split_merge(c, s, zones, nzones, step, 0, &ns, &nm, &nsp, nullptr, origin, nullptr);
         if (rc) return rc;
+        if (hfac) {
+            rc = hfac_apply(c, s, origin, hfac);
+            if (rc) return rc;
+        }
     }
     rc = build_cells(c, s, nullptr, false);  // accelerations recomputed next
     if (rc) return rc;

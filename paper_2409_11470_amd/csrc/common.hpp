@@ -281,7 +281,10 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
                int64_t *offsets, int64_t *list, int64_t cap, int64_t *total);
 
 // integrate.hip
-int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt);  // kick by dtk, then drift
+// kick by dtk, then drift; with hfac_out the h prediction is stored (a
+// workspace of n factors, or null when there is none) instead of applied
+int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt, double **hfac_out = nullptr);
+int hfac_apply(apr_ctx *c, apr_state *s, const int64_t *origin, const double *hfac);
 // kick_dt != 0: also v += kick_dt a (and u) with the new accelerations
 int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const void *az,
                 const void *dudt, const apr_sink *sinks, int nsinks, double kick_dt = 0.0,

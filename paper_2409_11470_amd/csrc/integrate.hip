@@ -14,11 +14,14 @@ namespace {
 // guess of the next density pass: h *= exp(dt D / 3), the factor kept in
 // [0.8, 1.25].  D = div v, or with the divergence of the force evaluation
 // before (divv_prev) the two-step extrapolation D = div v + w (div v -
-// divv_prev), w = dt / (2 dt_last), which centres it on the new step.
+// divv_prev), w = dt / (2 dt_last), which centres it on the new step.  With
+// hfac the factor is stored there instead, for a split/merge pass to come
+// first (the pass works with the h of the last density pass).
 __global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, double *u, const double *ax, const double *ay,
                              const double *az, const double *dudt, double *h, const float *divv,
-                             const float *divv_prev, double w, double dtk, double dt, Box b)
+                             const float *divv_prev, double w, double dtk, double dt, Box b,
+                             double *hfac)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -30,8 +33,9 @@ __global__ void k_kick_drift(int64_t n, double *x, double *y, double *z, double 
     if (divv) {
         double D = (double)divv[i];
         if (divv_prev) D += w * (D - (double)divv_prev[i]);
-        double f = exp(dt * D / 3.0);
-        h[i] *= fmin(fmax(f, 0.8), 1.25);
+        const double f = fmin(fmax(exp(dt * D / 3.0), 0.8), 1.25);
+        if (hfac) hfac[i] = f;
+        else h[i] *= f;
     }
     double *p[3] = {x, y, z};
 #pragma unroll
@@ -123,9 +127,17 @@ __global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, do
     if (threadIdx.x == 0) *out = s[0];
 }
 
+// h[i] *= hfac[origin[i]]: the deferred prediction after a split/merge pass
+// (children take their parent's factor)
+__global__ void k_hfac_apply(int64_t n, const int64_t *origin, const double *hfac, double *h)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) h[i] *= hfac[origin[i]];
+}
+
 }  // namespace
 
-int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt)
+int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt, double **hfac_out)
 {
     if (!s->ax || !s->ay || !s->az) return fail(c, APR_ERR_INVALID, "state has no acceleration");
     int64_t n = s->n;
@@ -135,12 +147,30 @@ int kick_drift(apr_ctx *c, apr_state *s, double dtk, double dt)
                                  ? wsa<float>(c, "divv_prev", (size_t)n)
                                  : nullptr;
     const double w = divv_prev ? dt / (2.0 * c->dt_last) : 0.0;
+    double *hfac = nullptr;
+    if (hfac_out) {
+        *hfac_out = nullptr;
+        if (divv) {
+            hfac = wsa<double>(c, "hfac", (size_t)n);
+            if (!hfac) return fail(c, APR_ERR_HIP, "workspace");
+            *hfac_out = hfac;
+        }
+    }
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
                        n, s->x, s->y, s->z, s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt,
-                       s->h, divv, divv_prev, w, dtk, dt, make_box(c->p));
+                       s->h, divv, divv_prev, w, dtk, dt, make_box(c->p), hfac);
     APR_LAUNCHED(c);
     c->cells_n = -1;
     c->dt_last = dt;
+    return APR_OK;
+}
+
+int hfac_apply(apr_ctx *c, apr_state *s, const int64_t *origin, const double *hfac)
+{
+    const int64_t n = s->n;
+    hipLaunchKernelGGL(k_hfac_apply, dim3((unsigned)ceil_div(n > 0 ? n : 1, 256)), dim3(256), 0,
+                       c->stream, n, origin, hfac, s->h);
+    APR_LAUNCHED(c);
     return APR_OK;
 }
 

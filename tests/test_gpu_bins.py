@@ -152,3 +152,47 @@ def test_reorder_voids_the_stored_values():
     assert e.value.code == A.APR_ERR_INVALID
     A.apr_bins_init(ctx, ds, DT, 0.3, MAXB, p["sinks"])
     assert A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 1, 0.3, MAXB) >= 1
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_bin_zero_is_the_global_step(prec, tol):
+    """With max_bin 0 every particle sits in bin 0: one substep, every
+    particle active, i.e. apr_step's global step (random key step * 4096),
+    per id to tol of the largest value, in both forms; in FP64 both also
+    match the oracle.  The disc's velocity field has a divergence, so the h
+    predicted for the next density pass differs from the last converged h
+    that a split takes its offset and children's h from."""
+    st, p = W.planet_disc(n=4000)
+    out = []
+    for bins in (True, False):
+        ctx = A.Context(params_for(p, prec, seed=3, **SPLIT))
+        ds = A.DeviceState.from_numpy(st, capacity=3 * st["x"].shape[0] + 64)
+        if bins:
+            A.apr_bins_init(ctx, ds, DT, 0.3, 0, p["sinks"])
+            assert int(ds["bin"].max()) == 0
+            for step in range(2):
+                assert A.apr_step_bins(ctx, ds, p["zones"], p["sinks"], 0.05, step, 0.3, 0) == 1
+        else:
+            A.apr_accel(ctx, ds, p["sinks"])
+            for step in range(2):
+                A.apr_step(ctx, ds, p["zones"], p["sinks"], 0.05, step * 4096)
+        A.apr_sync_status(ctx)
+        out.append(_by_id(ds.to_numpy()))
+    if prec == "fp64":
+        # and both equal the oracle's global step (its bin-0 steps), whose
+        # splits use the h of the last density pass
+        phys = _phys(p)
+        o = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+        oracle.accel_bins(o, **phys)
+        o["bin"] = np.zeros(o["x"].shape[0], np.int8)
+        for step in range(2):
+            o = oracle.step_bins(o, zones=p["zones"], dt_max=0.05, step=step, max_bin=0,
+                                 seed=3, **SPLIT, **phys)
+        out.append(_by_id(o))
+    for o in out[1:]:
+        g = out[0]
+        assert np.array_equal(g["id"], o["id"]) and np.array_equal(g["level"], o["level"])
+        assert int((g["id"] >= st["x"].shape[0]).sum()) > 10
+        for k in ("x", "y", "z", "vx", "vy", "vz", "h"):
+            sc = max(np.max(np.abs(o[k])), 1e-30)
+            assert np.max(np.abs(g[k] - o[k])) / sc < tol, k
