@@ -146,7 +146,7 @@ def test_reorder_voids_the_stored_values():
     ds = A.DeviceState.from_numpy(st)
     A.apr_bins_init(ctx, ds, DT, 0.3, MAXB, p["sinks"])
     A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 0, 0.3, MAXB)
-    A.apr_build_cells(ctx, ds)          # a reorder outside the driver
+    A.apr_build_cells(ctx, ds)          # a reorder outside apr_step_bins
     with pytest.raises(A.AprError) as e:
         A.apr_step_bins(ctx, ds, [], p["sinks"], DT, 1, 0.3, MAXB)
     assert e.value.code == A.APR_ERR_INVALID
