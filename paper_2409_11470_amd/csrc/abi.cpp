@@ -349,8 +349,11 @@ int apr_split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int32_t nzo
         if (zones[k].n < 1 || zones[k].n > 8) return fail(c, APR_ERR_INVALID, "zone spheres");
     if (!s->u) return fail(c, APR_ERR_INVALID, "state needs u");
     int64_t d0 = 0, d1 = 0, d2 = 0;
-    return split_merge(c, s, zones, nzones, step, flags, n_split ? n_split : &d0,
-                       n_merged ? n_merged : &d1, n_spare ? n_spare : &d2);
+    rc = split_merge(c, s, zones, nzones, step, flags, n_split ? n_split : &d0,
+                     n_merged ? n_merged : &d1, n_spare ? n_spare : &d2);
+    if (rc) return rc;
+    APR_HIP(c, hipStreamSynchronize(c->stream));  // the state is final on return
+    return APR_OK;
 }
 
 // derived-value buffers the step and accel calls own

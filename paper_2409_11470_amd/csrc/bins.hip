@@ -56,31 +56,34 @@ __global__ void k_max_bin(int64_t n, const int8_t *bin, int32_t *out)
     if (lane_id() == 0 && v > 0) atomicMax(out, v);
 }
 
-// opening half kick of the particles whose step starts at substep s
-__global__ void k_open_kick(int64_t n, const int8_t *bin, int K, int64_t s, double dt_max,
-                            double *vx, double *vy, double *vz, double *u, const double *ax,
-                            const double *ay, const double *az, const double *dudt)
+// Substep s opens: the opening half kick of the particles whose step starts
+// (s a multiple of 2^(K-bin)), with their own dt; the drift of every particle
+// by the substep (wrapped into a periodic box); act = the particle's step ends
+// with this substep ((s+1) a multiple of 2^(K-bin)); made cleared.
+__global__ void k_substep_open(int64_t n, const int8_t *bin, int K, int64_t s, double dt_max,
+                               double delta, double *x, double *y, double *z, double *vx,
+                               double *vy, double *vz, double *u, const double *ax,
+                               const double *ay, const double *az, const double *dudt, Box b,
+                               uint8_t *act, uint8_t *made)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int b = bin[i];
-    if (s % ((int64_t)1 << (K - b))) return;
-    const double kd = 0.5 * ldexp(dt_max, -b);
-    vx[i] += kd * ax[i];
-    vy[i] += kd * ay[i];
-    vz[i] += kd * az[i];
-    if (u) u[i] += kd * dudt[i];
-}
-
-__global__ void k_drift_all(int64_t n, double *x, double *y, double *z, const double *vx,
-                            const double *vy, const double *vz, double dt, Box b)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int bi = bin[i];
+    const int64_t stride = (int64_t)1 << (K - bi);
+    double v[3] = {vx[i], vy[i], vz[i]};
+    if (s % stride == 0) {
+        const double kd = 0.5 * ldexp(dt_max, -bi);
+        v[0] += kd * ax[i];
+        v[1] += kd * ay[i];
+        v[2] += kd * az[i];
+        vx[i] = v[0];
+        vy[i] = v[1];
+        vz[i] = v[2];
+        if (u) u[i] += kd * dudt[i];
+    }
     double *p[3] = {x, y, z};
-    const double *v[3] = {vx, vy, vz};
     for (int k = 0; k < 3; ++k) {
-        double xn = p[k][i] + dt * v[k][i];
+        double xn = p[k][i] + delta * v[k];
         if (b.periodic) {
             const double hi = b.lo[k] + b.L[k];
             if (xn >= hi) xn -= b.L[k];
@@ -88,14 +91,7 @@ __global__ void k_drift_all(int64_t n, double *x, double *y, double *z, const do
         }
         p[k][i] = xn;
     }
-}
-
-// active: the particle's step ends with substep s
-__global__ void k_act(int64_t n, const int8_t *bin, int K, int64_t s, uint8_t *act, uint8_t *made)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    act[i] = ((s + 1) % ((int64_t)1 << (K - bin[i]))) == 0 ? 1 : 0;
+    act[i] = (s + 1) % stride == 0 ? 1 : 0;
     made[i] = 0;
 }
 
@@ -274,18 +270,17 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
     double *u = c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
     for (int64_t sub = 0; sub < nsub; ++sub) {
         int64_t n = s->n;
-        hipLaunchKernelGGL(k_open_kick, dim3(g256(n)), dim3(256), 0, c->stream, n, bin, K, sub,
-                           dt_max, s->vx, s->vy, s->vz, u, s->ax, s->ay, s->az, s->dudt);
-        hipLaunchKernelGGL(k_drift_all, dim3(g256(n)), dim3(256), 0, c->stream, n, s->x, s->y,
-                           s->z, s->vx, s->vy, s->vz, delta, box);
-        hipLaunchKernelGGL(k_act, dim3(g256(n)), dim3(256), 0, c->stream, n, bin, K, sub, act,
-                           made);
+        hipLaunchKernelGGL(k_substep_open, dim3(g256(n)), dim3(256), 0, c->stream, n, bin, K,
+                           sub, dt_max, delta, s->x, s->y, s->z, s->vx, s->vy, s->vz, u, s->ax,
+                           s->ay, s->az, s->dudt, box, act, made);
         APR_LAUNCHED(c);
         if (nzones > 0) {
-            // every particle's last nearest distance, for the split cap
-            APR_HIP(c, hipMemcpyAsync(dnn_ws<T>(c, n), b.dnn, (size_t)n * sizeof(T),
-                                      hipMemcpyDeviceToDevice, c->stream));
-            c->dens_n = n;
+            if (c->p.nn_cap > 0.0) {
+                // every particle's last nearest distance, for the split cap
+                APR_HIP(c, hipMemcpyAsync(dnn_ws<T>(c, n), b.dnn, (size_t)n * sizeof(T),
+                                          hipMemcpyDeviceToDevice, c->stream));
+                c->dens_n = n;
+            }
             int64_t ns = 0, nm = 0, nsp = 0;
             rc = split_merge(c, s, zones, nzones, step * 4096 + sub, 0, &ns, &nm, &nsp, act,
                              idx, made);

@@ -961,7 +961,6 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
     if (made && n > 0)
         APR_HIP(c, hipMemcpyAsync(made, changed, (size_t)n, hipMemcpyDeviceToDevice, c->stream));
     prof_end(c, tok);
-    APR_HIP(c, hipStreamSynchronize(c->stream));
     if (*n_split + *n_merged > 0) {  // the particle set changed: cells are stale
         if (!c->in_bins) c->bins_n = -1;
         c->cells_n = -1;
