@@ -9,8 +9,14 @@
 //   d2W/dh2 = (12 f + 8 q f' + q^2 f'')/(pi h^5),
 //   h <- h - (F/F') / (1 - F F''/(2 F'^2))   (plain Newton if |F F''/(2 F'^2)| >= 1/2).
 // It stops when |dh| < tol h; the h reported is the one the last sums were
-// taken at.  If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is
-// clamped to [h/2, 2h].
+// taken at.  In the FP64 form a Halley step with |dh| < sqrt(tol) h also
+// ends it: its
+// remaining error is of order (dh/h)^3 h, far below tol h, so h + dh is
+// reported without another pass, with rho and the h-derivative sum of Omega
+// carried to it by their Taylor series (rho to second order, errors of order
+// (dh/h)^3 and (dh/h)^2 <= tol) and the neighbour count of the last sums.
+// If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is clamped to
+// [h/2, 2h].
 //
 // Kernel (M4 or Wendland C2, support 2h, a template parameter): W = f(q)/(pi h^3),
 // q = r/h, so dW/dh = -(3f + q f')/(pi h^4).  Sums carry the normalised mass
@@ -62,6 +68,7 @@ struct DensArgs {
     float *hmax_new;      // per cell
     CandList pre;         // candidate cells walked ahead (radius 2 sigma hmax)
     double m0, hfact, tol;
+    double tol_take;      // sqrt(tol): a Halley step below it ends the iteration
     double hlim;          // periodic boxes: h must stay below this (0: no limit)
     int max_iter;
     int32_t *status;
@@ -193,6 +200,10 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         int nn;  // neighbour count; negative: the solve hit max_iter
     };
     __shared__ Out s_out[kCell];
+    // FP64 form: an accepted last step per target, {dh, drho/dh, d2rho/dh2}
+    // (dh = 0: none); one unused element in the FP32 form
+    constexpr int kTay = sizeof(T) == 8 ? kCell : 1;
+    __shared__ float s_tay[kTay][3];
 
     const Tree &tr = a.tree;
     const Geo tg = tr.lev[0][cell];
@@ -399,24 +410,36 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             double rhoh = ma * (a.hfact * a.hfact * a.hfact) * hi3;
             double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
             double hn;
+            bool halley = false;
             if (dF > 0.0) {
                 const double d2rho = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
                 const double d2F = d2rho - 12.0 * rhoh * hi * hi;
                 const double x = F * d2F / (2.0 * dF * dF);
-                hn = hh - F / (fabs(x) < 0.5 ? dF * (1.0 - x) : dF);
+                halley = fabs(x) < 0.5;
+                hn = hh - F / (halley ? dF * (1.0 - x) : dF);
             } else {
                 hn = a.hfact * cbrt(ma / rhos);
             }
             hn = fmin(fmax(hn, 0.5 * hh), 2.0 * hh);
-            bool conv = fabs(hn - hh) < a.tol * hh;
+            const double dh = hn - hh;
+            bool conv = fabs(dh) < a.tol * hh;
+            // (FP64 form only: in FP32 some target of nearly every cell is
+            // off by more than sqrt(tol), so it would save no pass)
+            const bool take = sizeof(T) == 8 && !conv && halley && fabs(dh) < a.tol_take * hh;
+            conv = conv || take;
             itc += 1;
             if (conv || itc >= a.max_iter) {
                 done = true;
-                h = hh;
+                h = take ? hn : hh;
                 if (j == 0) {
                     Out o;
                     o.rho = (T)rhos;
                     o.om = (T)(1.0 - D / (3.0 * W));
+                    if (sizeof(T) == 8) {
+                        s_tay[t % kTay][0] = take ? (float)dh : 0.0f;
+                        s_tay[t % kTay][1] = (float)drho;
+                        s_tay[t % kTay][2] = (float)((a.m0 / kPi) * (double)S.k * hi3 * hi * hi);
+                    }
                     o.dnn = nzero >= 2 ? T(0)
                                        : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
                     o.nn = conv ? nn : -1 - nn;
@@ -471,6 +494,15 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         int64_t i = s0 + t;
         Out o = s_out[t];
         a.h[i] = h;
+        if (sizeof(T) == 8 && s_tay[t % kTay][0] != 0.0f) {
+            // the accepted step carries rho (second order) and Omega = 1 +
+            // h rho'/(3 rho) (first order) from h0 = h - dh to h; only the small
+            // changes use the FP32-stored derivatives
+            const double dh = s_tay[t % kTay][0], r0 = (double)o.rho;
+            const double d1 = s_tay[t % kTay][1], d2 = s_tay[t % kTay][2], h0 = h - dh;
+            o.rho = (T)(r0 + dh * (d1 + 0.5 * dh * d2));
+            o.om = (T)((double)o.om + (dh / 3.0) * (d1 + h0 * (d2 - d1 * d1 / r0)) / r0);
+        }
         a.rho[i] = o.rho;
         a.omega[i] = o.om;
         if (a.nneigh) a.nneigh[i] = o.nn >= 0 ? o.nn : -1 - o.nn;
@@ -590,6 +622,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;
+        a.tol_take = std::sqrt(c->p.tol_h);
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
@@ -610,6 +643,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
         a.tol = c->p.tol_h;
+        a.tol_take = std::sqrt(c->p.tol_h);
         a.hlim = hlim;
         a.max_iter = c->p.max_iter;
         a.status = st;
