@@ -9,8 +9,7 @@
 //   d2W/dh2 = (12 f + 8 q f' + q^2 f'')/(pi h^5),
 //   h <- h - (F/F') / (1 - F F''/(2 F'^2))   (plain Newton if |F F''/(2 F'^2)| >= 1/2).
 // It stops when |dh| < tol h; the h reported is the one the last sums were
-// taken at.  In the FP64 form a Halley step with |dh| < sqrt(tol) h also
-// ends it: its
+// taken at.  A Halley step with |dh| < sqrt(tol) h also ends it: its
 // remaining error is of order (dh/h)^3 h, far below tol h, so h + dh is
 // reported without another pass, with rho and the h-derivative sum of Omega
 // carried to it by their Taylor series (rho to second order, errors of order
@@ -423,9 +422,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             hn = fmin(fmax(hn, 0.5 * hh), 2.0 * hh);
             const double dh = hn - hh;
             bool conv = fabs(dh) < a.tol * hh;
-            // (FP64 form only: in FP32 some target of nearly every cell is
-            // off by more than sqrt(tol), so it would save no pass)
-            const bool take = sizeof(T) == 8 && !conv && halley && fabs(dh) < a.tol_take * hh;
+            const bool take = !conv && halley && fabs(dh) < a.tol_take * hh;
             conv = conv || take;
             itc += 1;
             if (conv || itc >= a.max_iter) {
@@ -435,6 +432,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     Out o;
                     o.rho = (T)rhos;
                     o.om = (T)(1.0 - D / (3.0 * W));
+                    // The accepted step carries rho (second order) and Omega =
+                    // 1 + h rho'/(3 rho) (first order) from hh to hh + dh.  The
+                    // FP32 form does it here, in registers (three more values
+                    // per target in LDS would leave room for only three
+                    // workgroups per CU); the FP64 form keeps the values in LDS
+                    // and carries them after the loop, which spills less there.
+                    if (sizeof(T) == 4 && take) {
+                        const double d2 = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
+                        o.rho = (T)(rhos + dh * (drho + 0.5 * dh * d2));
+                        o.om = (T)(1.0 - D / (3.0 * W) +
+                                   (dh / 3.0) * (drho + hh * (d2 - drho * drho / rhos)) / rhos);
+                    }
                     if (sizeof(T) == 8) {
                         s_tay[t % kTay][0] = take ? (float)dh : 0.0f;
                         s_tay[t % kTay][1] = (float)drho;
@@ -495,9 +504,8 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         Out o = s_out[t];
         a.h[i] = h;
         if (sizeof(T) == 8 && s_tay[t % kTay][0] != 0.0f) {
-            // the accepted step carries rho (second order) and Omega = 1 +
-            // h rho'/(3 rho) (first order) from h0 = h - dh to h; only the small
-            // changes use the FP32-stored derivatives
+            // FP64 form: the accepted step's carry (only the small changes use
+            // the FP32-stored derivatives)
             const double dh = s_tay[t % kTay][0], r0 = (double)o.rho;
             const double d1 = s_tay[t % kTay][1], d2 = s_tay[t % kTay][2], h0 = h - dh;
             o.rho = (T)(r0 + dh * (d1 + 0.5 * dh * d2));
