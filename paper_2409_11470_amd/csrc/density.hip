@@ -199,10 +199,6 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         int nn;  // neighbour count; negative: the solve hit max_iter
     };
     __shared__ Out s_out[kCell];
-    // FP64 form: an accepted last step per target, {dh, drho/dh, d2rho/dh2}
-    // (dh = 0: none); one unused element in the FP32 form
-    constexpr int kTay = sizeof(T) == 8 ? kCell : 1;
-    __shared__ float s_tay[kTay][3];
 
     const Tree &tr = a.tree;
     const Geo tg = tr.lev[0][cell];
@@ -433,21 +429,14 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     o.rho = (T)rhos;
                     o.om = (T)(1.0 - D / (3.0 * W));
                     // The accepted step carries rho (second order) and Omega =
-                    // 1 + h rho'/(3 rho) (first order) from hh to hh + dh.  The
-                    // FP32 form does it here, in registers (three more values
-                    // per target in LDS would leave room for only three
-                    // workgroups per CU); the FP64 form keeps the values in LDS
-                    // and carries them after the loop, which spills less there.
-                    if (sizeof(T) == 4 && take) {
+                    // 1 + h rho'/(3 rho) (first order) from hh to hh + dh, here
+                    // in registers (three more values per target in LDS would
+                    // leave the FP32 form room for only three workgroups per CU)
+                    if (take) {
                         const double d2 = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
                         o.rho = (T)(rhos + dh * (drho + 0.5 * dh * d2));
                         o.om = (T)(1.0 - D / (3.0 * W) +
                                    (dh / 3.0) * (drho + hh * (d2 - drho * drho / rhos)) / rhos);
-                    }
-                    if (sizeof(T) == 8) {
-                        s_tay[t % kTay][0] = take ? (float)dh : 0.0f;
-                        s_tay[t % kTay][1] = (float)drho;
-                        s_tay[t % kTay][2] = (float)((a.m0 / kPi) * (double)S.k * hi3 * hi * hi);
                     }
                     o.dnn = nzero >= 2 ? T(0)
                                        : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
@@ -503,14 +492,6 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         int64_t i = s0 + t;
         Out o = s_out[t];
         a.h[i] = h;
-        if (sizeof(T) == 8 && s_tay[t % kTay][0] != 0.0f) {
-            // FP64 form: the accepted step's carry (only the small changes use
-            // the FP32-stored derivatives)
-            const double dh = s_tay[t % kTay][0], r0 = (double)o.rho;
-            const double d1 = s_tay[t % kTay][1], d2 = s_tay[t % kTay][2], h0 = h - dh;
-            o.rho = (T)(r0 + dh * (d1 + 0.5 * dh * d2));
-            o.om = (T)((double)o.om + (dh / 3.0) * (d1 + h0 * (d2 - d1 * d1 / r0)) / r0);
-        }
         a.rho[i] = o.rho;
         a.omega[i] = o.om;
         if (a.nneigh) a.nneigh[i] = o.nn >= 0 ? o.nn : -1 - o.nn;
