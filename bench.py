@@ -151,6 +151,18 @@ def run_form(A, torch, st, p, precision, steps, warmup):
     return res
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(st, p, nballs=64):
     """The FP64 oracle (brute force, OpenMP) on a bounded sample of the same
     workload: the density (h-rho Newton) of every particle within reach of
@@ -186,7 +198,7 @@ def cpu_baseline(st, p, nballs=64):
                            lo=p["lo"], hi=p["hi"], targets=tg)
     inter = float(np.sum(o["nneigh"] - 1)) + float(sum(len(a) for a in nb))
     return dict(value=inter / (t1 - t0), unit="interactions/s", cores=oracle.num_threads(),
-                kind="oracle",
+                cpu=_cpu_model(), kind="oracle",
                 sample="FP64 oracle: h-rho Newton for %d particles (within reach of %d balls "
                        "of 48 targets) over all %d sources, then forces on %d targets; %.1f s"
                        % (sh.shape[0], nballs, n, tg.shape[0], t1 - t0),

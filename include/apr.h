@@ -165,8 +165,12 @@ int apr_build_cells(apr_ctx *ctx, apr_state *s, int64_t *perm);
 int apr_density(apr_ctx *ctx, apr_state *s, void *rho, void *omega, int32_t *nneigh,
                 int32_t *iters);
 
-/* Hydrodynamic acceleration and du/dt (grad-h SPH with a per-particle
- * artificial viscosity; the paper runs Phantom's compressible SPH):
+/* Hydrodynamic acceleration and du/dt.  The paper runs Phantom's
+ * compressible SPH and states no force formula (Sec. 2.2 defers the SPH
+ * machinery to it; Sec. 3.1 and 3.2 give the locally isothermal EOS of the
+ * disc applications, appendix A the adiabatic one of its tests); the form
+ * here is the standard grad-h one, consistent with the density of
+ * apr_density, with a per-particle artificial viscosity:
  *   a_a = -sum_b m_b [(P_a + q^a)/(Omega_a rho_a^2) F_ab(h_a)
  *                   + (P_b + q^b)/(Omega_b rho_b^2) F_ab(h_b)] rhat_ab,
  *   du_a/dt = sum_b m_b (P_a + q^a)/(Omega_a rho_a^2) (v_ab . rhat) F_ab(h_a),
@@ -179,7 +183,11 @@ int apr_forces(apr_ctx *ctx, const apr_state *s, const void *rho, const void *om
 
 /* Vector-Jacobian product of the density and force sums (the adjoint; the
  * paper has none, it serves to tune split offsets against the density error
- * of Sec. 2.2 and 3.3).  Forward: rho, Omega at the h that solves
+ * of Sec. 2.2 and 3.3).  One entry point covers both products: with the
+ * force cotangents ax_bar .. dudt_bar all NULL it is the density VJP alone
+ * (an apr_density_vjp), and with them it is the VJP of density and forces
+ * together (an apr_forces_vjp that also chains through rho, h and Omega).
+ * Forward: rho, Omega at the h that solves
  * rho_sum(h) = m (hfact/h)^3 (apr_density, whose h s->h holds), then
  * apr_forces' a and du/dt.  Given cotangents rho_bar [n], h_bar [n],
  * ax_bar, ay_bar, az_bar, dudt_bar [n] (each may be NULL: zero), writes
@@ -288,8 +296,10 @@ int apr_neighbours(apr_ctx *ctx, const apr_state *s, const double *h, int32_t mo
  * on the widest axis at the floor of the mean, an even count forced on each
  * side, leaves of two); a leaf whose centre of mass lies in a zone of level
  * < l merges: the lower id stays at the centre of mass with the mean velocity
- * and mean u, level l - 1, h 2^(1/3); the other is removed.  Survivors keep
- * their order.
+ * and mean u, level l - 1, h 2^(1/3); the other is removed.  In a periodic
+ * box the centre of mass takes the other particle at its minimum image about
+ * the kept one and is wrapped back into the box (a pair across the boundary
+ * merges beside it).  Survivors keep their order.
  * Synchronises.  Updates s->n and s->next_id.  flags: bit 0 split, bit 1
  * merge (0 means both).  If the splits need more than s->capacity the state is
  * left unchanged, *n_split receives the capacity needed and APR_ERR_CAPACITY

@@ -6,7 +6,10 @@ shares no code with the GPU library.  Arrays are numpy; the arithmetic lives in
 ``apr_oracle.c`` (brute-force O(N^2) neighbour search, FP64, no FMA
 contraction) and, for gradients, in ``adjoint.py`` (dense PyTorch CPU float64).
 
-Every function below marshals arguments only.
+Most functions below marshal arguments to the C code only.  The exceptions
+hold oracle arithmetic of their own, in plain Python over those C calls:
+``relax`` (the shuffle loop of Sec. 2.4), ``courant_bin``, ``accel_bins`` and
+``step_bins`` (the individual timesteps of Sec. 2.5), each with its passage.
 """
 import ctypes as C
 import os

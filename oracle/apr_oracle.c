@@ -631,6 +631,22 @@ static double wrap(double v, int periodic, double lo, double hi)
     return v;
 }
 
+/* Centre of mass of a merging pair along one axis (Sec. 2.3: the merged
+ * particle sits at the pair's centre of mass; equal masses).  In a periodic
+ * box the removed particle's coordinate o is taken at its minimum image about
+ * the kept one's, k, before averaging, and the mean is wrapped back into the
+ * box, so that a pair across the boundary merges next to the boundary and
+ * not at mid-box.  Pairs closer than half the box average as they are. */
+static double merge_mid(double k, double o, int periodic, double lo, double hi)
+{
+    if (periodic) {
+        double L = hi - lo, d = o - k;
+        if (d > 0.5 * L) o -= L;
+        else if (d < -0.5 * L) o += L;
+    }
+    return wrap((k + o) * 0.5, periodic, lo, hi);
+}
+
 /* ------------------------------------------------------------------------ */
 /* The pairing tree used for merging (paper Sec. 2.3): a k-d tree cut       */
 /* through the centre of mass, with an even count forced on each side, so   */
@@ -884,12 +900,12 @@ int32_t orc_split_merge(int64_t n, int64_t cap, double *x, double *y, double *z,
             int64_t np = orc_pair_tree(nc, cand, x, y, z, id, lo, hi, n, pairs);
             for (int64_t k = 0; k < np; ++k) {
                 int64_t p = pairs[2 * k], q = pairs[2 * k + 1];
-                double cx = (x[p] + x[q]) * 0.5;
-                double cy = (y[p] + y[q]) * 0.5;
-                double cz = (z[p] + z[q]) * 0.5;
-                if (!(zone_level(&Z, cx, cy, cz, NULL) < l)) continue;
                 int64_t keep = id[p] < id[q] ? p : q;
                 int64_t gone = keep == p ? q : p;
+                double cx = merge_mid(x[keep], x[gone], periodic, lo[0], hi[0]);
+                double cy = merge_mid(y[keep], y[gone], periodic, lo[1], hi[1]);
+                double cz = merge_mid(z[keep], z[gone], periodic, lo[2], hi[2]);
+                if (!(zone_level(&Z, cx, cy, cz, NULL) < l)) continue;
                 x[keep] = cx; y[keep] = cy; z[keep] = cz;
                 vx[keep] = (vx[p] + vx[q]) * 0.5;
                 vy[keep] = (vy[p] + vy[q]) * 0.5;

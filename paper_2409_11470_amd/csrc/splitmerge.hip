@@ -613,19 +613,35 @@ __global__ void k_tree_root(int64_t m, int32_t *lo, int32_t *hi)
     hi[i] = (int32_t)m;
 }
 
-__global__ void k_merge_pairs(int64_t npairs, const uint32_t *es, SArr s, Zones Z, int l,
+// Centre of mass of a merging pair along axis k (equal masses, Sec. 2.3).
+// Periodic boxes: the removed particle's coordinate o is taken at its minimum
+// image about the kept one's, c, and the mean wrapped back into the box, so a
+// pair across the boundary merges beside it, not at mid-box.  A pair closer
+// than half the box averages as it is.
+__device__ inline double merge_mid(double c, double o, const Box &b, int k)
+{
+#pragma clang fp contract(off)
+    if (b.periodic) {
+        double d = o - c;
+        if (d > 0.5 * b.L[k]) o -= b.L[k];
+        else if (d < -0.5 * b.L[k]) o += b.L[k];
+    }
+    return wrap((c + o) * 0.5, b, k);
+}
+
+__global__ void k_merge_pairs(int64_t npairs, const uint32_t *es, SArr s, Zones Z, Box b, int l,
                               uint8_t *changed, uint8_t *removed, unsigned long long *count)
 {
 #pragma clang fp contract(off)
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npairs) return;
     uint32_t p = es[2 * k], q = es[2 * k + 1];
-    double cx = (s.x[p] + s.x[q]) * 0.5;
-    double cy = (s.y[p] + s.y[q]) * 0.5;
-    double cz = (s.z[p] + s.z[q]) * 0.5;
-    if (!(zone_level(Z, cx, cy, cz, nullptr) < l)) return;
     uint32_t keep = s.id[p] < s.id[q] ? p : q;
     uint32_t gone = keep == p ? q : p;
+    double cx = merge_mid(s.x[keep], s.x[gone], b, 0);
+    double cy = merge_mid(s.y[keep], s.y[gone], b, 1);
+    double cz = merge_mid(s.z[keep], s.z[gone], b, 2);
+    if (!(zone_level(Z, cx, cy, cz, nullptr) < l)) return;
     s.x[keep] = cx;
     s.y[keep] = cy;
     s.z[keep] = cz;
@@ -910,7 +926,7 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                 batch = 4;
             }
             hipLaunchKernelGGL(k_merge_pairs, dim3(grid(m / 2)), dim3(256), 0, c->stream, m / 2,
-                               es[cur], A, Z, l, changed, removed, mcount);
+                               es[cur], A, Z, b, l, changed, removed, mcount);
             APR_LAUNCHED(c);
         }
         unsigned long long nm = 0;

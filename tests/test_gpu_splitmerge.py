@@ -129,3 +129,30 @@ def test_capacity_error_leaves_state():
     after = ds.to_numpy()
     for k in ("x", "h", "level", "id"):
         assert np.array_equal(before[k], after[k])
+
+
+def test_merge_pairs_across_periodic_boundary():
+    # four level-1 pairs, each straddling the x boundary of a periodic box
+    # (minimum-image separation 0.3-0.4, plain separation above half the box),
+    # the pairs at the corners (y, z) in {0.02, 0.98}^2, so that the tree cuts
+    # y and z first and pairs them as built.  A small level-1 sphere sits on
+    # each pair's plain mean (x near 0.5): only a centre of mass taken across
+    # the boundary lies outside it, so every pair merges
+    rng = np.random.default_rng(2409114791)
+    g = 4
+    xa = 0.15 + 0.05 * rng.random(g)
+    xb = 0.80 + 0.05 * rng.random(g)
+    y = np.array([0.02, 0.02, 0.98, 0.98]) + 1e-3 * rng.random(g)
+    z = np.array([0.02, 0.98, 0.02, 0.98]) + 1e-3 * rng.random(g)
+    n = 2 * g
+    st = dict(x=np.concatenate([xa, xb]), y=np.concatenate([y, y]), z=np.concatenate([z, z]),
+              vx=rng.standard_normal(n), vy=rng.standard_normal(n), vz=rng.standard_normal(n),
+              u=1.0 + rng.random(n), h=np.full(n, 0.02), level=np.ones(n, np.int8),
+              id=rng.permutation(n).astype(np.int64), next_id=n)
+    p = dict(lo=(0, 0, 0), hi=(1, 1, 1), periodic=True, m0=1.0 / 4096)
+    zones = [dict(c=(0.5 * (xa[k] + xb[k]), y[k], z[k]), r=(0.1,), ell=(1,)) for k in range(g)]
+    gp, cnt = _gpu_pass(st, p, zones, 0, 2)
+    o = _orc_pass(st, p, zones, 0, 2)
+    assert cnt[1] == g
+    _compare(gp, o, cnt)
+    assert np.all((o["x"] < 0.1) | (o["x"] >= 0.9))

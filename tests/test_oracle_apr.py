@@ -301,3 +301,31 @@ def test_pair_tree_degenerate_cuts(orc):
     pr = orc.pair_tree(np.arange(6), xs, xs, xs, np.array([9, 3, 7, 1, 5, 11]), (0, 0, 0),
                        (1, 1, 1))
     assert sorted(map(tuple, np.sort(pr, 1).tolist())) == [(0, 5), (1, 3), (2, 4)]
+
+
+def test_merge_across_periodic_boundary(orc):
+    # Sec. 2.3: the merged particle sits at the pair's centre of mass.  A pair
+    # straddling a periodic boundary has it beside the boundary: with the kept
+    # particle (lower id) at x = 1/32 and the other at 61/64, the other's
+    # minimum image about it is 61/64 - 1 = -3/64, the mean is -1/128, and it
+    # wraps to 127/128.  The plain mean would be 63/128, at mid-box; the zone
+    # (level 1 inside r = 0.2 of the box centre) makes that difference decide
+    # the merge too: 63/128 lies in the zone (no merge), 127/128 outside.
+    zones = [dict(c=(0.5, 0.5, 0.5), r=(0.2,), ell=(1,))]
+    st = dict(x=np.array([61 / 64, 1 / 32]), y=np.array([0.5, 0.5]), z=np.array([0.5, 0.5]),
+              vx=np.array([1.0, 3.0]), vy=np.zeros(2), vz=np.zeros(2), u=np.array([1.0, 2.0]),
+              h=np.array([0.01, 0.01]), level=np.array([1, 1], np.int8), id=np.array([5, 2]),
+              next_id=6)
+    kw = dict(step=0, seed=0, lo=(0, 0, 0), hi=(1, 1, 1), do_split=False)
+    out = orc.split_merge(st, zones, periodic=True, **kw)
+    assert out["n_merged"] == 1 and out["id"][0] == 2 and out["level"][0] == 0
+    assert out["x"][0] == 127 / 128 and out["y"][0] == 0.5 and out["z"][0] == 0.5
+    assert out["vx"][0] == 2.0 and out["u"][0] == 1.5
+    # the same pair in y and z (kept particle above the boundary this time):
+    # mean of 63/64 and 1 + 1/64 is 1, wrapped to 0
+    st2 = dict(st, x=np.array([0.25, 0.25]), y=np.array([1 / 64, 63 / 64]),
+               z=np.array([1 / 64, 63 / 64]))
+    out2 = orc.split_merge(st2, [], periodic=True, **kw)
+    assert out2["n_merged"] == 1 and out2["y"][0] == 0.0 and out2["z"][0] == 0.0
+    # not periodic: the plain mean, which lies in the zone, so no merge
+    assert orc.split_merge(st, zones, periodic=False, **kw)["n_merged"] == 0
