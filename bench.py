@@ -26,8 +26,17 @@ stepped with its refinement zone (every step: cells, density, split/merge,
 forces, sink gravity, leapfrog) and the 8M-particle circumbinary disc (FP32
 density + forces + adjoint).
 
+The FP64 form runs twice: at its own Newton tolerance 1e-12 and at the FP32
+form's 1e-6 (the like-for-like comparison of the precisions); each form
+reports its Newton passes per step.
+
+The CPU baseline (the FP64 oracle on a bounded ball sample) is taken on the
+FP32 form's state after its timed steps, so that it also states that form's
+error: the oracle's h, rho, a and du/dt at the GPU's positions against the
+GPU's own ("error_vs_oracle").
+
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-legs]
-       [--no-cpu-baseline] [--fp32-only]
+       [--no-cpu-baseline] [--fp32-only] [--only-leg circumbinary]
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -42,17 +51,26 @@ sys.path.insert(0, ROOT)
 METRIC = "SPH pair interactions/s (density+force), FP32 vs FP64 form, at stated error"
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
-# Algorithmic floating-point operations per pair (adds, multiplies, compares,
-# square roots and reciprocals each count one), from the formulas the kernels
-# evaluate once per pair:
-#   density: separation 3, r^2 5, support test 1, sqrt 1, q 1, kernel
-#            polynomial f and 3f + q f' 7, two mass-weighted sums 4      -> 22
-#   force:   separation 3, r^2 5, two support tests 2, 1/r 1, r 1, q_a, q_b 2,
-#            f'(q_a), f'(q_b) 8, h^-4 factors 2, velocity difference 3,
-#            v.rhat 6, viscosity terms 10, pair weight 5, acceleration 6,
-#            du/dt 4, signal-velocity max 1                              -> 59
-FLOP_DENSITY_PAIR = 22
-FLOP_FORCE_PAIR = 59
+# Algorithmic floating-point operations per pair, as the hot-path scope
+# counts them: the density pair about 30 (the kernel, its h-derivative and
+# the second derivative for the h-rho Newton step, one sqrt) plus about 8 for
+# the compensated (Kahan) sums, 38 in all; the force pair about 70 (both
+# supports' kernel gradients, one sqrt and one reciprocal, the viscosity, the
+# acceleration and du/dt) plus about 16 of compensation, 86.  Each counts
+# once per pair at the converged h, however many Newton passes run.  The
+# leaner counts of the formulas alone, without compensation or the second
+# derivative (22 and 59), are reported beside them.
+FLOP_DENSITY_PAIR = 38
+FLOP_FORCE_PAIR = 86
+FLOP_DENSITY_PAIR_MIN = 22
+FLOP_FORCE_PAIR_MIN = 59
+# Algorithmic HBM bytes per particle (the hot-path scope's count): density
+# reads x (24), level (1), h (8) and writes h, rho, Omega, n_neigh (8 + 4 +
+# 4 + 4), 53 in all; forces read x, v, level, h, rho, Omega, u (24 + 24 + 1
+# + 8 + 4 + 4 + 8) and write a, du/dt, vsig (12 + 4 + 4), 93.
+BYTES_DENSITY = 53
+BYTES_FORCES = 93
+PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE over the 20 timed launches, each scaled by what the
@@ -84,15 +102,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_ctx(A, p, precision, seed=7):
-    """A context for a workload's parameter dict p in the given form."""
+def make_ctx(A, p, precision, seed=7, tol=None):
+    """A context for a workload's parameter dict p in the given form (Newton
+    tolerance 1e-6 for FP32, 1e-12 for FP64, unless tol is given)."""
+    if tol is None:
+        tol = 1e-6 if precision == "fp32" else 1e-12
     return A.Context(A.make_params(
         precision=A.APR_FP32 if precision == "fp32" else A.APR_FP64, eos=int(p["eos"]),
         periodic=int(p["periodic"]), box_lo=p["lo"], box_hi=p["hi"], m0=p["m0"],
         hfact=p["hfact"], kernel=int(p.get("kernel", 0)), gamma=p["gamma"], cs0=p["cs0"],
         q_cs=p.get("q_cs", 0.25),
         r_ref=p.get("r_ref", 1.0), av_alpha=p["alpha"], av_beta=p["beta"],
-        tol_h=1e-6 if precision == "fp32" else 1e-12, max_iter=60,
+        tol_h=tol, max_iter=60,
         r_sep_factor=p.get("r_sep_factor", 0.2), nn_cap=p.get("nn_cap", 0.0),
         split_mode=int(p.get("split_mode", 0)), seed=seed, G=p.get("G", 1.0)))
 
@@ -103,8 +124,38 @@ def count_interactions(A, ctx, ds):
             A.apr_neighbours(ctx, ds, h, 1, count_only=True))
 
 
-def run_form(A, torch, st, p, precision, steps, warmup):
-    ctx = make_ctx(A, p, precision)
+def final_values(A, torch, ctx, ds):
+    """Density and hydro forces on a copy of the state as it stands (cells
+    rebuilt): per-id numpy arrays of x, y, z, h, rho, ax, ay, az, dudt, and the
+    other state arrays the oracle needs."""
+    import numpy as np
+    w = ds.clone()
+    A.apr_build_cells(ctx, w)
+    n = w.n
+    dt = ctx.dtype
+    rho = torch.zeros(n, dtype=dt, device="cuda")
+    om = torch.zeros_like(rho)
+    A.apr_density(ctx, w, rho, om)
+    acc = [torch.zeros_like(rho) for _ in range(4)]
+    A.apr_forces(ctx, w, rho, om, *acc)
+    A.apr_sync_status(ctx)
+    g = w.to_numpy()
+    ids = g["id"]
+    out = {}
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level"):
+        v = np.empty_like(g[k])
+        v[ids] = g[k]
+        out[k] = v
+    for k, t in (("rho", rho), ("ax", acc[0]), ("ay", acc[1]), ("az", acc[2]),
+                 ("dudt", acc[3])):
+        v = np.empty(n)
+        v[ids] = t.double().cpu().numpy()
+        out[k] = v
+    return out
+
+
+def run_form(A, torch, st, p, precision, steps, warmup, tol=None, keep_final=False):
+    ctx = make_ctx(A, p, precision, tol=tol)
     ds = A.DeviceState.from_numpy(st)
     A.apr_accel(ctx, ds)
     dt = A.apr_timestep(ctx, ds, 0.3)
@@ -143,7 +194,10 @@ def run_form(A, torch, st, p, precision, steps, warmup):
                density_ms=ms_d / max(cnt_d, 1), forces_ms=ms_f / max(cnt_f, 1),
                cells_ms=ms_c / max(cnt_c, 1), launches=(cnt_d, cnt_f, cnt_c),
                cand_ms_per_step=ms_p / max(steps, 1),
-               counters=counters)
+               newton_passes_per_step=counters["density_passes"] / steps,
+               counters=counters, newton_tol=ctx.params.tol_h)
+    if keep_final:
+        res["final"] = final_values(A, torch, ctx, ds)
     # density + forces pass: both kernels and the candidate walks ahead of them
     res["density_force_rate"] = per_step / (1e-3 * (res["density_ms"] + res["forces_ms"] +
                                                     res["cand_ms_per_step"]))
@@ -163,14 +217,21 @@ def _cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(st, p, nballs=64):
+def cpu_baseline(st, p, nballs=64, gpu=None, h_guess=None):
     """The FP64 oracle (brute force, OpenMP) on a bounded sample of the same
     workload: the density (h-rho Newton) of every particle within reach of
     nballs balls of 48 targets, then the forces on the targets (about 15 s on
-    16 host threads)."""
+    16 host threads).
+
+    With gpu (the GPU form's per-id values on the state st, final_values),
+    the sample is also the stated error of that form: the oracle's h, rho
+    and forces at the same positions against the GPU's, at the targets.  The
+    oracle's Newton starts from h_guess (the workload's initial h), not from
+    the GPU's h."""
     import numpy as np
     import oracle
     n = st["x"].shape[0]
+    h0 = st["h"] if h_guess is None else h_guess
     pos = np.stack([st["x"], st["y"], st["z"]], 1)
     hs = 1.2 / 64
     rng = np.random.default_rng(99)
@@ -186,14 +247,28 @@ def cpu_baseline(st, p, nballs=64):
     sh = np.unique(np.concatenate(sh))
     kw = dict(m0=p["m0"], periodic=True, lo=p["lo"], hi=p["hi"])
     t0 = time.perf_counter()
-    o = oracle.density(st["x"], st["y"], st["z"], st["level"], st["h"][sh], tol=1e-12,
+    o = oracle.density(st["x"], st["y"], st["z"], st["level"], h0[sh], tol=1e-12,
                        max_iter=60, targets=sh, **kw)
     h, rho, om = np.full(n, 1e-9), np.ones(n), np.ones(n)
     h[sh], rho[sh], om[sh] = o["h"], o["rho"], o["omega"]
-    oracle.forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"], st["level"],
-                  h, rho, om, eos=int(p["eos"]), gamma=p["gamma"], alpha=p["alpha"],
-                  beta=p["beta"], targets=tg, **kw)
+    f = oracle.forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st["u"],
+                      st["level"], h, rho, om, eos=int(p["eos"]), gamma=p["gamma"],
+                      alpha=p["alpha"], beta=p["beta"], targets=tg, **kw)
     t1 = time.perf_counter()
+    err = None
+    if gpu is not None:
+        ga = np.sqrt(sum((gpu[k][tg] - f[k]) ** 2 for k in ("ax", "ay", "az")))
+        err = dict(targets=int(tg.shape[0]),
+                   h_max_rel=float(np.max(np.abs(gpu["h"][tg] / h[tg] - 1))),
+                   rho_max_rel=float(np.max(np.abs(gpu["rho"][tg] / rho[tg] - 1))),
+                   a_max_rel_l1=float(np.max(ga / f["anorm"])),
+                   dudt_max_rel_l1=float(np.max(np.abs(gpu["dudt"][tg] - f["dudt"])
+                                                / np.maximum(f["unorm"], 1e-300))),
+                   gates=dict(rho=1e-3, a=1e-3),
+                   definition="at the sampled targets, GPU FP32 form vs the FP64 oracle at "
+                              "the same positions: max |h/h_o - 1|, |rho/rho_o - 1|, "
+                              "|a - a_o| / sum_b |pair term| (the L1 pair sum), |du/dt - "
+                              "du/dt_o| / L1 sum")
     nb = oracle.neighbours(st["x"], st["y"], st["z"], h, symmetric=True, periodic=True,
                            lo=p["lo"], hi=p["hi"], targets=tg)
     inter = float(np.sum(o["nneigh"] - 1)) + float(sum(len(a) for a in nb))
@@ -202,7 +277,7 @@ def cpu_baseline(st, p, nballs=64):
                 sample="FP64 oracle: h-rho Newton for %d particles (within reach of %d balls "
                        "of 48 targets) over all %d sources, then forces on %d targets; %.1f s"
                        % (sh.shape[0], nballs, n, tg.shape[0], t1 - t0),
-                seconds=t1 - t0)
+                seconds=t1 - t0, error=err)
 
 
 def _cot(torch, n, dt, seed):
@@ -245,8 +320,8 @@ def forward_adjoint(A, torch, ctx, ds, reps):
            ("vjp_ms", A.APR_PROF_VJP))}
     ms["cand_ms_per_rep"] = prof[A.APR_PROF_CAND][0] / reps
     inter = d + f
-    out = dict(n=n, interactions=inter, failures=fails, reps=reps,
-               wall_ms_per_rep=1e3 * wall / reps, **ms)
+    out = dict(n=n, interactions=inter, density_pairs=d, force_pairs=f, failures=fails,
+               reps=reps, wall_ms_per_rep=1e3 * wall / reps, **ms)
     # each of density, forces and the adjoint has one candidate walk ahead of it
     cw = ms["cand_ms_per_rep"] / 3.0
     out["forward_rate"] = inter / (1e-3 * (ms["density_ms"] + ms["forces_ms"] + 2 * cw))
@@ -393,13 +468,28 @@ def leg_relax(A, torch, W):
 
 
 def leg_circumbinary(A, torch, W, reps):
-    """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint."""
+    """The 8M-particle circumbinary disc (three masses): FP32 forward + adjoint,
+    and the roofline of its density + force pass against both HBM (the
+    algorithmic bytes per particle) and the FP32 VALU (the algorithmic FLOPs
+    per pair)."""
     st, p = W.circumbinary_disc()
     ctx = make_ctx(A, p, "fp32")
     ds = A.DeviceState.from_numpy(st)
     del st
+    fa = forward_adjoint(A, torch, ctx, ds, reps)
+    n = fa["n"]
+    sec = 1e-3 * (fa["density_ms"] + fa["forces_ms"])
+    flops = FLOP_DENSITY_PAIR * (fa["density_pairs"] + n) + FLOP_FORCE_PAIR * fa["force_pairs"]
+    hbm = (BYTES_DENSITY + BYTES_FORCES) * n
+    fa["density_force_roofline"] = dict(
+        pass_ms=1e3 * sec,
+        valu=dict(achieved=flops / sec / 1e12, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                  frac=flops / sec / 1e12 / PEAK_FP32_TFLOPS, flop=flops),
+        hbm=dict(achieved=hbm / sec / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                 frac=hbm / sec / 1e9 / PEAK_HBM_GBS, bytes=hbm),
+        binding="valu")
     out = dict(workload="circumbinary disc, 8.0M particles (levels 0, 1, 2), locally "
-                        "isothermal", fp32=forward_adjoint(A, torch, ctx, ds, reps))
+                        "isothermal", fp32=fa)
     ctx.close()
     return out
 
@@ -483,6 +573,38 @@ def leg_planet_disc_bins(A, torch, W, nsub=64, max_bin=6):
     return out
 
 
+def form_summary(r):
+    return {k: r[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms", "cells_ms",
+                              "cand_ms_per_step", "interactions_per_step",
+                              "density_force_rate", "newton_tol", "newton_passes_per_step",
+                              "failures", "counters")}
+
+
+def density_roofline(r32):
+    """Roofline of the dominant kernel of the FP32 form (plain VALU arithmetic):
+    algorithmic FLOPs per launch over its mean launch time (HIP events on the
+    library's stream)."""
+    n = r32["n"]
+    if r32["density_ms"] >= r32["forces_ms"]:
+        kern, ms = "k_density<float, 0, false, false>", r32["density_ms"]
+        pairs = r32["density_pairs"] + n
+        flops, flops_min = FLOP_DENSITY_PAIR * pairs, FLOP_DENSITY_PAIR_MIN * pairs
+    else:
+        kern, ms = "k_forces<float, 0, false>", r32["forces_ms"]
+        pairs = r32["force_pairs"]
+        flops, flops_min = FLOP_FORCE_PAIR * pairs, FLOP_FORCE_PAIR_MIN * pairs
+    achieved = flops / (ms * 1e-3) / 1e12
+    traffic = measured_traffic(kern)
+    roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic, kernel=kern,
+                flop_per_launch=flops, ms_per_launch=ms,
+                frac_lean_flops=flops_min / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS)
+    if traffic is not None:
+        roof["traffic_unit"] = "bytes per launch (HBM, counters)"
+        roof["traffic_gbs"] = traffic / (ms * 1e-3) / 1e9
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,6 +614,8 @@ def main():
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the disc and refined-box legs")
+    ap.add_argument("--only-leg", default=None,
+                    help="run only this leg (circumbinary), for profiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -505,30 +629,28 @@ def main():
     torch.cuda.set_device(0)
     st, p = W.shock_box()
     log("workload: %d particles" % st["x"].shape[0])
-    r32 = run_form(A, torch, st, p, "fp32", args.steps, args.warmup)
-    log("fp32: %.3e interactions/s, %.3f ms/step" % (r32["value"], r32["ms_per_step"]))
-    r64 = None
-    if not args.fp32_only:
-        r64 = run_form(A, torch, st, p, "fp64", args.steps, args.warmup)
-        log("fp64: %.3e interactions/s, %.3f ms/step" % (r64["value"], r64["ms_per_step"]))
-    # roofline of the dominant kernel of the FP32 form (plain VALU arithmetic)
-    n = r32["n"]
-    if r32["density_ms"] >= r32["forces_ms"]:
-        kern, ms = "k_density<float, 0, false, false>", r32["density_ms"]
-        flops = FLOP_DENSITY_PAIR * (r32["density_pairs"] + n)
-    else:
-        kern, ms = "k_forces<float, 0, false>", r32["forces_ms"]
-        flops = FLOP_FORCE_PAIR * r32["force_pairs"]
-    achieved = flops / (ms * 1e-3) / 1e12
-    traffic = measured_traffic(kern)
-    roof = dict(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32_TFLOPS, traffic=traffic, kernel=kern,
-                flop_per_launch=flops, ms_per_launch=ms)
-    if traffic is not None:
-        roof["traffic_unit"] = "bytes per launch (HBM, counters)"
-        roof["traffic_gbs"] = traffic / (ms * 1e-3) / 1e9
+    only = args.only_leg
+    r32 = r64 = r64t = roof = None
+    if only is None:
+        r32 = run_form(A, torch, st, p, "fp32", args.steps, args.warmup, keep_final=True)
+        log("fp32: %.3e interactions/s, %.3f ms/step" % (r32["value"], r32["ms_per_step"]))
+        if not args.fp32_only:
+            r64 = run_form(A, torch, st, p, "fp64", args.steps, args.warmup)
+            log("fp64: %.3e interactions/s, %.3f ms/step" % (r64["value"], r64["ms_per_step"]))
+            # the FP64 form at the FP32 form's Newton tolerance: the like-for-like
+            # comparison of the two precisions
+            r64t = run_form(A, torch, st, p, "fp64", args.steps, args.warmup, tol=1e-6)
+            log("fp64 at tol 1e-6: %.3e interactions/s, %.3f ms/step"
+                % (r64t["value"], r64t["ms_per_step"]))
+        roof = density_roofline(r32)
     legs = None
-    if not args.no_legs:
+    if only is not None:
+        legs = {}
+        if only == "circumbinary":
+            legs["circumbinary_forward_adjoint"] = leg_circumbinary(A, torch, W, 3)
+        else:
+            raise SystemExit("unknown leg %r" % only)
+    elif not args.no_legs:
         legs = {}
         legs["refine_box_split_adjoint"] = leg_refine_box(A, torch, W, 5)
         log("refined box: split %.2f ms, fp32 adjoint %.3e interactions/s"
@@ -558,11 +680,18 @@ def main():
         log("circumbinary: fp32 forward+adjoint %.3e interactions/s"
             % legs["circumbinary_forward_adjoint"]["fp32"]["forward_adjoint_rate"])
         torch.cuda.empty_cache()
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(st, p)
+    cpu = err = None
+    if not args.no_cpu_baseline and r32 is not None:
+        cpu = cpu_baseline(r32["final"], p, gpu=r32["final"], h_guess=st["h"])
         log("cpu baseline: %.3e interactions/s on %d threads" % (cpu["value"], cpu["cores"]))
+        err = cpu.pop("error")
+        err["state"] = "the FP32 form's state after its %d timed steps" % args.steps
+        log("fp32 error vs oracle at the final state: rho %.2e, a %.2e (of the L1 pair sum)"
+            % (err["rho_max_rel"], err["a_max_rel_l1"]))
         cpu.pop("seconds")
+    if r32 is None:
+        print(json.dumps({"legs": legs}), flush=True)
+        return
     out = {
         "metric": METRIC, "value": r32["value"], "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
@@ -573,19 +702,15 @@ def main():
                    "n_particles": r32["n"], "precision_form": "fp32 (cell-relative, "
                    "compensated sums; FP64 positions, leapfrog, Newton test)",
                    "newton_tol": 1e-6},
-        "roofline": roof, "cpu_baseline": cpu,
-        "fp32_form": {k: r32[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms",
-                                           "cells_ms", "cand_ms_per_step", "interactions_per_step",
-                                           "density_force_rate", "failures", "counters")},
-        "fp64_form": None if r64 is None else {
-            k: r64[k] for k in ("value", "ms_per_step", "density_ms", "forces_ms", "cells_ms",
-                                "cand_ms_per_step", "interactions_per_step", "density_force_rate", "failures",
-                                "counters")},
+        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": err,
+        "fp32_form": form_summary(r32),
+        "fp64_form": None if r64 is None else form_summary(r64),
+        "fp64_form_at_fp32_tol": None if r64t is None else form_summary(r64t),
     }
     out["legs"] = legs
     if r64 is not None:
-        out["fp64_form"]["newton_tol"] = 1e-12
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
+        out["fp32_over_fp64_same_tol"] = r32["value"] / r64t["value"]
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

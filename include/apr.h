@@ -159,7 +159,11 @@ int apr_build_cells(apr_ctx *ctx, apr_state *s, int64_t *perm);
  * current h (until |dh| < tol_h h); writes the converged h into s->h and
  *   Omega_a = 1 + h_a / (3 rho_a) sum_b m_b dW_ab/dh_a.
  * rho, omega: [n] (float or double); nneigh (optional) counts b with
- * r_ab < 2 h_a, self included; iters (optional) Newton sums per particle.
+ * r_ab < 2 h_a at the h written, self included; iters (optional) Newton
+ * passes per particle.  Membership is that of the FP64 predicate of
+ * apr_neighbours (mode 0) in both precisions: the pair-precision test is
+ * decided again in FP64 on absolute positions inside a guard band about the
+ * support's edge.
  * Needs apr_build_cells on the same positions.  Asynchronous: failures to
  * converge are counted on the device; apr_sync_status reports them. */
 int apr_density(apr_ctx *ctx, apr_state *s, void *rho, void *omega, int32_t *nneigh,
@@ -177,9 +181,14 @@ int apr_density(apr_ctx *ctx, apr_state *s, void *rho, void *omega, int32_t *nne
  * F_ab(h) = W'(r)/... for r < 2h, q^a = -rho_a vsig_a (v_ab . rhat)/2 for
  * approaching pairs; pairs with r < 2 max(h_a, h_b).  P and c come from the
  * EOS.  vsig (optional) = max over pairs of alpha c_a + beta max(0, -v_ab.rhat).
- * rho, omega from apr_density on the same state.  Outputs [n]. */
+ * npair (optional, int32 [n]) counts each target's pairs: b != a with
+ * r_ab < 2 max(h_a, h_b).  Membership is that of the FP64 predicate of
+ * apr_neighbours (mode 1) in both precisions: the pair-precision test is
+ * decided again in FP64 on absolute positions inside a guard band about
+ * either support's edge.  rho, omega from apr_density on the same state.
+ * Outputs [n]. */
 int apr_forces(apr_ctx *ctx, const apr_state *s, const void *rho, const void *omega, void *ax,
-               void *ay, void *az, void *dudt, void *vsig);
+               void *ay, void *az, void *dudt, void *vsig, int32_t *npair);
 
 /* Vector-Jacobian product of the density and force sums (the adjoint; the
  * paper has none, it serves to tune split offsets against the density error
@@ -348,13 +357,19 @@ int apr_sync_status(apr_ctx *ctx, int64_t *count);
 enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
        APR_PROF_VJP = 4, APR_PROF_CAND = 5, APR_PROF_N = 6 };
 int apr_profile_enable(apr_ctx *ctx, int on);
-/* Work counters since the last reset (diagnostics), written to c[0..7]:
+/* Work counters since the last reset (diagnostics), written to
+ * c[0 .. APR_COUNTERS_N-1]:
  * [0] h-rho solves that hit max_iter, [1] smoothing lengths at the periodic limit,
  * [2] density cells whose candidates did not fit in one LDS window (staged
  * window by window instead), [3] the same for forces, [4] sub-block lists
  * that did not fit, [5] density searches repeated with a larger radius,
  * [6] density Newton passes summed over cells, [7] windows staged by the
- * density kernel summed over cells and passes.  Synchronises. */
+ * density kernel summed over cells and passes, [8] density targets so far
+ * from their cell's centre (|x - c|_1 >= 252 h) that the staging slack no
+ * longer covers the guard band of the support test (none expected; exact
+ * membership is then not assured), [9] pair tests decided in FP64 inside
+ * the guard band (density and forces).  Synchronises. */
+enum { APR_COUNTERS_N = 10 };
 int apr_counters(apr_ctx *ctx, int64_t *c, int reset);
 int apr_profile_read(apr_ctx *ctx, double *ms, int64_t *launches, int reset);
 

@@ -13,6 +13,12 @@ gradients; then one Newton step is taken from h* with F'(h*) held constant,
     h = h* - F(h*; x, m) / F'(h*),
 whose value equals h* to the solver tolerance and whose derivative is the
 implicit-function-theorem one, dh/dp = -(dF/dp) / F'.
+
+A subset of a large set can be solved alone: with ``solve`` (a bool mask),
+only those particles' h solve the h-rho relation; the others keep the given
+h0 as a constant (their own neighbourhoods may be incomplete in the subset,
+and a loss that depends on their h only through which pairs exist is exact
+when h0 is their converged value).
 """
 import math
 
@@ -70,7 +76,7 @@ def _rho_terms(r, h, m, kernel=0):
 
 
 def converge_h(x, m, h0, hfact=1.2, tol=1e-14, max_iter=100, periodic=False, L=(1, 1, 1),
-               kernel=0):
+               kernel=0, solve=None):
     with torch.no_grad():
         _, r, _ = _pairs(x, periodic, L)
         h = h0.clone()
@@ -82,6 +88,8 @@ def converge_h(x, m, h0, hfact=1.2, tol=1e-14, max_iter=100, periodic=False, L=(
             hn = torch.where(dF > 0, h - F / dF, hfact * (m / rs) ** (1.0 / 3.0))
             hn = torch.minimum(torch.maximum(hn, 0.5 * h), 2.0 * h)
             done = (hn - h).abs() < tol * h
+            if solve is not None:
+                done = done | ~solve
             h = torch.where(done, h, hn)
             if bool(done.all()):
                 break
@@ -101,11 +109,14 @@ def eos(x, rho, u, eos, cs0=1.0, q_cs=0.25, r_ref=1.0, gamma=5.0 / 3.0):
 
 
 def forward(x, m, v, u, h0, *, eos_kind, hfact=1.2, cs0=1.0, q_cs=0.25, r_ref=1.0,
-            gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, L=(1, 1, 1), kernel=0):
+            gamma=5.0 / 3.0, alpha=1.0, beta=2.0, periodic=False, L=(1, 1, 1), kernel=0,
+            solve=None):
     """rho [n], a [n, 3], du/dt [n], h [n], Omega [n] as differentiable functions
-    of x [n, 3] and m [n] (v, u held fixed).  kernel: 0 M4, 1 Wendland C2."""
+    of x [n, 3] and m [n] (v, u held fixed).  kernel: 0 M4, 1 Wendland C2.
+    solve (optional bool [n]): only those h solve the h-rho relation; the
+    others stay at h0, constants."""
     hs = converge_h(x.detach(), m.detach(), h0, hfact=hfact, periodic=periodic, L=L,
-                    kernel=kernel)
+                    kernel=kernel, solve=solve)
     d, r, eye = _pairs(x, periodic, L)
     # implicit h: one Newton step from h* with F'(h*) held fixed
     rs, drs = _rho_terms(r, hs, m, kernel)
@@ -113,6 +124,8 @@ def forward(x, m, v, u, h0, *, eos_kind, hfact=1.2, cs0=1.0, q_cs=0.25, r_ref=1.
     F = rs - rhoh
     dF = (drs + 3.0 * rhoh / hs).detach()
     h = hs - F / dF
+    if solve is not None:
+        h = torch.where(solve, h, h0)
     rho, drho = _rho_terms(r, h, m, kernel)
     omega = 1.0 + h * drho / (3.0 * rho)
     P, c = eos(x, rho, u, eos_kind, cs0, q_cs, r_ref, gamma)

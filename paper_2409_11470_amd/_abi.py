@@ -80,7 +80,7 @@ def lib():
     L.apr_last_error.argtypes = [_vp]
     L.apr_build_cells.argtypes = [_vp, C.POINTER(CState), _vp]
     L.apr_density.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp]
-    L.apr_forces.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.apr_forces.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.apr_vjp.argtypes = [_vp, C.POINTER(CState)] + [_vp] * 12
     L.apr_bins_init.argtypes = [_vp, C.POINTER(CState), _vp, C.POINTER(Sink), C.c_int32,
                                 C.c_double, C.c_double, C.c_int32]

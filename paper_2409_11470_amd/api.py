@@ -200,10 +200,10 @@ def apr_density(ctx, st, rho, omega, nneigh=None, iters=None):
                                 _ptr(iters)))
 
 
-def apr_forces(ctx, st, rho, omega, ax, ay, az, dudt, vsig=None):
+def apr_forces(ctx, st, rho, omega, ax, ay, az, dudt, vsig=None, npair=None):
     cs = st.cstate()
     ctx.check(lib().apr_forces(ctx.ptr, C.byref(cs), _ptr(rho), _ptr(omega), _ptr(ax), _ptr(ay),
-                               _ptr(az), _ptr(dudt), _ptr(vsig)))
+                               _ptr(az), _ptr(dudt), _ptr(vsig), _ptr(npair)))
 
 
 def apr_vjp(ctx, st, rho, omega, rho_bar=None, h_bar=None, ax_bar=None, ay_bar=None,
@@ -347,11 +347,11 @@ def apr_profile_read(ctx, reset=True):
 
 COUNTER_NAMES = ("noconverge", "periodic_range", "density_multiwindow_cells",
                  "force_multiwindow_cells", "subblock_direct", "density_restage",
-                 "density_passes", "density_windows")
+                 "density_passes", "density_windows", "band_beyond_slack", "edge_tests")
 
 
 def apr_counters(ctx, reset=True):
     """Work counters (see include/apr.h) as a dict; synchronises."""
-    c = (C.c_int64 * 8)()
+    c = (C.c_int64 * len(COUNTER_NAMES))()
     ctx.check(lib().apr_counters(ctx.ptr, c, int(bool(reset))))
     return {k: int(c[i]) for i, k in enumerate(COUNTER_NAMES)}

@@ -245,11 +245,11 @@ int apr_density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneig
 }
 
 int apr_forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-               void *ay, void *az, void *dudt, void *vsig)
+               void *ay, void *az, void *dudt, void *vsig, int32_t *npair)
 {
     int rc = check_state(c, s, true);
     if (rc) return rc;
-    return forces(c, s, rho, omega, ax, ay, az, dudt, vsig);
+    return forces(c, s, rho, omega, ax, ay, az, dudt, vsig, false, nullptr, npair);
 }
 
 int apr_vjp(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
@@ -483,7 +483,7 @@ int apr_counters(apr_ctx *c, int64_t *out, int reset)
     APR_HIP(c, hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * ST_WORDS,
                               hipMemcpyDeviceToHost, c->stream));
     APR_HIP(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 8; ++k) out[k] = k < ST_WORDS ? c->h_status[k] : 0;
+    for (int k = 0; k < APR_COUNTERS_N; ++k) out[k] = k < ST_WORDS ? c->h_status[k] : 0;
     if (reset) {
         int rc = fill_i32(c, c->d_status, 0, ST_WORDS);
         if (rc) return rc;

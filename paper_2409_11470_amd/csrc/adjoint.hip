@@ -26,7 +26,7 @@
 
 namespace apr {
 
-Tree make_tree(apr_ctx *c);
+Tree make_tree(apr_ctx *c, const apr_state *s);
 int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega);
 
 namespace {
@@ -45,6 +45,9 @@ struct VJPStage<double> {
 template <class T, int K>
 struct ForceVJP {
     static constexpr int NS = 4;
+    static constexpr int SK = 2, SC = 3;  // th.w carries the staged slot
+    static constexpr bool EXACT = false;
+    int32_t *npair = nullptr;
     using V = vec4_t<T>;
     const V *pm, *vh, *th, *cot;
     T alpha, beta;
@@ -131,6 +134,9 @@ struct ForceVJP {
 template <class T, int K>
 struct DensVJP {
     static constexpr int NS = 2;
+    static constexpr int SK = 1, SC = 2;  // dv.z carries the staged slot
+    static constexpr bool EXACT = false;
+    int32_t *npair = nullptr;
     using V = vec4_t<T>;
     const V *pm, *dv;  // dv = (c = rhobar/Omega, Dbar, 0, 1/h)
     const double *xb[3], *mb;
@@ -318,7 +324,7 @@ int vjp_t(apr_ctx *c, const apr_state *s, const void *rho, const void *omega,
     const V *pm = (const V *)ws(c, f32 ? "pm32" : "pm64", n * sizeof(V) + 256);
     const V *vh = (const V *)ws(c, f32 ? "vh32" : "vh64", n * sizeof(V) + 256);
     const V *th = (const V *)ws(c, f32 ? "th32" : "th64", n * sizeof(V) + 256);
-    Tree tr = make_tree(c);
+    Tree tr = make_tree(c, s);
     CandList pre;
     rc = cand_pre(c, tr, true, 2.0, &pre);
     if (rc) return rc;

@@ -31,7 +31,10 @@ enum {
     ST_RESTAGE = 5,       // density: searches repeated for a larger radius
     ST_PASSES = 6,        // density: Newton passes summed over cells
     ST_WINDOWS = 7,       // staged windows summed over cells and passes
-    ST_WORDS = 8
+    ST_BAND = 8,          // density targets whose support-test guard band exceeds the
+                          // staging slack (|t|_1 >= 126 R; none expected)
+    ST_EDGE = 9,          // pair tests decided in FP64 inside the guard band
+    ST_WORDS = 10
 };
 
 // A leaf cell or a tree node: centre in FP64 and conservative (rounded-up)
@@ -252,9 +255,10 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
 // this state just ran), so the refit from h is skipped.
 // active (optional): only those targets get their sums (outputs of the
 // others untouched).
+// npair (optional, [n]): pairs per target (b != a, r < 2 max(h_a, h_b)).
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
            void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh = false,
-           const uint8_t *active = nullptr);
+           const uint8_t *active = nullptr, int32_t *npair = nullptr);
 // EOS pack of forces.hip: vh = (v, 1/h), th = (P/(Omega rho^2), 1/(Omega rho), c, 0)
 // into the workspace buffers vh32/th32 (FP32) or vh64/th64 (FP64).
 int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega);

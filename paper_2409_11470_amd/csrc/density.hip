@@ -9,13 +9,19 @@
 //   d2W/dh2 = (12 f + 8 q f' + q^2 f'')/(pi h^5),
 //   h <- h - (F/F') / (1 - F F''/(2 F'^2))   (plain Newton if |F F''/(2 F'^2)| >= 1/2).
 // It stops when |dh| < tol h; the h reported is the one the last sums were
-// taken at.  A Halley step with |dh| < sqrt(tol) h also ends it: its
-// remaining error is of order (dh/h)^3 h, far below tol h, so h + dh is
-// reported without another pass, with rho and the h-derivative sum of Omega
-// carried to it by their Taylor series (rho to second order, errors of order
-// (dh/h)^3 and (dh/h)^2 <= tol) and the neighbour count of the last sums.
-// If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is clamped to
-// [h/2, 2h].
+// taken at.  A Halley step with |dh| < sqrt(tol) h also ends it when the
+// target's own neighbour list covers the new support: its remaining error is
+// of order (dh/h)^3 h, far below tol h, so h + dh is reported without
+// another pass, with rho and the h-derivative sum of Omega carried to it by
+// their Taylor series (rho to second order, errors of order (dh/h)^3 and
+// (dh/h)^2 <= tol) and the neighbour count taken again over the list at
+// h + dh.  If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is
+// clamped to [h/2, 2h].
+//
+// Membership r_ab < 2 h_a is tested in the pair precision and, inside a
+// guard band about the edge, decided again in FP64 on absolute positions
+// (exactly the neighbour export's predicate), so the pairs summed and the
+// count reported are those of the FP64 definition in both forms.
 //
 // Kernel (M4 or Wendland C2, support 2h, a template parameter): W = f(q)/(pi h^3),
 // q = r/h, so dW/dh = -(3f + q f')/(pi h^4).  Sums carry the normalised mass
@@ -74,6 +80,33 @@ struct DensArgs {
     const uint8_t *active;  // targets to solve (null: all); the others keep h, rho, Omega
 };
 
+// A staged density candidate carries its mass 2^-level (an exact power of
+// two, zero mantissa) with a tag in the low 14 mantissa bits: its candidate
+// cell's index in the chunk (8 bits) and its lane in that cell (6 bits).
+// The slot is then cs[sA[ci]] + lane, needed only by the FP64 edge test.
+constexpr uint32_t kTagBits = 14;
+__device__ inline float tag_mass(float m, int ci, int lane)
+{
+    return __int_as_float(__float_as_int(m) | (ci << 6) | lane);
+}
+__device__ inline double tag_mass(double m, int ci, int lane)
+{
+    return __longlong_as_double(__double_as_longlong(m) | (long long)((ci << 6) | lane));
+}
+__device__ inline float untag_mass(float w)
+{
+    return __int_as_float(__float_as_int(w) & ~((1 << kTagBits) - 1));
+}
+__device__ inline double untag_mass(double w)
+{
+    return __longlong_as_double(__double_as_longlong(w) & ~((1ll << kTagBits) - 1));
+}
+__device__ inline int tag_of(float w) { return __float_as_int(w) & ((1 << kTagBits) - 1); }
+__device__ inline int tag_of(double w)
+{
+    return (int)(__double_as_longlong(w) & ((1ll << kTagBits) - 1));
+}
+
 // Per-lane partial sums of one Newton evaluation (kernel K).
 template <class T, int K>
 struct DSum {
@@ -90,10 +123,16 @@ struct DSum {
         cnt = 0;
         dmin = T(3.0e38);
     }
-    __device__ void pair(T dx, T dy, T dz, T m, T R2, T hinv)
+    // wt: the staged mass with its candidate tag; edge(wt) decides membership
+    // in FP64 for pairs inside the guard band |r^2 - R^2| <= band
+    template <class Edge>
+    __device__ void pair(T dx, T dy, T dz, T wt, T R2, T band, T hinv, Edge edge)
     {
         T r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < R2) {
+        bool in = r2 < R2;
+        if (fabs(r2 - R2) <= band) in = edge(wt);
+        if (in) {
+            const T m = untag_mass(wt);
             T r = psqrt(r2);
             const T q = r * hinv;
             T f, df, d2f;
@@ -158,9 +197,12 @@ __device__ inline void count_cands(const vec4_t<T> *pm, const MetaBuf<T> &mb, in
 // Stages the counted candidates with staged offset in [w0, w0 + STAGE):
 // positions in the target cell's frame.  sB holds each candidate cell's
 // first offset.
+// The staged entry: position rounded once from FP64 (stage_pos), the mass
+// tagged with (ci, lane).  The reach test is cand_point's, as in counting, so
+// that the staged set is exactly the counted one.
 template <class T, int STAGE>
-__device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
-                                    const int32_t *sB, int nc, int total,
+__device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<T> *pm,
+                                    const MetaBuf<T> &mb, const int32_t *sB, int nc, int total,
                                     const WaveBoxes<T> &B, int w0, vec4_t<T> *stg)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -171,7 +213,11 @@ __device__ inline void stage_window(const vec4_t<T> *pm, const MetaBuf<T> &mb,
         bool hit = cand_point<T>(pm, mb, ci, lane, B, p);
         uint64_t m = __ballot(hit);
         int off = o0 + __popcll(m & lanemask_lt()) - w0;
-        if (hit && off >= 0 && off < STAGE) stg[off] = p;
+        if (hit && off >= 0 && off < STAGE) {
+            stage_pos<T>(tr, tg, mb.m[ci].wrap, (int64_t)mb.m[ci].b0 + lane, p);
+            p.w = tag_mass(p.w, ci, lane);
+            stg[off] = p;
+        }
     }
 }
 
@@ -189,7 +235,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     __shared__ uint16_t sub[kWaves][STAGE];
     __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
-    __shared__ int s_more;
+    __shared__ int s_more, s_edge;
     __shared__ Walk s_walk;
     __shared__ WaveBoxes<T> s_wb;
     __shared__ double s_Rw[kWaves];  // each wavefront's staged reach
@@ -229,10 +275,20 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     // work counters of the block (thread 0), added once at the end
     int c_restage = 0, c_direct = 0, c_windows = 0, c_passes = 0;
     bool done = !valid;
+    bool recount = false;  // took an accepted step: count again at the new h
     V tp;
     if (valid) tp = a.pm[s0 + t];
     else { tp.x = T(0); tp.y = T(0); tp.z = T(0); tp.w = T(0); }
     uint16_t *mylist = tls[t < kCell ? t : 0];
+    // FP64 decision for a pair inside the guard band: the candidate's slot
+    // from its tag and the chunk's candidate cells, then the exact predicate
+    // at this lane's current h (rare: a few pairs per thousand targets)
+    auto edge = [&](T wt, double hx) -> bool {
+        const int tag = tag_of(wt);
+        const int64_t b = (int64_t)tr.cs[sA[tag >> 6]] + (tag & 63);
+        atomicAdd(&s_edge, 1);
+        return inside_exact(r2_exact(tr, s0 + t, b), hx);
+    };
 
     // staged reach of each wavefront's targets (2 sigma of its largest h) and
     // of the whole cell (the tree walk's radius)
@@ -244,12 +300,14 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         __syncthreads();
         R = 0.0;
         for (int k = 0; k < kWaves; ++k) R = fmax(R, 2.0 * (double)kSigma * s_red[k]);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             for (int k = 0; k < kWaves; ++k) {
                 double rw = 2.0 * (double)kSigma * s_red[k];
                 s_Rw[k] = rw;
                 s_wb.R2[k] = 16 * k < cnt ? (T)(rw * rw) : T(-1);
             }
+            s_edge = 0;
+        }
     }
 
     // Every new search follows a Newton step that grew some h, and every
@@ -315,7 +373,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
                 lists = false;
                 if (nwin == 1) {
-                    stage_window<T, STAGE>(a.pm, s_lm.meta, sB, nc, total, s_wb, 0, stg);
+                    stage_window<T, STAGE>(tr, tg, a.pm, s_lm.meta, sB, nc, total, s_wb, 0, stg);
                     __syncthreads();
                 }
             }
@@ -329,7 +387,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     __syncthreads();
                     load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
                     __syncthreads();
-                    stage_window<T, STAGE>(a.pm, s_lm.meta, sB, nc, total, s_wb, w0, stg);
+                    stage_window<T, STAGE>(tr, tg, a.pm, s_lm.meta, sB, nc, total, s_wb, w0, stg);
                     __syncthreads();
                 }
                 if (!wave_busy) continue;
@@ -359,24 +417,27 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 T hf = (T)h;
                 T hinv = T(1) / hf;
                 T R2 = T(4) * hf * hf;
+                const T band = edge_band<T>(tp, T(2) * hf);
+                const double hx = (double)hf;  // the h these sums are reported at
+                auto ed = [&](T wt) { return edge(wt, hx); };
                 if (tlen <= kDTCap) {
                     // two entries per step (same order per lane), both reads in flight
                     int k = j;
                     for (; k + kLanes < tlen; k += 2 * kLanes) {
                         const int e0 = mylist[k], e1 = mylist[k + kLanes];
                         const V p0 = lds_ld4<T>(&stg[e0]), p1 = lds_ld4<T>(&stg[e1]);
-                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2, hinv);
-                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2, hinv);
+                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2, band, hinv, ed);
+                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2, band, hinv, ed);
                     }
                     if (k < tlen) {
                         const V p = lds_ld4<T>(&stg[mylist[k]]);
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, band, hinv, ed);
                     }
                 } else {
                     // own list overflowed: walk the whole window
                     for (int k = j; k < nstg; k += kLanes) {
                         V p = stg[k];
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, hinv);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, band, hinv, ed);
                     }
                 }
             }
@@ -396,18 +457,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         int nn = cnt4 & 0xffff, nzero = cnt4 >> 16;
         T dmin = min4(S.dmin);
         if (!done) {
-            double W = S.w.value(), D = S.d.value();
-            double hh = (double)(T)h;
-            double hi = 1.0 / hh, hi3 = hi * hi * hi;
-            double ma = a.m0 * (double)tp.w;
-            double rhos = (a.m0 / kPi) * W * hi3;
-            double drho = -(a.m0 / kPi) * D * hi3 * hi;
-            double rhoh = ma * (a.hfact * a.hfact * a.hfact) * hi3;
-            double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
+            const double W = S.w.value(), D = S.d.value();
+            const double hh = (double)(T)h;
+            const double hi = 1.0 / hh, c0 = (a.m0 / kPi) * hi * hi * hi;
+            const double ma = a.m0 * (double)tp.w;
+            const double rhos = c0 * W;                      // rho_sum(hh)
+            const double drho = -c0 * hi * D;                // d rho_sum / dh
+            const double d2rho = c0 * hi * hi * (double)S.k; // d2 rho_sum / dh2
+            const double rhoh = ma * (a.hfact * a.hfact * a.hfact) * hi * hi * hi;
+            const double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
             double hn;
             bool halley = false;
             if (dF > 0.0) {
-                const double d2rho = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
                 const double d2F = d2rho - 12.0 * rhoh * hi * hi;
                 const double x = F * d2F / (2.0 * dF * dF);
                 halley = fabs(x) < 0.5;
@@ -418,26 +479,25 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             hn = fmin(fmax(hn, 0.5 * hh), 2.0 * hh);
             const double dh = hn - hh;
             bool conv = fabs(dh) < a.tol * hh;
-            const bool take = !conv && halley && fabs(dh) < a.tol_take * hh;
+            // an accepted step needs this target's own list, valid for another
+            // pass, to hold the new support (with the guard band's slack)
+            const bool take = !conv && halley && fabs(dh) < a.tol_take * hh && lists &&
+                              tlen <= kDTCap && 2.0 * hn * (1.0 + 1.0 / 1024) < (double)Rt;
             conv = conv || take;
             itc += 1;
             if (conv || itc >= a.max_iter) {
                 done = true;
+                recount = take;
                 h = take ? hn : hh;
                 if (j == 0) {
-                    Out o;
-                    o.rho = (T)rhos;
-                    o.om = (T)(1.0 - D / (3.0 * W));
                     // The accepted step carries rho (second order) and Omega =
-                    // 1 + h rho'/(3 rho) (first order) from hh to hh + dh, here
-                    // in registers (three more values per target in LDS would
-                    // leave the FP32 form room for only three workgroups per CU)
-                    if (take) {
-                        const double d2 = (a.m0 / kPi) * (double)S.k * hi3 * hi * hi;
-                        o.rho = (T)(rhos + dh * (drho + 0.5 * dh * d2));
-                        o.om = (T)(1.0 - D / (3.0 * W) +
-                                   (dh / 3.0) * (drho + hh * (d2 - drho * drho / rhos)) / rhos);
-                    }
+                    // 1 + h rho'/(3 rho) (first order) from hh to hh + dh
+                    const double om = 1.0 - D / (3.0 * W);
+                    Out o;
+                    o.rho = (T)(take ? rhos + dh * (drho + 0.5 * dh * d2rho) : rhos);
+                    o.om = (T)(take ? om + (dh / 3.0) * (drho + hh * (d2rho - drho * drho / rhos)) /
+                                               rhos
+                                    : om);
                     o.dnn = nzero >= 2 ? T(0)
                                        : (dmin >= T(3.0e38) ? T(__builtin_huge_val()) : dmin);
                     o.nn = conv ? nn : -1 - nn;
@@ -449,6 +509,27 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 if (2.0 * hn > (double)Rt) lists = false;   // own list too short now
                 if (2.0 * hn > s_Rw[w]) needR = 2.0 * (double)kSigma * hn;
             }
+        }
+        // ---- a target that took its last step counts its neighbours again at
+        // the new h, over its own list (still staged: nothing is restaged
+        // before the block-wide step below)
+        if (__any(recount)) {
+            const T hf = (T)h;
+            const T R2 = T(4) * hf * hf;
+            const T band = edge_band<T>(tp, T(2) * hf);
+            const int len = recount ? tlen : 0;
+            int c = 0;
+            for (int k = j; k < len; k += kLanes) {
+                const V p = lds_ld4<T>(&stg[mylist[k]]);
+                const T dx = tp.x - p.x, dy = tp.y - p.y, dz = tp.z - p.z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                bool in = r2 < R2;
+                if (fabs(r2 - R2) <= band) in = edge(p.w, h);
+                c += in ? 1 : 0;
+            }
+            c = sum4(c);
+            if (recount && j == 0) s_out[t].nn = c;
+            recount = false;
         }
         // ---- block-wide: anything pending?  a larger search radius needed?
         {
@@ -499,8 +580,13 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         if (a.dnn) a.dnn[i] = o.dnn;
         if (o.nn < 0) atomicAdd(&a.status[ST_NOCONV], 1);
         if (a.hlim > 0.0 && !(h < a.hlim)) atomicOr(&a.status[ST_RANGE], 1);
+        // the staging slack covers the guard band while |t|_1 < 126 R
+        if ((double)(fabs(tp.x) + fabs(tp.y) + fabs(tp.z)) >= 252.0 * h)
+            atomicAdd(&a.status[ST_BAND], 1);
     }
+    __syncthreads();  // s_edge complete
     if (threadIdx.x == 0) {
+        if (s_edge) atomicAdd(&a.status[ST_EDGE], s_edge);
         if (c_restage) atomicAdd(&a.status[ST_RESTAGE], c_restage);
         if (c_direct) atomicAdd(&a.status[ST_DENS_DIRECT], c_direct);
         atomicAdd(&a.status[ST_WINDOWS], c_windows);
@@ -566,7 +652,7 @@ void launch_density(apr_ctx *c, const DensArgs<T> &a, int64_t grid, int tok)
 
 }  // namespace
 
-Tree make_tree(apr_ctx *c)
+Tree make_tree(apr_ctx *c, const apr_state *s)
 {
     Tree t;
     t.hdr = cell_hdr(c);
@@ -574,6 +660,10 @@ Tree make_tree(apr_ctx *c)
     for (int k = 0; k <= kMaxLev; ++k) t.lev[k] = k <= c->nlev ? cell_level(c, k) : nullptr;
     t.nlev = c->nlev;
     t.box = make_box(c->p);
+    t.px = s->x;
+    t.py = s->y;
+    t.pz = s->z;
+    t.ph = s->h;
     return t;
 }
 
@@ -585,7 +675,7 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
     const int64_t grid = c->node_grid[0];
     float *hmax_new = wsa<float>(c, "hmax_new", (size_t)c->node_cap[0]);
     int32_t *st = c->d_status;
-    Tree tr = make_tree(c);
+    Tree tr = make_tree(c, s);
     // periodic: 2 h < box / 4 on every axis
     double hlim = 0.0;
     if (c->p.periodic) {

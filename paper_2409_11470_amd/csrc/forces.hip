@@ -16,7 +16,7 @@
 
 namespace apr {
 
-Tree make_tree(apr_ctx *c);
+Tree make_tree(apr_ctx *c, const apr_state *s);
 
 namespace {
 
@@ -79,10 +79,13 @@ __device__ inline T kern_df(T q)
 template <class T, int K>
 struct ForceOp {
     static constexpr int NS = 3;
+    static constexpr int SK = 2, SC = 3;  // th.w carries the staged slot
+    static constexpr bool EXACT = true;
     using V = vec4_t<T>;
     const V *pm, *vh, *th;
     T *ax, *ay, *az, *dudt, *vsig;
     float *divv;
+    int32_t *npair = nullptr;
     const uint8_t *act = nullptr;
     double m0;
     T alpha, beta;
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kSearchThreads, kBlocksPerCU<T>) void k_forces(Tree
 template <class T, int K>
 void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
                    int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv,
-                   const uint8_t *active)
+                   const uint8_t *active, int32_t *npair)
 {
     using V = vec4_t<T>;
     const bool f32 = std::is_same<T, float>::value;
@@ -179,6 +182,7 @@ void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, i
     op.vsig = (T *)vsig;
     op.divv = divv;
     op.act = active;
+    op.npair = npair;
     op.m0 = c->p.m0;
     op.alpha = (T)c->p.av_alpha;
     op.beta = (T)c->p.av_beta;
@@ -192,12 +196,14 @@ void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, i
 template <class T>
 void launch_forces(apr_ctx *c, const Tree &tr, const CandList &pre, int64_t n, int64_t grid,
                    int tok, void *ax, void *ay, void *az, void *dudt, void *vsig, float *divv,
-                   const uint8_t *active)
+                   const uint8_t *active, int32_t *npair)
 {
     if (c->p.kernel == APR_KERNEL_WC2)
-        launch_forces<T, kWC2>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
+        launch_forces<T, kWC2>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active,
+                                npair);
     else
-        launch_forces<T, kM4>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
+        launch_forces<T, kM4>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active,
+                               npair);
 }
 
 }  // namespace
@@ -226,7 +232,8 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 }
 
 int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, void *ax,
-           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh, const uint8_t *active)
+           void *ay, void *az, void *dudt, void *vsig, bool hmax_fresh, const uint8_t *active,
+           int32_t *npair)
 {
     if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "apr_build_cells first");
     if (!rho || !omega || !ax || !ay || !az || !dudt)
@@ -240,7 +247,7 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     if (rc) return rc;
     rc = eos_pack(c, s, rho, omega);
     if (rc) return rc;
-    Tree tr = make_tree(c);
+    Tree tr = make_tree(c, s);
     float *divv = wsa<float>(c, "divv", (size_t)n);
     if (!divv) return fail(c, APR_ERR_HIP, "workspace");
     CandList pre;
@@ -248,9 +255,11 @@ int forces(apr_ctx *c, const apr_state *s, const void *rho, const void *omega, v
     if (rc) return rc;
     int tok = prof_begin(c, APR_PROF_FORCES);
     if (p.precision == APR_FP32)
-        launch_forces<float>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
+        launch_forces<float>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active,
+                             npair);
     else
-        launch_forces<double>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active);
+        launch_forces<double>(c, tr, pre, n, grid, tok, ax, ay, az, dudt, vsig, divv, active,
+                              npair);
     APR_LAUNCHED(c);
     c->force_n = n;
     c->divv_n = n;

@@ -21,11 +21,43 @@
 //   void finish(Acc &, int64_t i, const V *own, bool write) const;
 //     finish reduces over the target's 4 lanes (all lanes call it) and, if
 //     write, stores the target's results.
+//   static constexpr int SK, SC;        a staged component the pair sums never
+//                                       read (array SK, component SC = 0..3
+//                                       for x..w): it carries the candidate's
+//                                       slot for the exact edge test
+//   static constexpr bool EXACT;        with EXACT, membership is
+//                                       r < 2 max(h_a, h_b) of the FP64
+//                                       definition: the pair loop tests
+//                                       r^2 / h^2 < 4 for both supports in the
+//                                       pair precision and decides pairs
+//                                       inside the guard band of either edge
+//                                       (kBand) in FP64 on absolute positions;
+//                                       without it the pair-precision test
+//                                       stands (the adjoint: its terms vanish
+//                                       at the edge with their derivatives)
+//   int32_t *npair;                     optional (EXACT): pairs per target
+//                                       (b != a in the support, r = 0 pairs
+//                                       included)
+// Staged positions are rounded once from FP64 (stage_pos).
 #pragma once
 
 #include "search.hpp"
 
 namespace apr {
+
+template <class T>
+__device__ inline void set_comp(vec4_t<T> &v, int c, T x)
+{
+    if (c == 0) v.x = x;
+    else if (c == 1) v.y = x;
+    else if (c == 2) v.z = x;
+    else v.w = x;
+}
+template <class T>
+__device__ inline T get_comp(const vec4_t<T> &v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
 
 template <class T, class OP, int STAGE>
 __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const CandList &pre,
@@ -39,7 +71,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     __shared__ ListsMeta<T, kTCap> s_lm;  // per-target lists, or candidates' metadata
     uint16_t(*tls)[kTCap] = s_lm.tls;
     const MetaBuf<T> &mb = s_lm.meta;
-    __shared__ int s_ncand, s_total, s_more, s_tlen[kCell];
+    __shared__ int s_ncand, s_total, s_more, s_tlen[kCell], s_edge;
     __shared__ Walk s_walk;
 
     const Geo tg = tr.lev[0][cell];
@@ -69,6 +101,13 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     op.init(acc, own);
     const bool wave_busy = __any(valid);
     const T ra = valid ? T(2) / own[0].w : T(0);
+    // guard bands of r^2/h_a^2 and r^2/h_b^2 about 4: kBand R (mt + 2R) / h^2
+    // with R = 2h, i.e. kBand (8 + 2 mt / h)
+    const T mt = fabs(own[0].x) + fabs(own[0].y) + fabs(own[0].z);
+    const T band_a = kBand<T> * (T(8) + T(2) * mt * own[0].w);
+    const T band_b0 = kBand<T> * T(8), band_b1 = kBand<T> * T(2) * mt;
+    int npairs = 0;
+    if (threadIdx.x == 0) s_edge = 0;  // read after the loop's barriers
     // staged: candidates within max(R, 2 h_b) of the target cell's box
     const T ex = (T)tg.ex, ey = (T)tg.ey, ez = (T)tg.ez;
     const T R2c = (T)(R * R);
@@ -163,10 +202,16 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                 uint64_t m = __ballot(hit);
                 int off = o0 + __popcll(m & lanemask_lt()) - w0;
                 if (hit && off >= 0 && off < STAGE) {
-                    stg[0][off] = p;
-                    stg[1][off] = v;
+                    const int64_t b = (int64_t)b0 + lane;
+                    stage_pos<T>(tr, tg, x.wrap, b, p);
+                    V e[NS];
+                    e[0] = p;
+                    e[1] = v;
 #pragma unroll
-                    for (int k = 2; k < NS; ++k) stg[k][off] = op.load(k, b0 + lane);
+                    for (int k = 2; k < NS; ++k) e[k] = op.load(k, b);
+                    set_comp<T>(e[OP::SK], OP::SC, slot_bits(T(0), b));
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) stg[k][off] = e[k];
                 }
             }
             __syncthreads();
@@ -190,7 +235,9 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                     T hb = p.w;
                     T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
                     T r2 = dx * dx + dy * dy + dz * dz;
-                    return (r2 < rk * rk) | (r2 * hb * hb < T(4));
+                    // with the slack, every pair inside either guard band is listed
+                    return (r2 < rk * rk * kReachSlack<T>) |
+                           (r2 * hb * hb < T(4) * kReachSlack<T>);
                 });
             const int tlen = s_tlen[t < kCell ? t : 0];
             if (!valid) continue;
@@ -205,14 +252,35 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
                 T dx = own[0].x - nb[0].x, dy = own[0].y - nb[0].y, dz = own[0].z - nb[0].z;
                 T r2 = dx * dx + dy * dy + dz * dz;
                 T hb = nb[0].w;
-                if (((r2 * ha_inv2 < T(4)) | (r2 * hb * hb < T(4))) & (r2 > T(0)))
-                    op.pair(acc, own, dx, dy, dz, r2, nb);
+                const T ta = r2 * ha_inv2, tb = r2 * hb * hb;
+                bool in = (ta < T(4)) | (tb < T(4));
+                if (OP::EXACT) {
+                    const int64_t slot_b = slot_of(get_comp<T>(nb[OP::SK], OP::SC));
+                    const int64_t slot_a = (int64_t)s0 + t;
+                    if ((fabs(ta - T(4)) <= band_a) |
+                        (fabs(tb - T(4)) <= band_b0 + band_b1 * hb)) {
+                        // inside a guard band: the FP64 decision (rare)
+                        atomicAdd(&s_edge, 1);
+                        const double r2e = r2_exact(tr, slot_a, slot_b);
+                        in = inside_exact(r2e, tr.ph[slot_a]) | inside_exact(r2e, tr.ph[slot_b]);
+                    }
+                    npairs += (in & (slot_b != slot_a)) ? 1 : 0;
+                }
+                if (in & (r2 > T(0))) op.pair(acc, own, dx, dy, dz, r2, nb);
             }
         }
         if (!more) break;
     }
     op.finish(acc, s0 + t, own, valid && j == 0);
-    if (threadIdx.x == 0 && multiwin && st_word >= 0) atomicAdd(&status[st_word], 1);
+    if (OP::EXACT) {
+        npairs = sum4(npairs);
+        if (op.npair && valid && j == 0) op.npair[s0 + t] = npairs;
+    }
+    __syncthreads();  // s_edge complete
+    if (threadIdx.x == 0) {
+        if (multiwin && st_word >= 0) atomicAdd(&status[st_word], 1);
+        if (s_edge) atomicAdd(&status[ST_EDGE], s_edge);
+    }
 }
 
 // One workgroup per target cell, cells [0, grid) with the grid from the

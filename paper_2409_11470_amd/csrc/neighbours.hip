@@ -8,7 +8,7 @@
 
 namespace apr {
 
-Tree make_tree(apr_ctx *c);
+Tree make_tree(apr_ctx *c, const apr_state *s);
 
 namespace {
 
@@ -93,7 +93,7 @@ int neighbours(apr_ctx *c, const apr_state *s, const double *h, int mode, int64_
     int64_t n = s->n;
     int rc = cells_hmax_from(c, h, n);
     if (rc) return rc;
-    Tree tr = make_tree(c);
+    Tree tr = make_tree(c, s);
     unsigned nb = (unsigned)c->node_grid[0];
     if (!list) {
         hipLaunchKernelGGL(k_neigh, dim3(nb), dim3(64), 0, c->stream, tr, s->x, s->y, s->z, h,

@@ -19,7 +19,7 @@
 
 namespace apr {
 
-Tree make_tree(apr_ctx *c);
+Tree make_tree(apr_ctx *c, const apr_state *s);
 
 namespace {
 
@@ -269,8 +269,8 @@ int relax(apr_ctx *c, apr_state *s, apr_ctx *rc, const apr_state *ref, const voi
         r = forces(c, s, rho, om, an[0], an[1], an[2], an[3], nullptr);
         if (r) return r;
         InterpArgs ia;
-        ia.src = make_tree(rc);
-        ia.tgt = make_tree(c);
+        ia.src = make_tree(rc, ref);
+        ia.tgt = make_tree(c, s);
         ia.x = s->x;
         ia.y = s->y;
         ia.z = s->z;

@@ -9,9 +9,10 @@
 //     resumes: the number of candidate cells is unbounded.
 //  2. stage: the candidate cells' particles that can interact with the target
 //     cell are copied to LDS, with positions moved into the target cell's
-//     frame (FP64 cell-centre difference, minimum image, rounded once to the
-//     pair precision).  Counted per candidate cell first, then written at the
-//     prefix offsets, so the staged order is the candidate order (fixed).
+//     frame (FP64 absolute position minus the target cell's centre, minimum
+//     image of the cell pair, rounded once to the pair precision).  Counted
+//     per candidate cell first, then written at the prefix offsets, so the
+//     staged order is the candidate order (fixed).
 //  3. sub-block lists: the 64 targets form 16 sub-blocks of 4; a wavefront
 //     serves one sub-block at a time with 16 lanes per target, and the staged
 //     candidates that can reach the sub-block are listed (u16 LDS indices).
@@ -58,7 +59,71 @@ struct Tree {
     const Geo *lev[kMaxLev + 1]; // lev[0] = cells
     int nlev;
     Box box;
+    // the state the cells were built on (cell order): FP64 positions for the
+    // staged coordinates and, with ph, the exact support test near its edge
+    const double *px, *py, *pz, *ph;
 };
+
+// ------------------------------------------------------------ exact support
+// Membership in a support is decided like the FP64 neighbour export: the
+// minimum-image separation of the absolute positions, r^2 = dx*dx + dy*dy +
+// dz*dz summed left to right with every product and sum rounded on its own
+// (no contraction), tested strictly against (2 h)^2.  The pair loops test in
+// the pair precision on cell-frame coordinates and take this FP64 decision
+// only inside a guard band about the edge, where the rounding of the
+// pair-precision test could decide otherwise.
+__device__ inline double sep_exact(double a, double b, double L, int periodic)
+{
+#pragma clang fp contract(off)
+    double d = a - b;
+    if (periodic) {
+        if (d > 0.5 * L) d -= L;
+        else if (d < -0.5 * L) d += L;
+    }
+    return d;
+}
+
+__device__ inline double r2_exact(const Tree &t, int64_t a, int64_t b)
+{
+#pragma clang fp contract(off)
+    double dx = sep_exact(t.px[a], t.px[b], t.box.L[0], t.box.periodic);
+    double dy = sep_exact(t.py[a], t.py[b], t.box.L[1], t.box.periodic);
+    double dz = sep_exact(t.pz[a], t.pz[b], t.box.L[2], t.box.periodic);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// r_ab^2 < (2 h)^2, h in FP64, evaluated exactly as above.
+__device__ inline bool inside_exact(double r2, double h)
+{
+#pragma clang fp contract(off)
+    double R = 2.0 * h;
+    return r2 < R * R;
+}
+
+// Guard band of the pair-precision support test, in units of r^2: for a
+// target at cell-frame position t (|t|_1 = mt) and support radius R,
+//   band = kBand * R * (mt + 2 R).
+// The staged coordinates are rounded once from FP64 (relative error 2^-24 in
+// FP32), so a separation near R carries an error below about
+// 2^-23 (|t|_inf + R) per component and r^2 one below about
+// 2^-21 R (mt + R); kBand leaves a factor of 8 over that.  The FP64 form
+// rounds the same way at 2^-53 (and at most 2^-53 L more in a periodic
+// image), covered by its kBand with the same margin.
+template <class T>
+constexpr T kBand = sizeof(T) == 4 ? T(1.0 / (1 << 18)) : T(1.0 / (1ll << 44));
+
+template <class T>
+__device__ inline T edge_band(const vec4_t<T> &t, T R)
+{
+    return kBand<T> * R * (fabs(t.x) + fabs(t.y) + fabs(t.z) + T(2) * R);
+}
+
+// The slot of a staged candidate rides in a component the pair sums never
+// read (bit pattern of an int32 or int64).
+__device__ inline float slot_bits(float, int64_t i) { return __int_as_float((int32_t)i); }
+__device__ inline double slot_bits(double, int64_t i) { return __longlong_as_double(i); }
+__device__ inline int64_t slot_of(float v) { return (int64_t)__float_as_int(v); }
+__device__ inline int64_t slot_of(double v) { return (int64_t)__double_as_longlong(v); }
 
 // Appends the lanes' hits to a per-group (16-lane) list; len is group-uniform.
 __device__ inline void group_append(bool hit, uint16_t e, uint16_t *list, int &len)
@@ -355,6 +420,8 @@ template <class T>
 struct CandMeta {
     T sx, sy, sz;
     int32_t b0;
+    uint32_t wrap;  // periodic image of the candidate cell, 2 bits per axis:
+                    // 1 adds the box length, 2 subtracts it
 };
 template <class T>
 struct MetaBuf {
@@ -379,16 +446,38 @@ __device__ inline void load_meta(const Tree &tr, const Geo &tg, const int32_t *s
     for (int ci = threadIdx.x; ci < nc; ci += kSearchThreads) {
         int cc = sA[ci];
         int32_t b0 = tr.cs[cc], b1 = tr.cs[cc + 1];
+        const Geo g = tr.lev[0][cc];
         double sh[3];
-        cell_shift(tr.lev[0][cc], tg, tr.box, sh);
+        cell_shift(g, tg, tr.box, sh);
+        const double raw[3] = {g.cx - tg.cx, g.cy - tg.cy, g.cz - tg.cz};
         CandMeta<T> x;
         x.sx = (T)sh[0];
         x.sy = (T)sh[1];
         x.sz = (T)sh[2];
         x.b0 = b0;
+        x.wrap = 0;
+        for (int k = 0; k < 3; ++k)
+            x.wrap |= (sh[k] > raw[k] ? 1u : (sh[k] < raw[k] ? 2u : 0u)) << (2 * k);
         mb->m[ci] = x;
         mb->bn[ci] = (uint8_t)(b1 - b0);
     }
+}
+
+// Position of candidate particle b in the target cell's frame (centre tg),
+// rounded once from FP64: (x_b + image shift) - c.
+template <class T>
+__device__ inline void stage_pos(const Tree &tr, const Geo &tg, uint32_t wrap, int64_t b,
+                                 vec4_t<T> &p)
+{
+#pragma clang fp contract(off)
+    const Box &bx = tr.box;
+    auto img = [&](double v, int k) {
+        uint32_t c = (wrap >> (2 * k)) & 3u;
+        return c == 1u ? v + bx.L[k] : (c == 2u ? v - bx.L[k] : v);
+    };
+    p.x = (T)(img(tr.px[b], 0) - tg.cx);
+    p.y = (T)(img(tr.py[b], 1) - tg.cy);
+    p.z = (T)(img(tr.pz[b], 2) - tg.cz);
 }
 
 // One staged entry as a single vector read: the pair loops test the
@@ -410,8 +499,11 @@ __device__ inline vec4_t<T> lds_ld4(const vec4_t<T> *p)
 // Staging and the per-block box tests keep a relative slack over the exact
 // criteria: a candidate that the exact per-target test accepts must pass them
 // whatever the rounding of the (differently grouped) distance sums.
+// The slack also covers the guard band of the support test (kBand) for
+// targets within 126 R of their cell's centre (|t|_1 < 126 R); the density
+// kernel counts targets beyond that (ST_BAND).
 template <class T>
-constexpr T kReachSlack = T(1) + T(1.0 / (1 << 20));
+constexpr T kReachSlack = T(1) + T(1.0 / (1 << 10));
 
 // Square root and reciprocal square root in the pair precision: the FP32
 // form uses the hardware v_sqrt_f32 / v_rsq_f32 (about 1 ulp), the FP64 form

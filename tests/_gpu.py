@@ -6,6 +6,7 @@ from scipy.spatial import cKDTree
 
 import oracle
 import paper_2409_11470_amd as A
+from _balls import dependency_ball, oracle_grads
 
 
 def params_for(p, precision, tol=None, **kw):
@@ -173,3 +174,83 @@ def oracle_balls(st, p, nballs, ntarget, seed, tol=1e-12, forces=True, safety=1.
                       alpha=p.get("alpha", 1.0), beta=p.get("beta", 2.0), targets=loc[Tg],
                       **{k: v for k, v in kw.items() if k != "hfact"})
     return Tg, dens, f
+
+
+def gpu_grads(st, p, prec, cot, tol=None):
+    """apr_sums (forward on the GPU, backward by apr_vjp) on the whole state
+    with cotangents cot (as for oracle_grads); returns dL/dx [n, 3], dL/dm [n]
+    in the order of st."""
+    ctx = A.Context(params_for(p, prec, tol=tol))
+    ds = A.DeviceState.from_numpy(st)
+    x = ds["x"].clone().requires_grad_(True)
+    y = ds["y"].clone().requires_grad_(True)
+    z = ds["z"].clone().requires_grad_(True)
+    m = (p["m0"] * torch.pow(2.0, -ds["level"].double())).requires_grad_(True)
+    rho, h, ax, ay, az, du = A.apr_sums(ctx, ds, x, y, z, m)
+    d = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
+    loss = ((d(cot["rho"]) * rho.double()).sum() + (d(cot["h"]) * h.double()).sum()
+            + (d(cot["a"][:, 0]) * ax.double()).sum() + (d(cot["a"][:, 1]) * ay.double()).sum()
+            + (d(cot["a"][:, 2]) * az.double()).sum() + (d(cot["du"]) * du.double()).sum())
+    loss.backward()
+    gx = torch.stack([x.grad, y.grad, z.grad], 1).cpu().numpy()
+    gm = m.grad.cpu().numpy()
+    del ctx, ds, x, y, z, m, rho, h, ax, ay, az, du, loss
+    torch.cuda.empty_cache()
+    return gx, gm
+
+
+_BALL_CACHE = {}
+
+
+def ball_vjp_check(key, st, p, prec, centre, ntarget=16, seed=0, gtol=None):
+    """Sampled-ball parity of the adjoint on a large set: seeded N(0,1)
+    cotangents on the rho, h, a and du/dt of the ntarget particles nearest to
+    particle `centre` (scaled by the size of each quantity there, from the C
+    oracle, so that no term hides the others) and zero elsewhere; the GPU's
+    dL/dx and dL/dm over the whole set against torch autograd of the dense
+    FP64 oracle solved on the dependency ball alone (dependency_ball).
+    Gradients must vanish outside the ball and match inside it, relative to
+    their max-norm, within gtol.  The oracle's side is cached per key (it does
+    not depend on the form).  Returns the two relative errors."""
+    n = st["x"].shape[0]
+    if key not in _BALL_CACHE:
+        T, S, solve, hS = dependency_ball(st, p, centre, ntarget)
+        sub = {k: st[k][S] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "level")}
+        sub["h"] = hS
+        ti = np.searchsorted(S, T)
+        # sizes of the targets' rho, a, du/dt from the C oracle on the ball
+        d = oracle.density(sub["x"], sub["y"], sub["z"], sub["level"], hS[ti], m0=p["m0"],
+                           hfact=p.get("hfact", 1.2), tol=1e-14, max_iter=100,
+                           periodic=bool(p.get("periodic", False)), lo=p.get("lo", (0, 0, 0)),
+                           hi=p.get("hi", (1, 1, 1)), targets=ti, kernel=int(p.get("kernel", 0)))
+        hh, rr, oo = hS.copy(), np.ones(S.size), np.ones(S.size)
+        dn = oracle.density(sub["x"], sub["y"], sub["z"], sub["level"], hS[solve], m0=p["m0"],
+                            hfact=p.get("hfact", 1.2), tol=1e-14, max_iter=100,
+                            periodic=bool(p.get("periodic", False)),
+                            lo=p.get("lo", (0, 0, 0)), hi=p.get("hi", (1, 1, 1)),
+                            targets=np.nonzero(solve)[0], kernel=int(p.get("kernel", 0)))
+        hh[solve], rr[solve], oo[solve] = dn["h"], dn["rho"], dn["omega"]
+        f = oracle_forces(sub, p, hh, rr, oo, targets=ti)
+        rng = np.random.default_rng(seed)
+        cs = dict(rho=np.zeros(S.size), h=np.zeros(S.size), a=np.zeros((S.size, 3)),
+                  du=np.zeros(S.size))
+        amag = np.sqrt(f["ax"] ** 2 + f["ay"] ** 2 + f["az"] ** 2)
+        cs["rho"][ti] = rng.normal(size=T.size) / d["rho"]
+        cs["h"][ti] = rng.normal(size=T.size) / d["h"]
+        cs["a"][ti] = rng.normal(size=(T.size, 3)) / np.maximum(amag, 1e-300)[:, None]
+        cs["du"][ti] = rng.normal(size=T.size) / np.maximum(np.abs(f["dudt"]), 1e-300)
+        gx, gm = oracle_grads(sub, p, cs, solve=solve)
+        cot = {k: np.zeros((n,) + v.shape[1:]) for k, v in cs.items()}
+        for k in cot:
+            cot[k][S] = cs[k]
+        _BALL_CACHE[key] = (T, S, cot, gx, gm)
+    T, S, cot, ox, om_ = _BALL_CACHE[key]
+    gx, gm = gpu_grads(st, p, prec, cot)
+    outside = np.ones(n, bool)
+    outside[S] = False
+    assert not np.any(gx[outside]) and not np.any(gm[outside]), "gradient outside the ball"
+    ex = float(np.max(np.abs(gx[S] - ox)) / np.max(np.abs(ox)))
+    em = float(np.max(np.abs(gm[S] - om_)) / np.max(np.abs(om_)))
+    if gtol is not None:
+        assert ex < gtol and em < gtol, (ex, em, T.size, S.size)
+    return ex, em

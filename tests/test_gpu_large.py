@@ -190,3 +190,18 @@ def test_refine_box_split_separation_gradient(prec):
     an = float(s.grad)
     print(f"full-size r_sep gradient {prec}: {an:.10e} fd {fd:.10e}")
     assert abs(an - fd) < (1e-4 if prec == "fp64" else 1e-3) * abs(fd), (an, fd)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_circumbinary_8M_vjp_sampled(cb_disc, prec, level):
+    # the adjoint on the 8M disc: one ball centred on a particle of each level
+    # (masses m, m/2, m/4), cotangents on its 16 targets, gradients over all
+    # 8M particles against the dense gradient oracle on the ball's dependency
+    # set; gates 1e-6 (FP64) and 1e-3 (FP32) of the max-norm
+    from _gpu import ball_vjp_check
+    st, p = cb_disc
+    rng = np.random.default_rng(2409114705 + level)
+    centre = int(rng.choice(np.nonzero(st["level"] == level)[0]))
+    ball_vjp_check(("circumbinary", level), st, p, prec, centre, seed=level,
+                   gtol={"fp64": 1e-6, "fp32": 1e-3}[prec])

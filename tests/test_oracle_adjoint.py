@@ -115,3 +115,43 @@ def test_mass_gradient_single_particle_direction(kern):
     W0 = f0 / (np.pi * h[0].item() ** 3)
     r0, m0, o0 = rho[0].item(), m[0], om[0].item()
     assert abs(g[0].item() - (r0 / m0 + (W0 - r0 / m0) / o0)) < 1e-9 * abs(r0 / m0)
+
+
+def test_subset_solve_gives_the_full_gradient():
+    # The dense oracle on a dependency ball alone (targets T, their pair
+    # partners N1 solving the h-rho relation, the sources N2 of N1's
+    # densities holding their converged h) gives the gradient of a loss on
+    # T's rho, h, a and du/dt exactly as the dense oracle on the whole set:
+    # nothing outside the ball enters the loss.
+    from _balls import dependency_ball, oracle_grads
+    st, dx = W.random_cluster(1331, seed_k=310, levels=(0, 1), vscale=0.4)
+    n = st["x"].shape[0]
+    p = dict(m0=1.0, eos=2, gamma=G, hfact=1.2, alpha=1.0, beta=2.0, periodic=False,
+             lo=(-1.0, -1.0, -1.0), hi=(3.0, 3.0, 3.0))
+    pos = np.stack([st["x"], st["y"], st["z"]], 1)
+    centre = int(np.argmin(((pos - pos.mean(0)) ** 2).sum(1)))
+    T, S, solve, hS = dependency_ball(st, p, centre, 8)
+    assert S.size < n - 200 and solve.sum() < S.size
+    rng = np.random.default_rng(5)
+    cot = dict(rho=np.zeros(n), h=np.zeros(n), a=np.zeros((n, 3)), du=np.zeros(n))
+    cot["rho"][T] = rng.normal(size=T.size)
+    cot["h"][T] = rng.normal(size=T.size)
+    cot["a"][T] = rng.normal(size=(T.size, 3))
+    cot["du"][T] = rng.normal(size=T.size)
+    gx, gm = oracle_grads(st, p, cot)
+    sub = {k: st[k][S] for k in ("x", "y", "z", "vx", "vy", "vz", "u", "level")}
+    sub["h"] = hS
+    sx, sm = oracle_grads(sub, p, {k: v[S] for k, v in cot.items()}, solve=solve)
+    out = np.ones(n, bool)
+    out[S] = False
+    assert np.max(np.abs(gx[out])) < 1e-12 * np.max(np.abs(gx))
+    assert np.max(np.abs(gm[out])) < 1e-12 * np.max(np.abs(gm))
+    assert np.max(np.abs(gx[S] - sx)) < 1e-10 * np.max(np.abs(gx))
+    assert np.max(np.abs(gm[S] - sm)) < 1e-10 * np.max(np.abs(gm))
+    # the particles outside the solved set keep the h they were given
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64)  # noqa: E731
+    *_, h, _ = ADJ.forward(t(np.stack([sub["x"], sub["y"], sub["z"]], 1)),
+                           t(2.0 ** -sub["level"].astype(float)),
+                           t(np.stack([sub["vx"], sub["vy"], sub["vz"]], 1)), t(sub["u"]), t(hS),
+                           eos_kind=2, gamma=G, solve=torch.as_tensor(solve))
+    assert np.array_equal(h.detach().numpy()[~solve], hS[~solve])
