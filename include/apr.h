@@ -341,6 +341,21 @@ int apr_accel(apr_ctx *ctx, apr_state *s, const apr_sink *sinks, int32_t nsinks)
  * (0.3 by analogy with the paper's relaxation step, Sec. 2.4).  Synchronises. */
 int apr_timestep(apr_ctx *ctx, const apr_state *s, double C, double *dt);
 
+/* For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  apr_timestep without any
+ * allocation and without host synchronisation: enqueues on the context's
+ * stream the reduction C min_a h_a / vsig_a over the state's last
+ * apr_accel / apr_step and writes it to dt_dev (one double in device memory,
+ * caller-owned).  The reduction's partial minima live in a fixed library
+ * array of 1024 doubles per GPU (8 KB, held until the process ends), set up
+ * by apr_ctx_create on that GPU; every n fits it (the reduction strides), so
+ * no size is refused for it.  All calls on one GPU share that array and keep
+ * the last call's contents: calls that overlap on one GPU (several streams
+ * or host threads) race and must be ordered by the caller.  Errors
+ * (APR_ERR_INVALID, nothing enqueued): an empty state, a NULL dt_dev, no
+ * force evaluation of this state in the context. */
+int apr_timestep_noalloc(apr_ctx *ctx, const apr_state *s, double C, double *dt_dev);
+
 /* Waits for the stream and returns APR_ERR_NOCONVERGE / APR_ERR_RANGE if
  * a kernel since the last call flagged one; *count receives the number of
  * particles that failed to converge (may be NULL).  Clears the flags. */

@@ -81,6 +81,7 @@ def lib():
     L.apr_build_cells.argtypes = [_vp, C.POINTER(CState), _vp]
     L.apr_density.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp]
     L.apr_forces.argtypes = [_vp, C.POINTER(CState), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.apr_timestep_noalloc.argtypes = [_vp, C.POINTER(CState), C.c_double, _vp]
     L.apr_vjp.argtypes = [_vp, C.POINTER(CState)] + [_vp] * 12
     L.apr_bins_init.argtypes = [_vp, C.POINTER(CState), _vp, C.POINTER(Sink), C.c_int32,
                                 C.c_double, C.c_double, C.c_int32]
@@ -107,7 +108,8 @@ def lib():
               "apr_density", "apr_forces", "apr_vjp", "apr_relax", "apr_bins_init",
               "apr_step_bins", "apr_neighbours",
               "apr_split_merge", "apr_step",
-              "apr_accel", "apr_timestep", "apr_sync_status", "apr_profile_enable",
+              "apr_accel", "apr_timestep", "apr_timestep_noalloc", "apr_sync_status",
+              "apr_profile_enable",
               "apr_profile_read", "apr_counters"):
         getattr(L, f).restype = C.c_int
     _LIB = L

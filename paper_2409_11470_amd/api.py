@@ -321,6 +321,13 @@ def apr_timestep(ctx, st, C_cfl=0.3):
     return dt.value
 
 
+def apr_timestep_noalloc(ctx, st, dt_dev, C_cfl=0.3):
+    """apr_timestep into a device float64 tensor of one element, with no
+    allocation and no synchronisation (enqueued on the context's stream)."""
+    cs = st.cstate()
+    ctx.check(lib().apr_timestep_noalloc(ctx.ptr, C.byref(cs), float(C_cfl), _ptr(dt_dev)))
+
+
 def apr_sync_status(ctx, raise_noconverge=True):
     """Waits for the stream; returns the number of unconverged h-rho solves.
     Raises AprError on any flag (non-convergence only if raise_noconverge)."""

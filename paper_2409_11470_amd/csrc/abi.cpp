@@ -13,6 +13,12 @@ int fail(apr_ctx *c, int code, const std::string &msg)
     return code;
 }
 
+int fail(apr_ctx *c, int code, const char *msg)
+{
+    if (c) c->err.assign(msg);  // within the reserved capacity: no allocation
+    return code;
+}
+
 int hip_check(apr_ctx *c, hipError_t e, const char *what)
 {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
@@ -47,6 +53,13 @@ void *ws(apr_ctx *c, const char *name, size_t bytes)
     }
     c->bufs.push_back(b);
     return b.p;
+}
+
+void *ws_peek(apr_ctx *c, const char *name, size_t bytes)
+{
+    for (auto &b : c->bufs)
+        if (b.name == name) return b.bytes >= bytes ? b.p : nullptr;
+    return nullptr;
 }
 
 void *ws_keep(apr_ctx *c, const char *name, size_t bytes, size_t keep)
@@ -175,7 +188,9 @@ int apr_ctx_create(apr_ctx **out, const apr_params *p, void *stream)
     if (!c) return APR_ERR_INVALID;
     c->p = *p;
     c->stream = (hipStream_t)stream;
-    if (hipMalloc(&c->d_status, sizeof(int32_t) * ST_WORDS) != hipSuccess ||
+    c->err.reserve(256);  // short messages never allocate (the allocation-free entry)
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipMalloc(&c->d_status, sizeof(int32_t) * ST_WORDS) != hipSuccess ||
         hipHostMalloc(&c->h_status, sizeof(int32_t) * ST_WORDS, hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(&c->count_pin, sizeof(uint64_t), hipHostMallocCoherent) != hipSuccess ||
@@ -188,6 +203,10 @@ int apr_ctx_create(apr_ctx **out, const apr_params *p, void *stream)
         return APR_ERR_HIP;
     }
     *c->count_pin = 0;  // no build has written a count yet
+    if (dt_scratch_setup(c) != APR_OK) {
+        (void)apr_ctx_destroy(c);
+        return APR_ERR_HIP;
+    }
     *out = c;
     return APR_OK;
 }
@@ -445,6 +464,18 @@ int apr_timestep(apr_ctx *c, const apr_state *s, double C, double *dt)
     void *rho, *om, *a, *vs;
     step_buffers(c, s->capacity, &rho, &om, &a, &vs);
     return min_timestep(c, s, vs, C, dt);
+}
+
+int apr_timestep_noalloc(apr_ctx *c, const apr_state *s, double C, double *dt_dev)
+{
+    int rc = check_state(c, s, false);
+    if (rc) return rc;
+    if (!dt_dev) return fail(c, APR_ERR_INVALID, "dt_dev");
+    if (c->force_n != s->n) return fail(c, APR_ERR_INVALID, "no force evaluation for this state");
+    const size_t e = c->p.precision == APR_FP32 ? 4 : 8;
+    const void *vs = ws_peek(c, "st_vsig", (size_t)s->capacity * e);
+    if (!vs) return fail(c, APR_ERR_INVALID, "no force evaluation for this state");
+    return min_timestep_noalloc(c, s, vs, C, dt_dev);
 }
 
 int apr_profile_enable(apr_ctx *c, int on)

@@ -20,6 +20,8 @@ constexpr int kFan = 64;        // tree fan-out (one wavefront tests all childre
 constexpr int kMaxLev = 6;      // tree levels above the cells
 constexpr int kNumXcd = 8;      // MI355X: workgroups go round-robin over 8 XCDs
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxDevices = 64;  // GPUs per process the allocation-free scratch table covers
+constexpr int kDtParts = 1024;   // partial minima of the timestep reduction
 
 // Status words on the device (ctx->d_status).
 enum {
@@ -63,6 +65,7 @@ struct Box {
 struct apr_ctx {
     apr_params p;
     hipStream_t stream = nullptr;
+    int device = -1;               // the HIP device current at creation
     std::string err;
     struct Buf {
         std::string name;
@@ -125,6 +128,7 @@ T *wsa(apr_ctx *c, const char *name, size_t count)
 }
 
 int fail(apr_ctx *c, int code, const std::string &msg);
+int fail(apr_ctx *c, int code, const char *msg);
 int hip_check(apr_ctx *c, hipError_t e, const char *what);
 #define APR_HIP(ctx, call)                                        \
     do {                                                          \
@@ -295,6 +299,13 @@ int total_accel(apr_ctx *c, apr_state *s, const void *ax, const void *ay, const 
                const uint8_t *active = nullptr, const int8_t *bin = nullptr,
                double dt_max = 0.0);
 int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, double *dt);
+// the same reduction into a device double, with the partial minima in the
+// library's per-device scratch array: no allocation, no synchronisation
+int dt_scratch_setup(apr_ctx *c);
+int min_timestep_noalloc(apr_ctx *c, const apr_state *s, const void *vsig, double C,
+                         double *dt_dev);
+// an existing workspace buffer of at least `bytes`, or null (never allocates)
+void *ws_peek(apr_ctx *c, const char *name, size_t bytes);
 
 // splitmerge.hip
 // Individual timesteps: active (optional, [n]) restricts the pass to those

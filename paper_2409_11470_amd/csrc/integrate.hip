@@ -1,6 +1,8 @@
 // Kick-drift-kick leapfrog (FP64), point-mass (sink) gravity and the Courant
 // timestep.  The paper integrates with its host code's individual-timestep
 // scheme; this is the standard global-step KDK.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace apr {
@@ -113,8 +115,11 @@ __global__ __launch_bounds__(256) void k_dt_partial(int64_t n, const double *h, 
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-__global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, double *out)
+// out = C min(part[0..np)) (C = 1: the minimum itself)
+__global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, double C,
+                                                  double *out)
 {
+#pragma clang fp contract(off)
     __shared__ double s[256];
     double m = __builtin_huge_val();
     for (int i = threadIdx.x; i < np; i += 256) m = fmin(m, part[i]);
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(256) void k_dt_final(const double *part, int np, do
         if ((int)threadIdx.x < o) s[threadIdx.x] = fmin(s[threadIdx.x], s[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = s[0];
+    if (threadIdx.x == 0) *out = C * s[0];
 }
 
 // h[i] *= hfac[origin[i]]: the deferred prediction after a split/merge pass
@@ -220,12 +225,61 @@ int min_timestep(apr_ctx *c, const apr_state *s, const void *vsig, double C, dou
     else
         hipLaunchKernelGGL(k_dt_partial<double>, dim3(np), dim3(256), 0, c->stream, n, s->h,
                            (const double *)vsig, part);
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, c->stream, part, np, out);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, c->stream, part, np, 1.0, out);
     APR_LAUNCHED(c);
     double v = 0.0;
     APR_HIP(c, hipMemcpyAsync(&v, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     APR_HIP(c, hipStreamSynchronize(c->stream));
     *dt = C * v;
+    return APR_OK;
+}
+
+// ---------------------------------------------------- the timestep, allocation-free
+// apr_timestep_noalloc keeps the partial minima of its reduction in this
+// file-scope device array instead of the context's workspace.  Each GPU holds
+// its own copy until the process ends.  On the host, `scratch` names no
+// device address: its address on each device is taken once, with that
+// device current, by hipGetSymbolAddress (dt_scratch_setup, from
+// apr_ctx_create) and only that pointer is passed to kernels.
+static __device__ __align__(256) __attribute__((used)) double scratch[kDtParts];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+}  // namespace
+
+int dt_scratch_setup(apr_ctx *c)
+{
+    if (c->device < 0 || c->device >= kMaxDevices)
+        return fail(c, APR_ERR_INVALID, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[c->device]) return APR_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_check(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch[c->device] = ptr;
+    return APR_OK;
+}
+
+int min_timestep_noalloc(apr_ctx *c, const apr_state *s, const void *vsig, double C,
+                         double *dt_dev)
+{
+    double *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        part = static_cast<double *>(g_scratch[c->device]);
+    }
+    if (!part) return fail(c, APR_ERR_INVALID, "no timestep scratch on this device");
+    const int64_t n = s->n;
+    const int np = (int)std::min<int64_t>(kDtParts, ceil_div(n, 256));
+    if (c->p.precision == APR_FP32)
+        hipLaunchKernelGGL(k_dt_partial<float>, dim3(np), dim3(256), 0, c->stream, n, s->h,
+                           (const float *)vsig, part);
+    else
+        hipLaunchKernelGGL(k_dt_partial<double>, dim3(np), dim3(256), 0, c->stream, n, s->h,
+                           (const double *)vsig, part);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, c->stream, part, np, C, dt_dev);
+    APR_LAUNCHED(c);
     return APR_OK;
 }
 
