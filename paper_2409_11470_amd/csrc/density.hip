@@ -58,7 +58,12 @@ template <>
 struct StageCap<double> {
     static constexpr int value = 768;
 };
-constexpr int kDTCap = 96;   // per-target list capacity (density)
+// Per-target list capacity (density).  A uniform medium has about 57
+// neighbours within 2h, but at an interface of masses differing eightfold
+// (the shock box) half a heavy particle's neighbours are light, its h grows
+// by about a fifth and its count reaches about 100; a longer list would
+// leave the target walking the whole staged set every pass.
+constexpr int kDTCap = 128;
 
 template <class T>
 struct DensArgs {
@@ -232,7 +237,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     __shared__ V stg[STAGE];
     __shared__ ListsMeta<T, kDTCap> s_lm;  // per-target lists, or candidates' metadata
     uint16_t(*tls)[kDTCap] = s_lm.tls;
-    __shared__ uint16_t sub[kWaves][STAGE];
+    __shared__ uint16_t sub[kWaves][kSubCap];
     __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
     __shared__ int s_more, s_edge;
@@ -396,7 +401,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     Rt = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
                     const T Rtl = (T)Rt;
                     build_lists<T, false, kListLanes>(
-                        nstg, stg, sub[w], &tls[0][0], kDTCap, s_tlen,
+                        nstg, stg, sub[w], kSubCap, &tls[0][0], kDTCap, s_tlen,
                         [&](int k) {
                             V q;
                             int tt = 16 * w + k;

@@ -217,7 +217,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
             __syncthreads();
             if (!wave_busy) continue;
             build_lists<T, true, kListLanes>(
-                nstg, stg[0], sub[w], &tls[0][0], kTCap, s_tlen,
+                nstg, stg[0], sub[w], STAGE, &tls[0][0], kTCap, s_tlen,
                 [&](int k) {
                     V q;
                     int tt = 16 * w + k;

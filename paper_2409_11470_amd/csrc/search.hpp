@@ -578,14 +578,15 @@ __device__ inline T wmax_lanes(T v)
 // targets; with FULL the entry is read as one vector, w included), then each
 // target's G lanes keep the entries that accept(target position, reach, e).
 // pos(k) and reach(k) give target slot k's position and reach (0: no list);
-// every lane calls them.  sub is the wavefront's scratch list (room for nstg
-// entries).  Writes tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length
-// above cap means the list is incomplete and the caller must walk the staged
-// set instead.
+// every lane calls them.  sub is the wavefront's scratch list (room for
+// subcap entries; a sub-block with more marks its targets' lists incomplete).
+// Writes tls[(16 w + k) * cap ...] and tlen[16 w + k]; a length above cap
+// means the list is incomplete and the caller must walk the staged set
+// instead.
 template <class T, bool FULL, int G, class Pos, class Reach, class BoxOk, class Accept>
-__device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub, uint16_t *tls,
-                                   int cap, int *tlen, Pos pos, Reach reach, BoxOk box_ok,
-                                   Accept accept)
+__device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub, int subcap,
+                                   uint16_t *tls, int cap, int *tlen, Pos pos, Reach reach,
+                                   BoxOk box_ok, Accept accept)
 {
     static_assert(G == 8 || G == 16, "8 or 16 lanes per target");
     constexpr int TPS = kWave / G;   // targets per sub-block
@@ -618,10 +619,16 @@ __device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub
                     hit = box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2, p);
                 }
                 uint64_t m = __ballot(hit);
-                if (hit) sub[nsub + __popcll(m & lanemask_lt())] = (uint16_t)idx;
+                const int ps = nsub + __popcll(m & lanemask_lt());
+                if (hit && ps < subcap) sub[ps] = (uint16_t)idx;
                 nsub += __popcll(m);
             }
             wave_sync();
+            if (nsub > subcap) {
+                // the sub-block list did not fit: its targets walk the staged set
+                if (j == 0) tlen[16 * w + k] = cap + 1;
+                continue;
+            }
             uint16_t *L = tls + (size_t)(16 * w + k) * cap;
             constexpr uint64_t gmask = G == 16 ? 0xffffull : 0xffull;
             for (int base = 0; base < nsub; base += G) {
