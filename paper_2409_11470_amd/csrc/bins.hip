@@ -25,6 +25,8 @@ namespace {
 
 unsigned g256(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 256); }
 
+constexpr int kRebuild = 8;  // substeps between full cell builds when nothing splits or merges
+
 // the smallest k >= 0 with dt_max 2^-k <= c_cfl h / vsig, at most kmax
 template <class T>
 __device__ inline int courant_k(double h, T vs, double dt_max, double c_cfl, int kmax)
@@ -270,6 +272,7 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
     double *u = c->p.eos == APR_EOS_ADIABATIC ? s->u : nullptr;
     for (int64_t sub = 0; sub < nsub; ++sub) {
         int64_t n = s->n;
+        bool changed = false;  // the split/merge pass changed the particle set
         hipLaunchKernelGGL(k_substep_open, dim3(g256(n)), dim3(256), 0, c->stream, n, bin, K,
                            sub, dt_max, delta, s->x, s->y, s->z, s->vx, s->vy, s->vz, u, s->ax,
                            s->ay, s->az, s->dudt, box, act, made);
@@ -286,6 +289,7 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
                              idx, made);
             if (rc) return rc;
             if (ns + nm > 0) {
+                changed = true;
                 n = s->n;
                 rc = remap_all<T>(c, bin, b, act, nullptr, idx, n);
                 if (rc) return rc;
@@ -294,10 +298,18 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
                 APR_LAUNCHED(c);
             }
         }
-        rc = build_cells(c, s, idx, true);
-        if (rc) return rc;
-        rc = remap_all<T>(c, bin, b, act, made, idx, n);
-        if (rc) return rc;
+        // a substep whose pass changed nothing keeps the cells and refits them
+        // to the drifted positions (the particles of a cell move together);
+        // every kRebuild-th substep sorts again, so that they stay compact
+        if (sub % kRebuild == 0 || changed || c->cells_n != n) {
+            rc = build_cells(c, s, idx, true);
+            if (rc) return rc;
+            rc = remap_all<T>(c, bin, b, act, made, idx, n);
+            if (rc) return rc;
+        } else {
+            rc = refit_cells(c, s);
+            if (rc) return rc;
+        }
         rc = density(c, s, b.rho, b.om, nullptr, nullptr, act);
         if (rc) return rc;
         hipLaunchKernelGGL(k_copy_active<T>, dim3(g256(n)), dim3(256), 0, c->stream, n, act,

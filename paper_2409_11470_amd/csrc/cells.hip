@@ -541,6 +541,35 @@ int cells_hmax_from(apr_ctx *c, const double *h, int64_t n)
 static int build_cells_impl(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel,
                             bool carry_divv);
 
+int refit_cells(apr_ctx *c, apr_state *s)
+{
+    if (c->cells_n != s->n) return fail(c, APR_ERR_INVALID, "cells not built for this state");
+    int tok = prof_begin(c, APR_PROF_CELLS);
+    Hdr *hdr = wsa<Hdr>(c, "cell_hdr", 1);
+    const int32_t *cs = cell_start(c);
+    Geo *cells = cell_level(c, 0);
+    const int64_t n = s->n;
+    if (c->p.precision == APR_FP32) {
+        float4 *pm = wsa<float4>(c, "pm32", (size_t)n);
+        hipLaunchKernelGGL(k_cell_geo<float>, dim3((unsigned)ceil_div(c->node_grid[0], 4)),
+                           dim3(256), 0, c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level,
+                           cells, pm);
+    } else {
+        double4 *pm = wsa<double4>(c, "pm64", (size_t)n);
+        hipLaunchKernelGGL(k_cell_geo<double>, dim3((unsigned)ceil_div(c->node_grid[0], 4)),
+                           dim3(256), 0, c->stream, hdr, cs, s->x, s->y, s->z, s->h, s->level,
+                           cells, pm);
+    }
+    for (int k = 1; k <= c->nlev; ++k)
+        hipLaunchKernelGGL(k_tree_level, dim3((unsigned)ceil_div(c->node_grid[k], 4)), dim3(256),
+                           0, c->stream, hdr, k, cell_level(c, k - 1), cell_level(c, k));
+    APR_LAUNCHED(c);
+    prof_end(c, tok);
+    c->dens_n = -1;
+    c->force_n = -1;
+    return APR_OK;
+}
+
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel)
 {
     if (!c->in_bins) c->bins_n = -1;  // a reorder the stored per-particle values miss

@@ -243,6 +243,10 @@ int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bi
 // keep_accel false: ax, ay, az, dudt are left unpermuted (the caller
 // recomputes them before reading them)
 int build_cells(apr_ctx *c, apr_state *s, int64_t *perm, bool keep_accel = true);
+// The cells of the last build, refitted to particles that moved but kept
+// their order: boxes, centres, h_max, cell-frame positions and the tree's
+// boxes from the current state (no sort, no permutation).
+int refit_cells(apr_ctx *c, apr_state *s);
 int refit_hmax_from_cells(apr_ctx *c);   // tree nodes' hmax from the cells' hmax
 int set_hmax_new(apr_ctx *c, const float *hmax_new);  // cells' hmax from hmax_new[cell], then the tree's
 int cells_hmax_from(apr_ctx *c, const double *h, int64_t n);  // cells' hmax from h, then refit

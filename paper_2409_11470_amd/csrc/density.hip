@@ -128,14 +128,15 @@ struct DSum {
         cnt = 0;
         dmin = T(3.0e38);
     }
-    // wt: the staged mass with its candidate tag; edge(wt) decides membership
-    // in FP64 for pairs inside the guard band |r^2 - R^2| <= band
+    // wt: the staged mass with its candidate tag; inside the guard band
+    // R2lo <= r^2 <= R2hi (R^2 -+ band) edge(wt) decides membership in FP64,
+    // below it the pair is in, above it out
     template <class Edge>
-    __device__ void pair(T dx, T dy, T dz, T wt, T R2, T band, T hinv, Edge edge)
+    __device__ void pair(T dx, T dy, T dz, T wt, T R2lo, T R2hi, T hinv, Edge edge)
     {
         T r2 = dx * dx + dy * dy + dz * dz;
-        bool in = r2 < R2;
-        if (fabs(r2 - R2) <= band) in = edge(wt);
+        bool in = r2 < R2lo;
+        if (!in && r2 <= R2hi) in = edge(wt);
         if (in) {
             const T m = untag_mass(wt);
             T r = psqrt(r2);
@@ -423,6 +424,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 T hinv = T(1) / hf;
                 T R2 = T(4) * hf * hf;
                 const T band = edge_band<T>(tp, T(2) * hf);
+                const T R2lo = R2 - band, R2hi = R2 + band;
                 const double hx = (double)hf;  // the h these sums are reported at
                 auto ed = [&](T wt) { return edge(wt, hx); };
                 if (tlen <= kDTCap) {
@@ -431,18 +433,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     for (; k + kLanes < tlen; k += 2 * kLanes) {
                         const int e0 = mylist[k], e1 = mylist[k + kLanes];
                         const V p0 = lds_ld4<T>(&stg[e0]), p1 = lds_ld4<T>(&stg[e1]);
-                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2, band, hinv, ed);
-                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2, band, hinv, ed);
+                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2lo, R2hi, hinv, ed);
+                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2lo, R2hi, hinv, ed);
                     }
                     if (k < tlen) {
                         const V p = lds_ld4<T>(&stg[mylist[k]]);
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, band, hinv, ed);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2lo, R2hi, hinv, ed);
                     }
                 } else {
                     // own list overflowed: walk the whole window
                     for (int k = j; k < nstg; k += kLanes) {
                         V p = stg[k];
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, band, hinv, ed);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2lo, R2hi, hinv, ed);
                     }
                 }
             }

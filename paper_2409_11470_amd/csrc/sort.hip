@@ -2,7 +2,9 @@
 // uint32 value) pairs, built from wavefront-level scans (shuffles) and
 // ballot-based ranking.  No spin-waits: every scan is reduce-then-scan over
 // two launches (the second sums the earlier tiles' totals itself), so every
-// kernel finishes on its own.
+// kernel finishes on its own.  Beyond kScanTile tiles (16.8M elements) the
+// tiles' totals are themselves scanned first, recursively, and the second
+// launch reads its tile's offset.
 #include "common.hpp"
 
 namespace apr {
@@ -92,8 +94,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const T *in, T *out,
     if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
 }
 
+// The same with the tile's offset given: offset[blockIdx.x] is the sum of the
+// earlier tiles' totals (an exclusive scan of them, for more tiles than one
+// block can sum).
 template <class T>
-int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const char *tag)
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_off(const T *in, T *out, int64_t n,
+                                                                 const T *offset, T *total)
+{
+    __shared__ T lw[kScanThreads / kWave + 1];
+    const T off = offset[blockIdx.x];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : T(0);
+        s += v[k];
+    }
+    T tot;
+    T ex = block_excl_scan(s, lw, &tot) + off;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
+}
+
+// level: recursion depth (each level has workspaces of its own)
+template <class T>
+int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const char *tag,
+              int level = 0)
 {
     if (n <= 0) {
         if (total_dev) {
@@ -101,14 +132,25 @@ int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const ch
         }
         return APR_OK;
     }
-    int64_t nb = ceil_div(n, kScanTile);
-    if (nb > kScanTile) return fail(c, APR_ERR_INVALID, "scan too long");
-    T *partial = wsa<T>(c, tag, (size_t)nb + 1);
+    const int64_t nb = ceil_div(n, kScanTile);
+    if (nb > ((int64_t)1 << 31)) return fail(c, APR_ERR_INVALID, "scan too long");
+    const std::string nm = std::string(tag) + (level ? "_" + std::to_string(level) : "");
+    T *partial = wsa<T>(c, nm.c_str(), (size_t)nb + 1);
     if (!partial) return fail(c, APR_ERR_HIP, "scan workspace");
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
                        in, n, partial);
-    hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
-                       in, out, n, partial, total_dev);
+    if (nb <= kScanTile) {
+        hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
+                           in, out, n, partial, total_dev);
+    } else {
+        // more tiles than one block sums: scan their totals first
+        T *offset = wsa<T>(c, (nm + "_off").c_str(), (size_t)nb + 1);
+        if (!offset) return fail(c, APR_ERR_HIP, "scan workspace");
+        int rc = excl_scan<T>(c, partial, offset, nb, (T *)nullptr, tag, level + 1);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_scan_down_off<T>, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                           c->stream, in, out, n, offset, total_dev);
+    }
     APR_LAUNCHED(c);
     return APR_OK;
 }

@@ -48,8 +48,10 @@ __device__ inline double zone_dz(const Zones &Z, int k, double z)
 
 // Level of a point: innermost sphere (or cylinder) of each zone (strict),
 // combined by max (or min when derefining); *which = first zone giving the
-// combined level.
-__device__ int zone_level(const Zones &Z, double x, double y, double z, int *which)
+// combined level.  shrink < 1 scales the radii (a conservative level near a
+// boundary); 1 is the exact test.
+__device__ int zone_level(const Zones &Z, double x, double y, double z, int *which,
+                          double shrink = 1.0)
 {
 #pragma clang fp contract(off)
     int best = Z.bg, w = -1;
@@ -58,7 +60,7 @@ __device__ int zone_level(const Zones &Z, double x, double y, double z, int *whi
         double d2 = dx * dx + dy * dy + dz * dz;
         int lev = -1;
         for (int s = 0; s < Z.nsh[k]; ++s) {
-            double rr = Z.r[k][s];
+            double rr = Z.r[k][s] * shrink;
             if (d2 < rr * rr) lev = Z.ell[k][s];
         }
         if (lev < 0) continue;
@@ -282,6 +284,19 @@ __global__ void k_cand_flags(int64_t n, const int8_t *level, const uint8_t *chan
     flag[i] = (level[i] == l && !changed[i] && !removed[i] && (!active || i >= n0 || active[i]))
                   ? 1u
                   : 0u;
+}
+
+// Counts the merge candidates of level l that lie outside the level-l region
+// of the zones, or within a relative 1e-9 of its boundary (*out, zeroed by the
+// caller).  None, with zones whose level can only fall with the distance from
+// one centre (merge_tree_skippable), means that no pair's centre of mass can
+// lie outside it either: no pair merges and the pairing tree can be skipped.
+__global__ void k_cand_outside(int64_t n, const uint32_t *flag, SArr s, Zones Z, int l,
+                               uint32_t *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    if (zone_level(Z, s.x[i], s.y[i], s.z[i], nullptr, 1.0 - 1e-9) < l) atomicAdd(out, 1u);
 }
 
 __global__ void k_compact_idx(int64_t n, const uint32_t *flag, const uint32_t *pos,
@@ -721,6 +736,23 @@ int sort_slots_by_id(apr_ctx *c, uint32_t *slot, uint32_t *keys, int64_t m, cons
 
 }  // namespace
 
+// Whether the pairing tree of a level may be skipped when all its candidates
+// lie inside that level's region (k_cand_outside): one zone in a
+// non-periodic box whose levels never fall inward (and none below the
+// background), combined by max.  Its level then falls with the distance from
+// the centre (or the axis), and a pair's centre of mass is no farther out
+// than the farther of the two: no pair of particles inside the level-l
+// region can have its centre of mass outside it.  Exact: the oracle builds
+// the tree and merges nothing either.
+static bool merge_tree_skippable(const Zones &Z, const apr_params &P)
+{
+    if (Z.nz != 1 || Z.derefine || P.periodic) return false;
+    if (Z.nsh[0] < 1 || Z.ell[0][0] < Z.bg) return false;
+    for (int s = 1; s < Z.nsh[0]; ++s)
+        if (Z.ell[0][s] < Z.ell[0][s - 1] || !(Z.r[0][s] < Z.r[0][s - 1])) return false;
+    return true;
+}
+
 int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int64_t step,
                 int flags, int64_t *n_split, int64_t *n_merged, int64_t *n_spare,
                 const uint8_t *active, int64_t *origin, uint8_t *made)
@@ -857,18 +889,30 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             return fail(c, APR_ERR_HIP, "merge workspace");
         double sc[3];
         for (int k = 0; k < 3; ++k) sc[k] = kQuant / b.L[k];
+        const bool skippable = merge_tree_skippable(Z, P);
         for (int l = lmax; l >= 1; --l) {
             hipLaunchKernelGGL(k_cand_flags, dim3(grid(n)), dim3(256), 0, c->stream, n, s->level,
                                changed, removed, l, active, n0, flag);
             APR_LAUNCHED(c);
             int rc = exclusive_scan_u32(c, flag, scan, n, tot);
             if (rc) return rc;
-            APR_HIP(c, hipMemcpyAsync(&h32, tot, 4, hipMemcpyDeviceToHost, c->stream));
+            uint32_t hc[2] = {0, 0};
+            if (skippable) {
+                rc = fill_u32(c, tot + 2, 0u, 1);
+                if (rc) return rc;
+                hipLaunchKernelGGL(k_cand_outside, dim3(grid(n)), dim3(256), 0, c->stream, n,
+                                   flag, A, Z, l, tot + 2);
+                APR_LAUNCHED(c);
+            }
+            APR_HIP(c, hipMemcpyAsync(&hc[0], tot, 4, hipMemcpyDeviceToHost, c->stream));
+            if (skippable)
+                APR_HIP(c, hipMemcpyAsync(&hc[1], tot + 2, 4, hipMemcpyDeviceToHost, c->stream));
             APR_HIP(c, hipStreamSynchronize(c->stream));
-            int64_t nc = h32;
+            int64_t nc = hc[0];
             if (nc % 2) *n_spare += 1;
             int64_t m = nc - (nc % 2);
             if (m < 2) continue;
+            if (skippable && hc[1] == 0) continue;  // no pair can merge at this level
             hipLaunchKernelGGL(k_compact_idx, dim3(grid(n)), dim3(256), 0, c->stream, n, flag,
                                scan, cand);
             rc = sort_slots_by_id(c, cand, keys, nc, s->id, s->next_id);

@@ -205,3 +205,41 @@ def test_circumbinary_8M_vjp_sampled(cb_disc, prec, level):
     centre = int(rng.choice(np.nonzero(st["level"] == level)[0]))
     ball_vjp_check(("circumbinary", level), st, p, prec, centre, seed=level,
                    gtol={"fp64": 1e-6, "fp32": 1e-3}[prec])
+
+
+def test_beyond_16M_particles_scans_cells_density():
+    # 272^3 = 20.1M particles (the benchmarked box's shape): the cell build,
+    # the density and the neighbour export run scans of more than 4096 tiles
+    # of 4096 elements (the recursive level of the scan).  The export's
+    # offsets must be the exact prefix sums of its counts, the density
+    # kernel's own neighbour count must equal the export's (FP64 predicate)
+    # for every particle, and sampled densities must match the oracle.
+    import ctypes as C
+    nside = 272
+    st, p = W.shock_box(nside=nside)
+    p = dict(p, m0=1.0 / nside ** 3)
+    n = st["x"].shape[0]
+    assert n > 4096 * 4096
+    g, ctx, ds, (rho, om) = gpu_density(st, p, "fp32")
+    assert g["failures"] == 0
+    cs = ds.cstate()
+    counts = torch.zeros(n, dtype=torch.int64, device="cuda")
+    offs = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    total = C.c_int64()
+    hd = ds["h"].contiguous()
+    rc = A.lib().apr_neighbours(ctx.ptr, C.byref(cs), C.c_void_p(hd.data_ptr()), 0,
+                                C.c_void_p(counts.data_ptr()), C.c_void_p(offs.data_ptr()), None,
+                                0, C.byref(total))
+    assert rc == A.APR_OK
+    cnt = counts.cpu().numpy()
+    off = offs.cpu().numpy()
+    assert off[0] == 0 and np.array_equal(off[1:], np.cumsum(cnt)) and total.value == cnt.sum()
+    ids = ds["id"].cpu().numpy()
+    own = np.empty(n, np.int64)
+    own[ids] = cnt
+    assert np.array_equal(g["nneigh"], own + 1)
+    del ctx, ds, rho, om, counts, offs, hd
+    torch.cuda.empty_cache()
+    tg, od, _ = oracle_balls(st, p, 2, 32, seed=23, forces=False)
+    for k in ("h", "rho", "omega"):
+        assert _rel(g[k][tg], od[k]) < TOL["fp32"], k
