@@ -79,10 +79,10 @@ PEAK_HBM_GBS = 8000.0
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     "k_density<float, 0, false, false>": dict(
-        bytes_per_launch=93250729,
+        bytes_per_launch=155985248,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
-        sha256="21138473389d532cfb9dc38f40ffd9ebad996e7871c38fddd4495d985a5b55b8"),
+        sha256="f14528443c4aa02d630c2b826f998d7999e2162ec13241653da3cf571f41878b"),
 }
 
 
