@@ -11,7 +11,9 @@
  *  - Every call returns an int status (APR_OK = 0 or an APR_ERR_* code) and
  *    never throws.  apr_last_error() gives a message for the last failure.
  *  - Particle arrays are caller-owned DEVICE pointers (one GPU), structure of
- *    arrays, n valid entries out of `capacity` allocated ones.  The library
+ *    arrays, n valid entries out of `capacity` allocated ones (capacity at
+ *    most 2^31 - 1: cell starts and particle slots are 32-bit; larger states
+ *    are rejected with APR_ERR_INVALID).  The library
  *    owns only its workspace (sort buffers, cells, tree, per-particle
  *    derived values), which lives in the context and grows as needed.
  *  - Calls enqueue work on the context's HIP stream and return without

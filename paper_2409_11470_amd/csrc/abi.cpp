@@ -123,6 +123,9 @@ int check_state(apr_ctx *c, const apr_state *s, bool need_vel)
     if (!c) return APR_ERR_INVALID;
     if (!s) return fail(c, APR_ERR_INVALID, "null state");
     if (s->n <= 0 || s->n > s->capacity) return fail(c, APR_ERR_INVALID, "bad n / capacity");
+    // cell starts and particle slots are 32-bit
+    if (s->capacity > (int64_t)INT32_MAX)
+        return fail(c, APR_ERR_INVALID, "capacity above 2^31 - 1 particles");
     if (!s->x || !s->y || !s->z || !s->h || !s->level || !s->id)
         return fail(c, APR_ERR_INVALID, "state needs x, y, z, h, level, id");
     if (need_vel && (!s->vx || !s->vy || !s->vz))

@@ -2,6 +2,8 @@
 
 - An empty state (n = 0): every entry point that takes a state returns
   APR_ERR_INVALID (a bad n / capacity), and the context stays usable.
+- A state claiming a capacity of 2^31 particles (cell starts and slots are
+  32-bit) is rejected before anything reads its arrays.
 - Coincident particles: pairs at r = 0 count in the density (W(0)), add
   nothing to the forces, and give a nearest-neighbour distance of 0; the GPU
   agrees with the oracle per particle (FP64 form)."""
@@ -45,6 +47,19 @@ def test_empty_state_rejected_and_context_usable():
     g = np.empty(ds.n)
     g[ds["id"].cpu().numpy()] = rho.cpu().numpy()
     assert np.max(np.abs(g / o["rho"] - 1)) < 1e-9
+
+
+def test_capacity_beyond_int32_rejected():
+    st, p = W.lattice_box(nside=4)
+    ctx = A.Context(params_for(p, "fp64"))
+    ds = A.DeviceState.from_numpy(st)
+    ds.capacity = 2 ** 31   # the arrays hold 64; the check comes before any access
+    with pytest.raises(A.AprError) as e:
+        A.apr_build_cells(ctx, ds)
+    assert e.value.code == A.APR_ERR_INVALID
+    ds.capacity = ds.n
+    A.apr_build_cells(ctx, ds)
+    assert A.apr_sync_status(ctx) == 0
 
 
 def test_coincident_particles():
