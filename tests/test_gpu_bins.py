@@ -1,5 +1,6 @@
 """Individual timesteps (paper Sec. 2.5) on the GPU (apr_bins_init,
-apr_step_bins) against the oracle's step_bins, FP64 form.
+apr_step_bins) against the oracle's step_bins: the FP64 form per id at 1e-9,
+the FP32 form within bounds grown from its per-evaluation gate.
 
 The 4000-particle planet disc with its sink and refinement zone, dt_max 0.5:
 the Courant bins spread over 0..3 (8 substeps).  Two steps, compared per id
@@ -196,3 +197,82 @@ def test_bin_zero_is_the_global_step(prec, tol):
         for k in ("x", "y", "z", "vx", "vy", "vz", "h"):
             sc = max(np.max(np.abs(o[k])), 1e-30)
             assert np.max(np.abs(g[k] - o[k])) / sc < tol, k
+
+
+def _l1_bounds(st, phys):
+    """The largest L1 sums of the acceleration (hydro pair terms plus the sink
+    pull) and of du/dt over the particles of a state, from the oracle."""
+    box = dict(periodic=phys["periodic"], lo=phys["lo"], hi=phys["hi"])
+    d = oracle.density(st["x"], st["y"], st["z"], st["level"], st["h"], m0=phys["m0"],
+                       hfact=phys["hfact"], tol=1e-12, max_iter=60, **box)
+    f = oracle.forces(st["x"], st["y"], st["z"], st["vx"], st["vy"], st["vz"], st.get("u"),
+                      st["level"], d["h"], d["rho"], d["omega"], m0=phys["m0"], eos=phys["eos"],
+                      cs0=phys["cs0"], q_cs=phys["q_cs"], r_ref=phys["r_ref"],
+                      gamma=phys["gamma"], alpha=phys["alpha"], beta=phys["beta"], **box)
+    a = f["anorm"]
+    if phys["sinks"]:
+        n = st["x"].shape[0]
+        g = [np.zeros(n) for _ in range(3)]
+        s = phys["sinks"]
+        oracle.sink_gravity(st["x"], st["y"], st["z"], [q["x"] for q in s], [q["m"] for q in s],
+                            [q.get("eps", 0.0) for q in s], 1.0, *g)
+        a = a + np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+    return float(np.max(a)), float(np.max(f["unorm"])), float(np.min(d["h"]))
+
+
+@pytest.mark.parametrize("case", ["wave", "disc"])
+def test_fp32_steps_within_bounds(case):
+    """The FP32 form of individual timesteps against the FP64 oracle: the wave
+    box (periodic, adiabatic, cylinder zone, bins 1-2) and the planet disc
+    (sink, sphere zone, bins 0-3), two steps of dt_max each.  Levels and bins
+    exactly; the continuous values within bounds grown from the FP32 form's
+    per-evaluation gate eps = 1e-3 of the L1 sums (A for the acceleration,
+    hydro terms plus the sink pull; U for du/dt) over the time advanced,
+    T = 2 dt_max:  v: T eps A_max,  x: T^2 eps A_max,  u: T eps U_max,
+    h: eps + 3 (x bound) / h_min, with A_max, U_max the larger of the start's
+    and the end's.  The measured errors are orders below (about 1e-7 of
+    these scales); a missing or doubled kick, a substep drifted twice or a
+    particle in the wrong bin exceeds them."""
+    if case == "wave":
+        st, p = W.wave_box(nx=16)
+    else:
+        st, p = W.planet_disc(n=4000)
+    phys = _phys(p)
+    o = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    oracle.accel_bins(o, **phys)
+    if case == "wave":
+        dtm = 2.0 * float(np.median(0.3 * o["h"] / o["vsig"])) * 1.000123
+    else:
+        dtm = DT
+    o["bin"] = oracle.courant_bin(o["h"], o["vsig"], dt_max=dtm, c_cfl=0.3, max_bin=MAXB)
+    assert len(np.unique(o["bin"])) >= 2
+    for step in range(2):
+        o = oracle.step_bins(o, zones=p["zones"], dt_max=dtm, step=step, max_bin=MAXB, seed=3,
+                             **SPLIT, **phys)
+    ctx = A.Context(params_for(p, "fp32", seed=3, **SPLIT))
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_bins_init(ctx, ds, dtm, 0.3, MAXB, p.get("sinks", []))
+    for step in range(2):
+        A.apr_step_bins(ctx, ds, p["zones"], p.get("sinks", []), dtm, step, 0.3, MAXB)
+    A.apr_sync_status(ctx)
+    g, o = _by_id(ds.to_numpy()), _by_id(o)
+    assert np.array_equal(g["id"], o["id"])
+    assert int((g["id"] >= st["x"].shape[0]).sum()) > 10     # children were made
+    for k in ("level", "bin"):
+        assert np.array_equal(g[k], o[k]), k
+    a0, u0, h0 = _l1_bounds(st, phys)
+    a1, u1, h1 = _l1_bounds(o, phys)
+    eps, T = 1e-3, 2 * dtm
+    A_max, U_max = max(a0, a1), max(u0, u1)
+    bound = dict(x=T * T * eps * A_max, v=T * eps * A_max, u=T * eps * U_max)
+    L = np.asarray(p["hi"], float) - np.asarray(p["lo"], float)
+    for i, k in enumerate(("x", "y", "z")):
+        d = g[k] - o[k]
+        if p["periodic"]:
+            d -= L[i] * np.round(d / L[i])
+        assert np.max(np.abs(d)) < bound["x"], (k, np.max(np.abs(d)), bound["x"])
+    for k in ("vx", "vy", "vz"):
+        assert np.max(np.abs(g[k] - o[k])) < bound["v"], (k, bound["v"])
+    if p["eos"] == 2:
+        assert np.max(np.abs(g["u"] - o["u"])) < bound["u"], bound["u"]
+    assert np.max(np.abs(g["h"] / o["h"] - 1)) < eps + 3 * bound["x"] / min(h0, h1)

@@ -6,7 +6,8 @@ split pass of it with the cylinder zone (108 children), made by the oracle's
 split.  Each side solves the reference set's density and forces itself, then
 shuffles.  FP64 form: the number of shuffles, the first and last KE (1e-9
 relative) and every position per id (1e-9 of the box); FP32 form: five
-shuffles, positions within 2e-3 of the largest displacement."""
+shuffles and the full fifty, positions within 2e-3 of the largest
+displacement."""
 import numpy as np
 import pytest
 import torch
@@ -120,3 +121,25 @@ def test_relax_rejects_bad_arguments():
         A.apr_relax(ctx, ds, other, dr, z, z, z, z)
     with pytest.raises(A.AprError):   # no shuffles asked for
         A.apr_relax(ctx, ds, rctx, dr, z, z, z, z, max_shuffles=0)
+
+
+def test_relax_fp32_fifty_shuffles():
+    """The FP32 form over the full run (50 shuffles with the paper's stopping
+    rule, which this box does not reach: KE falls to about 17 % of the
+    first shuffle's) against the FP64 oracle.  The gate stays that of the
+    five-shuffle case, 2e-3 of the largest displacement: twice the FP32
+    form's per-evaluation gate.  The measured error is about 4e-6 of it; one
+    shuffle missing or doubled moves particles by about 1/50 of it."""
+    st, new, p, box = _inputs()
+    o, ns_o, kes = _oracle(st, new, p, box, max_shuffles=50, ke_frac=0.005)
+    g, ns_g, k0, k1 = _gpu(st, new, p, "fp32", 50, 0.005)
+    o, n0 = _by_id(o), _by_id(new)
+    assert ns_g == ns_o == 50
+    assert abs(k0 / kes[0] - 1) < 1e-3 and abs(k1 / kes[-1] - 1) < 1e-3
+    assert np.array_equal(g["id"], o["id"])
+    L = np.asarray(p["hi"], float)
+    disp = np.sqrt(sum((o[k] - n0[k]) ** 2 for k in ("x", "y", "z")))
+    for a, k in enumerate(("x", "y", "z")):
+        d = g[k] - o[k]
+        d -= L[a] * np.round(d / L[a])
+        assert np.max(np.abs(d)) < 2e-3 * disp.max(), k
