@@ -120,7 +120,7 @@ struct DSum {
                   // Newton step uses it, so a plain sum suffices (one register fewer)
     int cnt;       // neighbours in the low 16 bits, those at r = 0 above
     T dmin;
-    T emin;        // min |r^2 - R^2| over every pair evaluated, in or out
+    T emin;        // min |r^2 - R2hi| over every pair evaluated, in or out
     __device__ void zero()
     {
         w.zero();
@@ -134,10 +134,10 @@ struct DSum {
     // R2lo <= r^2 <= R2hi (R^2 -+ band) edge(wt) decides membership in FP64,
     // below it the pair is in, above it out
     template <class Edge>
-    __device__ void pair(T dx, T dy, T dz, T wt, T R2, T R2lo, T R2hi, T hinv, Edge edge)
+    __device__ void pair(T dx, T dy, T dz, T wt, T R2lo, T R2hi, T hinv, Edge edge)
     {
         T r2 = dx * dx + dy * dy + dz * dz;
-        const T e = fabs(r2 - R2);
+        const T e = fabs(r2 - R2hi);
         emin = emin < e ? emin : e;
         bool in = r2 < R2lo;
         if (!in && r2 <= R2hi) in = edge(wt);
@@ -437,20 +437,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     for (; k + kLanes < tlen; k += 2 * kLanes) {
                         const int e0 = mylist[k], e1 = mylist[k + kLanes];
                         const V p0 = lds_ld4<T>(&stg[e0]), p1 = lds_ld4<T>(&stg[e1]);
-                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2, R2lo, R2hi, hinv,
-                               ed);
-                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2, R2lo, R2hi, hinv,
-                               ed);
+                        S.pair(tp.x - p0.x, tp.y - p0.y, tp.z - p0.z, p0.w, R2lo, R2hi, hinv, ed);
+                        S.pair(tp.x - p1.x, tp.y - p1.y, tp.z - p1.z, p1.w, R2lo, R2hi, hinv, ed);
                     }
                     if (k < tlen) {
                         const V p = lds_ld4<T>(&stg[mylist[k]]);
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, R2lo, R2hi, hinv, ed);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2lo, R2hi, hinv, ed);
                     }
                 } else {
                     // own list overflowed: walk the whole window
                     for (int k = j; k < nstg; k += kLanes) {
                         V p = stg[k];
-                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2, R2lo, R2hi, hinv, ed);
+                        S.pair(tp.x - p.x, tp.y - p.y, tp.z - p.z, p.w, R2lo, R2hi, hinv, ed);
                     }
                 }
             }
@@ -499,13 +497,14 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             // and no evaluated pair lies between the supports at hh and hn: a
             // pair there has |r^2 - R^2| in the pair precision within
             // |4 hn^2 - 4 hh^2| plus the rounding of r^2 (below a quarter of
-            // the guard band) and of R^2.  Otherwise the target's own list, if
-            // valid for another pass and holding the new support, counts again.
+            // the guard band) and of R^2, so |r^2 - R2hi| within that plus
+            // the band.  Otherwise the target's own list, if valid for
+            // another pass and holding the new support, counts again.
             const bool small = !conv && halley && fabs(dh) < a.tol_take * hh;
             const double hcov = 2.0 * hn * (1.0 + 1.0 / 1024);
             const bool covered = hcov < fmin((double)Rt, s_Rw[w]);
             const double shell = fabs(4.0 * (hn * hn - hh * hh)) +
-                                 (double)edge_band<T>(tp, T(2) * (T)hh) +
+                                 2.0 * (double)edge_band<T>(tp, T(2) * (T)hh) +
                                  0x1p-20 * (4.0 * hh * hh);
             const bool same = covered && (double)emin > shell;
             const bool relist = lists && tlen <= kDTCap && hcov < (double)Rt;
