@@ -103,7 +103,7 @@ typedef struct {
     int32_t eos;        /* APR_EOS_* */
     double hfact;       /* h = hfact (m / rho)^(1/3); 1.2 for M4, 1.3 for Wendland C2 */
     double tol_h;       /* Newton stops when |dh| < tol_h h */
-    int32_t max_iter;   /* Newton iterations per particle */
+    int32_t max_iter;   /* Newton iterations per particle, 1 .. 1000 */
     int32_t kernel;     /* APR_KERNEL_M4 or APR_KERNEL_WC2 (support 2h either way) */
     double cs0;         /* sound speed (isothermal) or its value at R = r_ref */
     double q_cs;        /* locally isothermal: cs = cs0 (R / r_ref)^-q_cs, R cylindrical */

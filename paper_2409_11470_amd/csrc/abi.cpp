@@ -138,7 +138,8 @@ int check_params(const apr_params *p, std::string &why)
     if (p->precision != APR_FP32 && p->precision != APR_FP64) return why = "precision", 1;
     if (p->eos < 0 || p->eos > 2) return why = "eos", 1;
     if (p->kernel != APR_KERNEL_M4 && p->kernel != APR_KERNEL_WC2) return why = "kernel", 1;
-    if (!(p->hfact > 0) || !(p->tol_h > 0) || p->max_iter < 1) return why = "hfact/tol/max_iter", 1;
+    if (!(p->hfact > 0) || !(p->tol_h > 0) || p->max_iter < 1 || p->max_iter > 1000)
+        return why = "hfact/tol/max_iter", 1;
     if (!(p->m0 > 0)) return why = "m0", 1;
     for (int k = 0; k < 3; ++k)
         if (!(p->box_hi[k] > p->box_lo[k])) return why = "box", 1;

@@ -264,7 +264,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     const int t = 16 * w + (lane >> 2);   // this lane's target (4 lanes each)
     const bool mine = t < cnt;
     const bool valid = mine && (!ACT || a.active[s0 + t] != 0);
-    if (ACT && !__syncthreads_or(valid)) {
+    bool any_valid = true;
+    if (ACT) {
+        // block vote through the wavefront flags (no library reduction buffer)
+        const int v = __any(valid) ? 1 : 0;
+        if (lane == 0) s_flag[w] = v;
+        __syncthreads();
+        int f = 0;
+        for (int k = 0; k < kWaves; ++k) f |= s_flag[k];
+        any_valid = f != 0;
+        __syncthreads();  // s_flag is written again below
+    }
+    if (!any_valid) {
         // nothing to solve here: the cell's h_max from the stored h
         double m = wave_max64(mine ? a.h[s0 + t] : 0.0);
         if (lane_id() == 0) s_red[threadIdx.x / kWave] = m;
@@ -278,12 +289,15 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     }
 
     double h = valid ? a.h[s0 + t] : 0.0;
-    float Rt = 0.0f;  // reach of this target's list (2 sigma h, a 10% margin)
-    int itc = 0, tlen = 0;
+    // per target, in LDS (registers are scarce): the reach of its list (2
+    // sigma h), the list's length and the Newton passes taken
+    __shared__ float s_Rt[kCell];
+    __shared__ uint16_t s_itc[kCell];  // max_iter <= 1000
     // results are kept in s_out and stored once after the iteration (no global
     // writes inside the loop: every barrier waits for outstanding ones)
     // work counters of the block (thread 0), added once at the end
-    int c_restage = 0, c_direct = 0, c_windows = 0, c_passes = 0;
+    // (in LDS, thread 0's: registers are scarce)
+    __shared__ int c_restage, c_direct, c_windows, c_passes;
     bool done = !valid;
     bool recount = false;  // took an accepted step: count again at the new h
     V tp;
@@ -317,6 +331,12 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 s_wb.R2[k] = 16 * k < cnt ? (T)(rw * rw) : T(-1);
             }
             s_edge = 0;
+            c_restage = c_direct = c_windows = c_passes = 0;
+        }
+        if (threadIdx.x < kCell) {
+            s_Rt[threadIdx.x] = 0.0f;
+            s_itc[threadIdx.x] = 0;
+            s_tlen[threadIdx.x] = 0;
         }
     }
 
@@ -342,7 +362,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         if (walking && !use_pre) {
             __syncthreads();
             if (w == 0) walk_init(tr, tg, R, false, &s_walk);
-            if (search && pass > 0) c_restage += 1;
+            if (search && pass > 0 && threadIdx.x == 0) c_restage += 1;
         }
         for (int chunk = 0;; ++chunk) {
             bool last = true;
@@ -403,8 +423,8 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 if (!wave_busy) continue;
                 if (!lists) {
                     // this target's candidates within 2 sigma h (with margin)
-                    Rt = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
-                    const T Rtl = (T)Rt;
+                    if (j == 0) s_Rt[t] = done ? 0.0f : (float)(2.0 * (double)kSigma * h);
+                    wave_sync();
                     build_lists<T, false, kListLanes>(
                         nstg, stg, sub[w], kSubCap, &tls[0][0], kDTCap, s_tlen,
                         [&](int k) {
@@ -414,16 +434,16 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                             else { q.x = T(0); q.y = T(0); q.z = T(0); q.w = T(0); }
                             return q;
                         },
-                        [&](int k) { return __shfl(Rtl, 4 * k, kWave); },
+                        [&](int k) { return (T)s_Rt[16 * w + k]; },
                         [&](T d2, T Rs2, const V &) { return d2 < Rs2; },
                         [&](const V &q, T rk, int e) {
                             V p = stg[e];
                             T dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
                             return dx * dx + dy * dy + dz * dz < rk * rk;
                         });
-                    tlen = s_tlen[t < kCell ? t : 0];
                 }
                 if (done) continue;
+                const int tlen = s_tlen[t];
                 T hf = (T)h;
                 T hinv = T(1) / hf;
                 T R2 = T(4) * hf * hf;
@@ -452,12 +472,12 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                     }
                 }
             }
-            c_windows += nwin;
+            if (threadIdx.x == 0) c_windows += nwin;
             if (last) break;
         }
         search = false;
         lists = !multi && nwin == 1;
-        c_passes += 1;
+        if (threadIdx.x == 0) c_passes += 1;
         // ---- FP64 Newton step of this lane's target (its 4 lanes agree)
         double needR = 0.0;
         bool pending = false;
@@ -502,15 +522,18 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             // another pass and holding the new support, counts again.
             const bool small = !conv && halley && fabs(dh) < a.tol_take * hh;
             const double hcov = 2.0 * hn * (1.0 + 1.0 / 1024);
-            const bool covered = hcov < fmin((double)Rt, s_Rw[w]);
+            const double Rt = (double)s_Rt[t];
+            const int tlen = s_tlen[t];
+            const bool covered = hcov < fmin(Rt, s_Rw[w]);
             const double shell = fabs(4.0 * (hn * hn - hh * hh)) +
                                  2.0 * (double)edge_band<T>(tp, T(2) * (T)hh) +
                                  0x1p-20 * (4.0 * hh * hh);
             const bool same = covered && (double)emin > shell;
-            const bool relist = lists && tlen <= kDTCap && hcov < (double)Rt;
+            const bool relist = lists && tlen <= kDTCap && hcov < Rt;
             const bool take = small && (same || relist);
             conv = conv || take;
-            itc += 1;
+            const int itc = s_itc[t] + 1;
+            if (j == 0) s_itc[t] = (uint16_t)itc;
             if (conv || itc >= a.max_iter) {
                 done = true;
                 recount = take && !same;
@@ -532,7 +555,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             } else {
                 h = hn;
                 pending = true;
-                if (2.0 * hn > (double)Rt) lists = false;   // own list too short now
+                if (2.0 * hn > Rt) lists = false;   // own list too short now
                 if (2.0 * hn > s_Rw[w]) needR = 2.0 * (double)kSigma * hn;
             }
         }
@@ -543,7 +566,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
             const T hf = (T)h;
             const T R2 = T(4) * hf * hf;
             const T band = edge_band<T>(tp, T(2) * hf);
-            const int len = recount ? tlen : 0;
+            const int len = recount ? s_tlen[t] : 0;
             int c = 0;
             for (int k = j; k < len; k += kLanes) {
                 const V p = lds_ld4<T>(&stg[mylist[k]]);
@@ -602,7 +625,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         a.rho[i] = o.rho;
         a.omega[i] = o.om;
         if (a.nneigh) a.nneigh[i] = o.nn >= 0 ? o.nn : -1 - o.nn;
-        if (a.iters) a.iters[i] = itc;
+        if (a.iters) a.iters[i] = s_itc[t];
         if (a.dnn) a.dnn[i] = o.dnn;
         if (o.nn < 0) atomicAdd(&a.status[ST_NOCONV], 1);
         if (a.hlim > 0.0 && !(h < a.hlim)) atomicOr(&a.status[ST_RANGE], 1);

@@ -82,7 +82,16 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     // op.act (optional): only those targets get their sums; a cell without
     // one is left at once
     const bool valid = t < cnt && (!op.act || op.act[s0 + t] != 0);
-    if (op.act && !__syncthreads_or(valid)) return;
+    if (op.act) {
+        // block vote through per-wavefront flags (no library reduction buffer)
+        __shared__ int s_vote[kWaves];
+        const int v = __any(valid) ? 1 : 0;  // every lane votes, then lane 0 stores
+        if (lane == 0) s_vote[w] = v;
+        __syncthreads();
+        int f = 0;
+        for (int k = 0; k < kWaves; ++k) f |= s_vote[k];
+        if (!f) return;
+    }
     uint16_t *mylist = tls[t < kCell ? t : 0];
     const double R = 2.0 * (double)tg.hmax;  // targets' own supports
 
