@@ -184,11 +184,11 @@ __device__ inline bool cand_point(const vec4_t<T> *pm, const MetaBuf<T> &mb, int
 }
 
 // Counts, per candidate cell, the particles within reach of some
-// wavefront's targets (into sB).  Two cells per wavefront at a time, so that
-// two loads are in flight.
+// wavefront's targets (into sB), and keeps which lanes they are (smask).
+// Two cells per wavefront at a time, so that two loads are in flight.
 template <class T>
 __device__ inline void count_cands(const vec4_t<T> *pm, const MetaBuf<T> &mb, int nc,
-                                   const WaveBoxes<T> &B, int32_t *sB)
+                                   const WaveBoxes<T> &B, int32_t *sB, uint64_t *smask)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
     for (int ci = w; ci < nc; ci += 2 * kWaves) {
@@ -199,8 +199,34 @@ __device__ inline void count_cands(const vec4_t<T> *pm, const MetaBuf<T> &mb, in
         uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
         if (lane == 0) {
             sB[ci] = __popcll(m0);
-            if (c1 < nc) sB[c1] = __popcll(m1);
+            smask[ci] = m0;
+            if (c1 < nc) {
+                sB[c1] = __popcll(m1);
+                smask[c1] = m1;
+            }
         }
+    }
+}
+
+// Stages everything counted when it fits one window: the lanes counting
+// found (smask) at the offsets of the scan (sB), without testing the reach
+// again.
+template <class T>
+__device__ inline void stage_counted(const Tree &tr, const Geo &tg, const vec4_t<T> *pm,
+                                     const MetaBuf<T> &mb, const int32_t *sB,
+                                     const uint64_t *smask, int nc, vec4_t<T> *stg)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    for (int ci = w; ci < nc; ci += kWaves) {
+        const uint64_t m = smask[ci];
+        if (!((m >> lane) & 1ull)) continue;
+        const int off = sB[ci] + __popcll(m & lanemask_lt());
+        const int64_t b = (int64_t)mb.m[ci].b0 + lane;
+        vec4_t<T> p;
+        p.w = pm[b].w;
+        stage_pos<T>(tr, tg, mb.m[ci].wrap, b, p);
+        p.w = tag_mass(p.w, ci, lane);
+        stg[off] = p;
     }
 }
 
@@ -242,7 +268,11 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     __shared__ V stg[STAGE];
     __shared__ ListsMeta<T, kDTCap> s_lm;  // per-target lists, or candidates' metadata
     uint16_t(*tls)[kDTCap] = s_lm.tls;
-    __shared__ uint16_t sub[kWaves][kSubCap];
+    // the list builders' scratch; between counting and staging, which lanes
+    // of each candidate cell were counted
+    __shared__ __attribute__((aligned(16))) uint16_t sub[kWaves][kSubCap];
+    static_assert(sizeof(sub) >= kCandCap * sizeof(uint64_t), "counted-lane masks");
+    uint64_t *smask = reinterpret_cast<uint64_t *>(&sub[0][0]);
     __shared__ int s_ncand, s_total, s_flag[kWaves], s_tlen[kCell];
     __shared__ double s_red[kWaves];
     __shared__ int s_more, s_edge;
@@ -389,7 +419,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 if (!last) multi = true;
                 load_meta<T>(tr, tg, sA, nc, &s_lm.meta);
                 __syncthreads();
-                count_cands<T>(a.pm, s_lm.meta, nc, s_wb, sB);
+                count_cands<T>(a.pm, s_lm.meta, nc, s_wb, sB, smask);
                 __syncthreads();
                 if (w == 0) {
                     int tot = wave_excl_scan_lds(sB, nc);
@@ -403,7 +433,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
                 nwin = total > STAGE ? (total + STAGE - 1) / STAGE : 1;
                 lists = false;
                 if (nwin == 1) {
-                    stage_window<T, STAGE>(tr, tg, a.pm, s_lm.meta, sB, nc, total, s_wb, 0, stg);
+                    stage_counted<T>(tr, tg, a.pm, s_lm.meta, sB, smask, nc, stg);
                     __syncthreads();
                 }
             }
