@@ -137,8 +137,10 @@ int excl_scan(apr_ctx *c, const T *in, T *out, int64_t n, T *total_dev, const ch
     const std::string nm = std::string(tag) + (level ? "_" + std::to_string(level) : "");
     T *partial = wsa<T>(c, nm.c_str(), (size_t)nb + 1);
     if (!partial) return fail(c, APR_ERR_HIP, "scan workspace");
-    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
-                       in, n, partial);
+    // one tile: no earlier tiles to sum (k_scan_down reads none of partial)
+    if (nb > 1)
+        hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                           c->stream, in, n, partial);
     if (nb <= kScanTile) {
         hipLaunchKernelGGL(k_scan_down<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, c->stream,
                            in, out, n, partial, total_dev);

@@ -345,9 +345,13 @@ __global__ void k_quant(int64_t m, const uint32_t *slot, SArr s, Box b, double s
 // ------------------------------------------------------------ pairing tree
 // Element arrays (position i in the tree order): es[i] particle slot, lo[i],
 // hi[i] the range of its node.  Node statistics live at the node's start.
+// A depth takes four passes: min / max and coordinate sums, counts about
+// the cut, each element's side (then a scan of the sides), the partition,
+// which also clears the next depth's nodes (their own array: a left child
+// starts where its parent does, whose statistics the partition still reads).
 struct Node {
     int32_t mn[3], mx[3];
-    unsigned long long sum;
+    unsigned long long sum[3];
     uint32_t kc, keq;
     unsigned long long amin_c, amax_c, amin_c1, amax_c1;
     int32_t ax, kp;  // axis and left count, stored for the passes after the one that finds them
@@ -364,16 +368,13 @@ struct TreeArgs {
 
 __device__ inline bool active(const TreeArgs &a, int64_t i) { return a.hi[i] - a.lo[i] > 2; }
 
-__global__ void k_tree_init(TreeArgs a)
+__device__ inline void clear_node(Node &nd)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.m || a.lo[i] != i || !active(a, i)) return;
-    Node &nd = a.node[i];
     for (int k = 0; k < 3; ++k) {
         nd.mn[k] = INT32_MAX;
         nd.mx[k] = INT32_MIN;
+        nd.sum[k] = 0;
     }
-    nd.sum = 0;
     nd.kc = 0;
     nd.keq = 0;
     nd.amin_c = ~0ull;
@@ -393,37 +394,6 @@ __device__ inline bool wave_one_node(bool act, int32_t L, int *first)
     *first = __ffsll((unsigned long long)m) - 1;
     int32_t L0 = __shfl(L, *first, 64);
     return __all(!act || L == L0) != 0;
-}
-
-__global__ void k_tree_minmax(TreeArgs a)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = i < a.m && active(a, i);
-    int32_t L = act ? a.lo[i] : -1;
-    uint32_t p = act ? a.es[i] : 0u;
-    int first = 0;
-    if (wave_one_node(act, L, &first)) {
-        int32_t mn[3], mx[3];
-        for (int k = 0; k < 3; ++k) {
-            int32_t v = act ? a.q[k][p] : 0;
-            mn[k] = wave_reduce(act ? v : INT32_MAX, imin);
-            mx[k] = wave_reduce(act ? v : INT32_MIN, imax);
-        }
-        if (__lane_id() == first) {
-            Node &nd = a.node[L];
-            for (int k = 0; k < 3; ++k) {
-                atomicMin(&nd.mn[k], mn[k]);
-                atomicMax(&nd.mx[k], mx[k]);
-            }
-        }
-        return;
-    }
-    if (!act) return;
-    Node &nd = a.node[L];
-    for (int k = 0; k < 3; ++k) {
-        atomicMin(&nd.mn[k], a.q[k][p]);
-        atomicMax(&nd.mx[k], a.q[k][p]);
-    }
 }
 
 // Axis of the node's largest integer extent (ties to the lower axis), from
@@ -449,27 +419,39 @@ __device__ inline unsigned long long uadd64(unsigned long long a, unsigned long 
     return a + b;
 }
 
-// Sum of the coordinates along the node's axis.  Every element takes the axis
-// from the node's min / max itself; the node's first element stores it for
-// the later passes (no element reads it here).
-__global__ void k_tree_sum(TreeArgs a)
+__global__ void k_tree_minmax(TreeArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool act = i < a.m && active(a, i);
     int32_t L = act ? a.lo[i] : -1;
+    uint32_t p = act ? a.es[i] : 0u;
     int first = 0;
-    unsigned long long v = 0ull;
-    if (act) {
-        const int ax = node_axis(a.node[L]);
-        if (i == L) a.node[L].ax = ax;
-        v = (unsigned long long)a.q[ax][a.es[i]];
-    }
     if (wave_one_node(act, L, &first)) {
-        v = wave_reduce(v, uadd64);
-        if (__lane_id() == first) atomicAdd(&a.node[L].sum, v);
+        int32_t mn[3], mx[3];
+        unsigned long long sm[3];
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = act ? a.q[k][p] : 0;
+            mn[k] = wave_reduce(act ? v : INT32_MAX, imin);
+            mx[k] = wave_reduce(act ? v : INT32_MIN, imax);
+            sm[k] = wave_reduce(act ? (unsigned long long)v : 0ull, uadd64);
+        }
+        if (__lane_id() == first) {
+            Node &nd = a.node[L];
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&nd.mn[k], mn[k]);
+                atomicMax(&nd.mx[k], mx[k]);
+                atomicAdd(&nd.sum[k], sm[k]);
+            }
+        }
         return;
     }
-    if (act) atomicAdd(&a.node[L].sum, v);
+    if (!act) return;
+    Node &nd = a.node[L];
+    for (int k = 0; k < 3; ++k) {
+        atomicMin(&nd.mn[k], a.q[k][p]);
+        atomicMax(&nd.mx[k], a.q[k][p]);
+        atomicAdd(&nd.sum[k], (unsigned long long)a.q[k][p]);
+    }
 }
 
 __global__ void k_tree_count(TreeArgs a)
@@ -482,10 +464,14 @@ __global__ void k_tree_count(TreeArgs a)
     unsigned long long key = 0;
     if (act) {
         Node &nd = a.node[L];
+        // the axis from the completed min / max; the node's first element
+        // stores it for the later passes (no element reads it here)
+        const int ax = node_axis(nd);
+        if (i == L) nd.ax = ax;
         int64_t n = a.hi[i] - L;
-        int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
+        int64_t c = (int64_t)(nd.sum[ax] / (unsigned long long)n);
         uint32_t p = a.es[i];
-        int64_t v = a.q[nd.ax][p];
+        int64_t v = a.q[ax][p];
         key = ((unsigned long long)v << kIdBits) |
               ((unsigned long long)a.id[p] & ((1ull << kIdBits) - 1));
         lt = v < c;
@@ -535,7 +521,7 @@ struct Cut {
 __device__ inline Cut node_cut(const Node &nd, int64_t n)
 {
     Cut r;
-    int64_t c = (int64_t)(nd.sum / (unsigned long long)n);
+    int64_t c = (int64_t)(nd.sum[nd.ax] / (unsigned long long)n);
     int64_t k = nd.kc;
     unsigned long long amin = nd.amin_c, amax = nd.amax_c;
     if (k == 0) {  // nothing below the cut: move it up one step
@@ -564,9 +550,10 @@ __device__ inline Cut node_cut(const Node &nd, int64_t n)
 
 // Side of every element.  Each takes the node's cut itself; the node's first
 // element stores kp for the partition (no element reads it here).
-__global__ void k_tree_left(TreeArgs a, uint32_t *left)
+__global__ void k_tree_left(TreeArgs a, uint32_t *left, int32_t *more)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *more = 0;  // the partition after this pass sets it
     if (i >= a.m) return;
     if (!active(a, i)) {
         left[i] = 1u;  // leaves stay in place
@@ -590,7 +577,8 @@ __global__ void k_tree_left(TreeArgs a, uint32_t *left)
 }
 
 __global__ void k_tree_partition(TreeArgs a, const uint32_t *left, const uint32_t *lscan,
-                                 uint32_t *es2, int32_t *lo2, int32_t *hi2, int32_t *more)
+                                 uint32_t *es2, int32_t *lo2, int32_t *hi2, int32_t *more,
+                                 Node *next)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.m) return;
@@ -617,15 +605,19 @@ __global__ void k_tree_partition(TreeArgs a, const uint32_t *left, const uint32_
     es2[pos] = a.es[i];
     lo2[pos] = nl;
     hi2[pos] = nh;
-    if (nh - nl > 2) atomicOr(more, 1);
+    if (nh - nl > 2) {
+        if (pos == nl) clear_node(next[nl]);  // one element per child starts it
+        atomicOr(more, 1);
+    }
 }
 
-__global__ void k_tree_root(int64_t m, int32_t *lo, int32_t *hi)
+__global__ void k_tree_root(int64_t m, int32_t *lo, int32_t *hi, Node *node)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     lo[i] = 0;
     hi[i] = (int32_t)m;
+    if (i == 0 && m > 2) clear_node(node[0]);
 }
 
 // Centre of mass of a merging pair along axis k (equal masses, Sec. 2.3).
@@ -883,9 +875,9 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                            wsa<uint32_t>(c, "sm_es1", (size_t)n)};
         int32_t *lo[2] = {wsa<int32_t>(c, "sm_lo0", (size_t)n), wsa<int32_t>(c, "sm_lo1", (size_t)n)};
         int32_t *hi[2] = {wsa<int32_t>(c, "sm_hi0", (size_t)n), wsa<int32_t>(c, "sm_hi1", (size_t)n)};
-        Node *node = wsa<Node>(c, "sm_node", (size_t)n);
+        Node *node[2] = {wsa<Node>(c, "sm_node0", (size_t)n), wsa<Node>(c, "sm_node1", (size_t)n)};
         int32_t *more = imax + 1;
-        if (!cand || !keys || !q[2] || !es[1] || !lo[1] || !hi[1] || !node)
+        if (!cand || !keys || !q[2] || !es[1] || !lo[1] || !hi[1] || !node[0] || !node[1])
             return fail(c, APR_ERR_HIP, "merge workspace");
         double sc[3];
         for (int k = 0; k < 3; ++k) sc[k] = kQuant / b.L[k];
@@ -923,7 +915,7 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             APR_HIP(c, hipMemcpyAsync(es[0], cand, (size_t)m * 4, hipMemcpyDeviceToDevice,
                                       c->stream));
             hipLaunchKernelGGL(k_tree_root, dim3(grid(m)), dim3(256), 0, c->stream, m, lo[0],
-                               hi[0]);
+                               hi[0], node[0]);
             APR_LAUNCHED(c);
             // Depths run in batches between host checks of `more` (set by
             // the last partition when a node still holds more than two
@@ -943,19 +935,18 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
                     ta.hi = hi[cur];
                     for (int k = 0; k < 3; ++k) ta.q[k] = q[k];
                     ta.id = s->id;
-                    ta.node = node;
+                    ta.node = node[cur];
                     unsigned g = grid(m);
-                    hipLaunchKernelGGL(k_tree_init, dim3(g), dim3(256), 0, c->stream, ta);
                     hipLaunchKernelGGL(k_tree_minmax, dim3(g), dim3(256), 0, c->stream, ta);
-                    hipLaunchKernelGGL(k_tree_sum, dim3(g), dim3(256), 0, c->stream, ta);
                     hipLaunchKernelGGL(k_tree_count, dim3(g), dim3(256), 0, c->stream, ta);
-                    hipLaunchKernelGGL(k_tree_left, dim3(g), dim3(256), 0, c->stream, ta, flag);
+                    hipLaunchKernelGGL(k_tree_left, dim3(g), dim3(256), 0, c->stream, ta, flag,
+                                       more);
                     APR_LAUNCHED(c);
                     rc = exclusive_scan_u32(c, flag, scan, m, nullptr);
                     if (rc) return rc;
-                    APR_HIP(c, hipMemsetAsync(more, 0, 4, c->stream));
                     hipLaunchKernelGGL(k_tree_partition, dim3(g), dim3(256), 0, c->stream, ta,
-                                       flag, scan, es[1 - cur], lo[1 - cur], hi[1 - cur], more);
+                                       flag, scan, es[1 - cur], lo[1 - cur], hi[1 - cur], more,
+                                       node[1 - cur]);
                     APR_LAUNCHED(c);
                     cur = 1 - cur;
                 }
