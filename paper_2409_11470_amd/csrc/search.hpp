@@ -610,23 +610,18 @@ __device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub
             T bex = T(0.5) * (hix - lox), bey = T(0.5) * (hiy - loy), bez = T(0.5) * (hiz - loz);
             int nsub = 0;
             wave_sync();
-            // two blocks of 64 entries per step: both reads in flight, the
-            // hits appended in entry order
-            auto test = [&](int idx) -> bool {
-                if (idx >= nstg) return false;
-                // FULL: box_ok reads the w component too (one vector read)
-                const vec4_t<T> p = FULL ? lds_ld4<T>(&stg[idx]) : stg[idx];
-                return box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2, p);
-            };
-            for (int base = 0; base < nstg; base += 2 * kWave) {
-                const int i0 = base + lane, i1 = i0 + kWave;
-                const bool h0 = test(i0), h1 = test(i1);
-                const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
-                const int ps0 = nsub + __popcll(m0 & lanemask_lt());
-                const int ps1 = nsub + __popcll(m0) + __popcll(m1 & lanemask_lt());
-                if (h0 && ps0 < subcap) sub[ps0] = (uint16_t)i0;
-                if (h1 && ps1 < subcap) sub[ps1] = (uint16_t)i1;
-                nsub += __popcll(m0) + __popcll(m1);
+            for (int base = 0; base < nstg; base += kWave) {
+                int idx = base + lane;
+                bool hit = false;
+                if (idx < nstg) {
+                    // FULL: box_ok reads the w component too (one vector read)
+                    const vec4_t<T> p = FULL ? lds_ld4<T>(&stg[idx]) : stg[idx];
+                    hit = box_ok(pt_box_d2<T>(p.x, p.y, p.z, bcx, bcy, bcz, bex, bey, bez), Rs2, p);
+                }
+                uint64_t m = __ballot(hit);
+                const int ps = nsub + __popcll(m & lanemask_lt());
+                if (hit && ps < subcap) sub[ps] = (uint16_t)idx;
+                nsub += __popcll(m);
             }
             wave_sync();
             if (nsub > subcap) {
@@ -636,22 +631,19 @@ __device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub
             }
             uint16_t *L = tls + (size_t)(16 * w + k) * cap;
             constexpr uint64_t gmask = G == 16 ? 0xffffull : 0xffull;
-            const uint32_t below = (1u << j) - 1u;
-            // two groups of G entries per step, as above
-            for (int base = 0; base < nsub; base += 2 * G) {
-                const int k0 = base + j, k1 = k0 + G;
-                const bool v0 = k0 < nsub && act, v1 = k1 < nsub && act;
-                const int e0 = v0 ? (int)sub[k0] : 0, e1 = v1 ? (int)sub[k1] : 0;
-                // both tests run (entry 0 stands in for a missing one): no branch
-                // between the two reads
-                const bool h0 = accept(tp, rk, e0) & v0, h1 = accept(tp, rk, e1) & v1;
-                const uint32_t gm0 = (uint32_t)((__ballot(h0) >> (G * g)) & gmask);
-                const uint32_t gm1 = (uint32_t)((__ballot(h1) >> (G * g)) & gmask);
-                const int p0 = len + __popc(gm0 & below);
-                const int p1 = len + __popc(gm0) + __popc(gm1 & below);
-                if (h0 && p0 < cap) L[p0] = (uint16_t)e0;
-                if (h1 && p1 < cap) L[p1] = (uint16_t)e1;
-                len += __popc(gm0) + __popc(gm1);
+            for (int base = 0; base < nsub; base += G) {
+                int k0 = base + j;
+                bool hit = false;
+                int e = 0;
+                if (k0 < nsub && act) {
+                    e = sub[k0];
+                    hit = accept(tp, rk, e);
+                }
+                uint64_t m = __ballot(hit);
+                uint32_t gm = (uint32_t)((m >> (G * g)) & gmask);
+                int p = len + __popc(gm & ((1u << j) - 1u));
+                if (hit && p < cap) L[p] = (uint16_t)e;
+                len += __popc(gm);
             }
         }
         if (j == 0) tlen[16 * w + k] = len;
