@@ -82,7 +82,7 @@ MEASURED_TRAFFIC = {
         bytes_per_launch=141401626,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
-        sha256="ceee9ca4b8ddcb44c3afa172fd7e1b5ee8ee0c2c3127a17992a7c23ea55dd380"),
+        sha256="326ce26339d3d910a3a73b48ce3818f42dd48b53eb206f9ed60ca49b6df526df"),
 }
 
 

@@ -9,14 +9,16 @@
 //   d2W/dh2 = (12 f + 8 q f' + q^2 f'')/(pi h^5),
 //   h <- h - (F/F') / (1 - F F''/(2 F'^2))   (plain Newton if |F F''/(2 F'^2)| >= 1/2).
 // It stops when |dh| < tol h; the h reported is the one the last sums were
-// taken at.  A Halley step with |dh| < sqrt(tol) h also ends it when the
-// target's own neighbour list covers the new support: its remaining error is
-// of order (dh/h)^3 h, far below tol h, so h + dh is reported without
-// another pass, with rho and the h-derivative sum of Omega carried to it by
-// their Taylor series (rho to second order, errors of order (dh/h)^3 and
-// (dh/h)^2 <= tol) and the neighbour count taken again over the list at
-// h + dh.  If F' <= 0 the step is h_fact (m/rho_sum)^(1/3); every step is
-// clamped to [h/2, 2h].
+// taken at.  A Halley step with |dh| < sqrt(tol) h also ends it: its
+// remaining error is of order (dh/h)^3 h, far below tol h, so h + dh is
+// reported without another pass, with rho and the h-derivative sum of Omega
+// carried to it by their Taylor series (rho to second order, errors of order
+// (dh/h)^3 and (dh/h)^2 <= tol).  The neighbour count reported is the one at
+// h + dh: the pass's own when no pair it evaluated lies between the two
+// supports and it evaluated every candidate within 2 (h + dh); else one
+// taken again over the target's list, if that list covers the new support;
+// else the step waits for another pass.  If F' <= 0 the step is
+// h_fact (m/rho_sum)^(1/3); every step is clamped to [h/2, 2h].
 //
 // Membership r_ab < 2 h_a is tested in the pair precision and, inside a
 // guard band about the edge, decided again in FP64 on absolute positions
@@ -329,7 +331,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     // (in LDS, thread 0's: registers are scarce)
     __shared__ int c_restage, c_direct, c_windows, c_passes;
     bool done = !valid;
-    bool recount = false;  // took an accepted step: count again at the new h
+    bool recount = false;  // took an accepted step that counts again at the new h
     V tp;
     if (valid) tp = a.pm[s0 + t];
     else { tp.x = T(0); tp.y = T(0); tp.z = T(0); tp.w = T(0); }
