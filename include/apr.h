@@ -158,7 +158,9 @@ int apr_build_cells(apr_ctx *ctx, apr_state *s, int64_t *perm);
  *   rho_a = sum_b m_b W(|x_a - x_b|, h_a)  (b = a included),
  *   h_a = hfact (m_a / rho_a)^(1/3)
  * by Newton steps with Halley's second-derivative correction from the
- * current h (until |dh| < tol_h h); writes the converged h into s->h and
+ * current h (until |dh| < tol_h h, or a Halley step below sqrt(tol_h) h,
+ * whose h + dh is written with rho and Omega carried to it by their Taylor
+ * series); writes the converged h into s->h and
  *   Omega_a = 1 + h_a / (3 rho_a) sum_b m_b dW_ab/dh_a.
  * rho, omega: [n] (float or double); nneigh (optional) counts b with
  * r_ab < 2 h_a at the h written, self included; iters (optional) Newton
