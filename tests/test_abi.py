@@ -91,3 +91,26 @@ def test_invalid_params_rejected_without_gpu_work(L):
     p = A.make_params(m0=-1.0)
     ptr = ctypes.c_void_p()
     assert L.apr_ctx_create(ctypes.byref(ptr), ctypes.byref(p), None) == A.APR_ERR_INVALID
+
+
+def test_newton_iteration_limit_validated_without_gpu_work(L):
+    # max_iter is 1 .. 1000 (the density kernel keeps each target's pass count
+    # in 16 bits)
+    import ctypes
+    import paper_2409_11470_amd as A
+    for bad in (0, 1001):
+        p = A.make_params(m0=1.0, max_iter=bad)
+        ptr = ctypes.c_void_p()
+        assert L.apr_ctx_create(ctypes.byref(ptr), ctypes.byref(p), None) == A.APR_ERR_INVALID
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU only: the multi-GPU request exits with a message before any GPU work
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
