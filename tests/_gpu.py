@@ -254,3 +254,27 @@ def ball_vjp_check(key, st, p, prec, centre, ntarget=16, seed=0, gtol=None):
     if gtol is not None:
         assert ex < gtol and em < gtol, (ex, em, T.size, S.size)
     return ex, em
+
+
+def exact_counts(st, p, targets, h):
+    """Neighbours of each target (self included) within 2 h[target] by the FP64
+    predicate of the oracle: r^2 < (2h)^2 with r^2 = dx dx + dy dy + dz dz, no
+    fused operations, dx = x_a - x_b at its minimum image in a periodic box.
+    Candidates come from a k-d tree with a slightly larger radius; the
+    predicate decides."""
+    pos = np.stack([st["x"], st["y"], st["z"]], 1)
+    per = bool(p.get("periodic", False))
+    lo = np.asarray(p.get("lo", (0, 0, 0)), float)
+    L = np.asarray(p.get("hi", (1, 1, 1)), float) - lo
+    tree = cKDTree(pos - lo if per else pos, boxsize=L if per else None)
+    out = np.empty(len(targets), np.int64)
+    for k, a in enumerate(targets):
+        R = 2.0 * float(h[a])
+        cand = np.asarray(tree.query_ball_point((pos[a] - lo) if per else pos[a],
+                                                R * (1.0 + 1e-9)), np.int64)
+        d = pos[a] - pos[cand]
+        if per:
+            d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+        r2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+        out[k] = int(np.sum(r2 < R * R))
+    return out

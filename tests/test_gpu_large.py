@@ -12,7 +12,7 @@ import torch
 import oracle
 import paper_2409_11470_amd as A
 import workloads as W
-from _gpu import gpu_density, gpu_forces, oracle_balls, params_for
+from _gpu import exact_counts, gpu_density, gpu_forces, oracle_balls, params_for
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,11 @@ def test_planet_disc_1M_sampled(prec):
     gf = gpu_forces(ctx, ds, rho, om)
     tg, od, of = oracle_balls(st, p, 6, 48, seed=21)
     _check(g, gf, tg, od, of, prec)
+    # the density kernel's own neighbour counts at the h it returned, exactly
+    # (the disc has cells whose candidates span several staging windows, where
+    # an accepted Halley step keeps the pass's count only when no pair lies
+    # between the supports)
+    assert np.array_equal(g["nneigh"][tg], exact_counts(st, p, tg, g["h"]))
 
 
 @pytest.fixture(scope="module")
