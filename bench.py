@@ -82,7 +82,7 @@ MEASURED_TRAFFIC = {
         bytes_per_launch=141401626,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
-        sha256="326ce26339d3d910a3a73b48ce3818f42dd48b53eb206f9ed60ca49b6df526df"),
+        sha256="b57ef0b46b120dbd308f2f2382a1fa4167597c081bd1f9d016d98f26e9a07902"),
 }
 
 

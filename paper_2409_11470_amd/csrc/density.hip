@@ -160,14 +160,6 @@ struct DSum {
             dmin = dmin < rr ? dmin : rr;
         }
     }
-    __device__ void reduce16()
-    {
-        w.reduce16();
-        d.reduce16();
-        k = wsum16(k);
-        cnt = wsum16(cnt);
-        dmin = wmin16(dmin);
-    }
 };
 
 // Candidate particle `lane` of candidate cell ci in the target cell's frame;

@@ -33,7 +33,6 @@ constexpr int kWaves = kSearchThreads / kWave;
 constexpr int kRestGrid = 256;   // workgroups of a search kernel's REST launch
 constexpr int kCandCap = 256;    // candidate cells per chunk of the walk
 constexpr int kSubCap = 512;     // staged candidates per sub-block
-constexpr int kGroup = 16;       // lanes per target (sub-block layout)
 constexpr int kListLanes = 16;   // lanes per target while building the per-target lists
 constexpr int kLanes = 4;        // lanes per target (one target per lane group of 4)
 constexpr int kTCap = 128;       // per-target candidate list (u16 LDS indices)
@@ -124,28 +123,6 @@ __device__ inline float slot_bits(float, int64_t i) { return __int_as_float((int
 __device__ inline double slot_bits(double, int64_t i) { return __longlong_as_double(i); }
 __device__ inline int64_t slot_of(float v) { return (int64_t)__float_as_int(v); }
 __device__ inline int64_t slot_of(double v) { return (int64_t)__double_as_longlong(v); }
-
-// Appends the lanes' hits to a per-group (16-lane) list; len is group-uniform.
-__device__ inline void group_append(bool hit, uint16_t e, uint16_t *list, int &len)
-{
-    int grp = lane_id() >> 4, j = lane_id() & 15;
-    uint64_t m = __ballot(hit);
-    uint32_t gm = (uint32_t)(m >> (16 * grp)) & 0xffffu;
-    int pos = len + __popc(gm & ((1u << j) - 1u));
-    if (hit && pos < kTCap) list[pos] = e;
-    len += __popc(gm);
-}
-
-// Appends the lanes' hits to a per-target (4-lane) list; len is group-uniform.
-__device__ inline void quad_append(bool hit, uint16_t e, uint16_t *list, int cap, int &len)
-{
-    int q = lane_id() >> 2, j = lane_id() & 3;
-    uint64_t m = __ballot(hit);
-    uint32_t gm = (uint32_t)(m >> (4 * q)) & 0xfu;
-    int pos = len + __popc(gm & ((1u << j) - 1u));
-    if (hit && pos < cap) list[pos] = e;
-    len += __popc(gm);
-}
 
 // Resumable depth-first walk of the cell tree by one wavefront, handing out
 // the candidate cells in chunks (in Morton order, the order of the cells), so
@@ -279,34 +256,6 @@ __device__ inline T pt_box_d2(T x, T y, T z, T cx, T cy, T cz, T ex, T ey, T ez)
     gy = gy > T(0) ? gy : T(0);
     gz = gz > T(0) ? gz : T(0);
     return gx * gx + gy * gy + gz * gz;
-}
-
-template <class T>
-__device__ inline T wmax16(T v)
-{
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o, kGroup);
-        v = v > u ? v : u;
-    }
-    return v;
-}
-template <class T>
-__device__ inline T wmin16(T v)
-{
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o, kGroup);
-        v = v < u ? v : u;
-    }
-    return v;
-}
-template <class T>
-__device__ inline T wsum16(T v)
-{
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, kGroup);
-    return v;
 }
 
 // Reductions over the 4 lanes of a target.
@@ -543,7 +492,6 @@ struct Acc {
             s = t;
         }
     }
-    __device__ void reduce16() { reduce<kGroup>(); }
     __device__ double value() const { return (double)s - (double)c; }
 };
 
