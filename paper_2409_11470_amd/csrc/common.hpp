@@ -159,6 +159,83 @@ __device__ inline int lane_id() { return __lane_id(); }
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
+// The wavefront's index in its workgroup, as a scalar (uniform) value.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)); }
+// A value every lane of the wavefront holds alike (an LDS broadcast read),
+// moved to a scalar register.
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The value of lane (lane ^ O), for every lane of the wavefront, with no
+// address register (a ds_bpermute needs one per distance, and the compiler
+// keeps those live across a whole kernel): O = 1, 2 quad permutations and
+// O = 8 a rotation of the 16-lane row by half its length (DPP), O = 4 the
+// swizzle's xor mode, O = 16 and 32 gfx950's swaps of odd and even rows and
+// of the wavefront's halves.  Every lane must be active.
+template <int O>
+__device__ inline int lane_xor_bits(int v)
+{
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8 || O == 16 || O == 32, "lane distance");
+    if constexpr (O == 1) {
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (O == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (O == 4) {
+        return __builtin_amdgcn_ds_swizzle(v, 0x101F);  // and 0x1f, or 0, xor 4
+    } else if constexpr (O == 8) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (O == 16) {
+        // the swap leaves rows (r0, r0, r2, r2) in the first result and
+        // (r1, r1, r3, r3) in the second
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane_id() & 16) ? (int)p[0] : (int)p[1];
+    } else {
+        // halves (lo, lo) in the first result, (hi, hi) in the second
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane_id() & 32) ? (int)p[0] : (int)p[1];
+    }
+}
+// For O = 16 or 32: the values of the two lanes (lane & ~O, lane | O), in
+// that order, in every lane: an operation on the pair then gives partner
+// lanes the same result, with one swap and no select.
+template <int O>
+__device__ inline void lane_pair_bits(int v, int &lo, int &hi)
+{
+    static_assert(O == 16 || O == 32, "row or half swap");
+    const auto p = O == 16 ? __builtin_amdgcn_permlane16_swap(v, v, false, false)
+                           : __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    lo = (int)p[0];
+    hi = (int)p[1];
+}
+template <int O>
+__device__ inline void lane_pair(float v, float &lo, float &hi)
+{
+    int a, b;
+    lane_pair_bits<O>(__float_as_int(v), a, b);
+    lo = __int_as_float(a);
+    hi = __int_as_float(b);
+}
+template <int O>
+__device__ inline void lane_pair(double v, double &lo, double &hi)
+{
+    const long long x = __double_as_longlong(v);
+    int a0, b0, a1, b1;
+    lane_pair_bits<O>((int)(x & 0xffffffffll), a0, b0);
+    lane_pair_bits<O>((int)(x >> 32), a1, b1);
+    lo = __longlong_as_double(((long long)a1 << 32) | (long long)(unsigned)a0);
+    hi = __longlong_as_double(((long long)b1 << 32) | (long long)(unsigned)b0);
+}
+template <int O>
+__device__ inline int lane_xor(int v) { return lane_xor_bits<O>(v); }
+template <int O>
+__device__ inline float lane_xor(float v) { return __int_as_float(lane_xor_bits<O>(__float_as_int(v))); }
+template <int O>
+__device__ inline double lane_xor(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor_bits<O>((int)(b & 0xffffffffll)), hi = lane_xor_bits<O>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // XCD-aware mapping of a 1-D grid: workgroup b runs on XCD b % 8, so give XCD
 // k a contiguous range of work items (neighbouring cells share candidates and
 // hit the same L2).

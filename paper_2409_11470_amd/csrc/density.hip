@@ -80,6 +80,8 @@ struct DensArgs {
     float *hmax_new;      // per cell
     CandList pre;         // candidate cells walked ahead (radius 2 sigma hmax)
     double m0, hfact, tol;
+    double m0_pi, hfact3; // m0 / pi and hfact^3, computed once on the host (kept in
+                          // scalar registers, not in vector registers across the kernel)
     double tol_take;      // sqrt(tol): a Halley step below it ends the iteration
     double hlim;          // periodic boxes: h must stay below this (0: no limit)
     int max_iter;
@@ -184,7 +186,7 @@ template <class T>
 __device__ inline void count_cands(const vec4_t<T> *pm, const MetaBuf<T> &mb, int nc,
                                    const WaveBoxes<T> &B, int32_t *sB, uint64_t *smask)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int w = wave_id(), lane = lane_id();
     for (int ci = w; ci < nc; ci += 2 * kWaves) {
         const int c1 = ci + kWaves;
         vec4_t<T> p0, p1;
@@ -210,7 +212,7 @@ __device__ inline void stage_counted(const Tree &tr, const Geo &tg, const vec4_t
                                      const MetaBuf<T> &mb, const int32_t *sB,
                                      const uint64_t *smask, int nc, vec4_t<T> *stg)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int w = wave_id(), lane = lane_id();
     for (int ci = w; ci < nc; ci += kWaves) {
         const uint64_t m = smask[ci];
         if (!((m >> lane) & 1ull)) continue;
@@ -235,7 +237,7 @@ __device__ inline void stage_window(const Tree &tr, const Geo &tg, const vec4_t<
                                     const MetaBuf<T> &mb, const int32_t *sB, int nc, int total,
                                     const WaveBoxes<T> &B, int w0, vec4_t<T> *stg)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int w = wave_id(), lane = lane_id();
     for (int ci = w; ci < nc; ci += kWaves) {
         int o0 = sB[ci], o1 = ci + 1 < nc ? sB[ci + 1] : total;
         if (o1 <= w0 || o0 >= w0 + STAGE || o1 == o0) continue;
@@ -284,7 +286,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
-    const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
+    const int w = wave_id(), lane = lane_id(), j = lane & 3;
     const int t = 16 * w + (lane >> 2);   // this lane's target (4 lanes each)
     const bool mine = t < cnt;
     const bool valid = mine && (!ACT || a.active[s0 + t] != 0);
@@ -302,7 +304,7 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
     if (!any_valid) {
         // nothing to solve here: the cell's h_max from the stored h
         double m = wave_max64(mine ? a.h[s0 + t] : 0.0);
-        if (lane_id() == 0) s_red[threadIdx.x / kWave] = m;
+        if (lane_id() == 0) s_red[wave_id()] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
             double hm = 0.0;
@@ -515,12 +517,12 @@ __device__ __forceinline__ void density_cell(const DensArgs<T> &a, const int64_t
         if (!done) {
             const double W = S.w.value(), D = S.d.value();
             const double hh = (double)(T)h;
-            const double hi = 1.0 / hh, c0 = (a.m0 / kPi) * hi * hi * hi;
+            const double hi = 1.0 / hh, c0 = a.m0_pi * hi * hi * hi;
             const double ma = a.m0 * (double)tp.w;
             const double rhos = c0 * W;                      // rho_sum(hh)
             const double drho = -c0 * hi * D;                // d rho_sum / dh
             const double d2rho = c0 * hi * hi * (double)S.k; // d2 rho_sum / dh2
-            const double rhoh = ma * (a.hfact * a.hfact * a.hfact) * hi * hi * hi;
+            const double rhoh = ma * a.hfact3 * hi * hi * hi;
             const double F = rhos - rhoh, dF = drho + 3.0 * rhoh * hi;
             double hn;
             bool halley = false;
@@ -773,6 +775,8 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.pre = pre;
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
+        a.m0_pi = c->p.m0 / kPi;
+        a.hfact3 = c->p.hfact * c->p.hfact * c->p.hfact;
         a.tol = c->p.tol_h;
         a.tol_take = std::sqrt(c->p.tol_h);
         a.hlim = hlim;
@@ -794,6 +798,8 @@ int density(apr_ctx *c, apr_state *s, void *rho, void *omega, int32_t *nneigh, i
         a.pre = pre;
         a.m0 = c->p.m0;
         a.hfact = c->p.hfact;
+        a.m0_pi = c->p.m0 / kPi;
+        a.hfact3 = c->p.hfact * c->p.hfact * c->p.hfact;
         a.tol = c->p.tol_h;
         a.tol_take = std::sqrt(c->p.tol_h);
         a.hlim = hlim;

@@ -77,7 +77,7 @@ __device__ __forceinline__ void gather_cell(const Tree &tr, const OP &op, const 
     const Geo tg = tr.lev[0][cell];
     const int32_t s0 = tr.cs[cell];
     const int cnt = tr.cs[cell + 1] - s0;
-    const int w = threadIdx.x / kWave, lane = lane_id(), j = lane & 3;
+    const int w = wave_id(), lane = lane_id(), j = lane & 3;
     const int t = 16 * w + (lane >> 2);  // this lane's target (4 lanes each)
     // op.act (optional): only those targets get their sums; a cell without
     // one is left at once

@@ -226,14 +226,18 @@ __device__ inline int wave_excl_scan_lds(int32_t *cnt, int n)
     for (int base = 0; base < n; base += kWave) {
         int i = base + lane;
         int v = i < n ? cnt[i] : 0;
+        // inclusive scan by DPP: within each 16-lane row by shifts of 1, 2,
+        // 4, 8 (lanes with no source add 0), then row 0's total into row 1
+        // and row 2's into row 3, then lane 31's prefix into rows 2 and 3
         int incl = v;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            int t = __shfl_up(incl, o, kWave);
-            if (lane >= o) incl += t;
-        }
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xF, 0xF, false);  // row_shr:1
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xF, 0xF, false);  // row_shr:2
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xF, 0xF, false);  // row_shr:4
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xF, 0xF, false);  // row_shr:8
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xA, 0xF, false);  // row_bcast:15
+        incl += __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xC, 0xF, false);  // row_bcast:31
         if (i < n) cnt[i] = carry + incl - v;
-        carry += __shfl(incl, kWave - 1, kWave);
+        carry += __builtin_amdgcn_readlane(incl, kWave - 1);
     }
     wave_sync();
     return carry;
@@ -262,46 +266,73 @@ __device__ inline T pt_box_d2(T x, T y, T z, T cx, T cy, T cz, T ex, T ey, T ez)
 template <class T>
 __device__ inline T sum4(T v)
 {
-    v += __shfl_xor(v, 1, kLanes);
-    v += __shfl_xor(v, 2, kLanes);
+    v += lane_xor<1>(v);
+    v += lane_xor<2>(v);
     return v;
 }
 template <class T>
 __device__ inline T min4(T v)
 {
-    T u = __shfl_xor(v, 1, kLanes);
+    T u = lane_xor<1>(v);
     v = v < u ? v : u;
-    u = __shfl_xor(v, 2, kLanes);
+    u = lane_xor<2>(v);
     return v < u ? v : u;
 }
 template <class T>
 __device__ inline T max4(T v)
 {
-    T u = __shfl_xor(v, 1, kLanes);
+    T u = lane_xor<1>(v);
     v = v > u ? v : u;
-    u = __shfl_xor(v, 2, kLanes);
+    u = lane_xor<2>(v);
     return v > u ? v : u;
 }
 // Max / min over the whole wavefront.
+// One butterfly step of a max / min over lanes O apart: within rows the
+// partner's value (op(own, partner)), across rows and halves the ordered
+// pair (so partner lanes agree bitwise).
+template <int O, bool MAX, class T>
+__device__ inline T minmax_step(T v)
+{
+    auto op = [](T x, T y) { return MAX ? (x > y ? x : y) : (x < y ? x : y); };
+    if constexpr (O >= 16) {
+        T lo, hi;
+        lane_pair<O>(v, lo, hi);
+        return op(lo, hi);
+    } else {
+        return op(v, lane_xor<O>(v));
+    }
+}
+// Max / min over the lanes j, j + G, j + 2G, ... of the wavefront (G = 1: over
+// all of it), which every lane ends with.
+template <int G, bool MAX, class T>
+__device__ inline T wminmax_lanes(T v)
+{
+    if constexpr (G <= 1) v = minmax_step<1, MAX>(v);
+    if constexpr (G <= 2) v = minmax_step<2, MAX>(v);
+    if constexpr (G <= 4) v = minmax_step<4, MAX>(v);
+    if constexpr (G <= 8) v = minmax_step<8, MAX>(v);
+    if constexpr (G <= 16) v = minmax_step<16, MAX>(v);
+    return minmax_step<32, MAX>(v);
+}
+template <int G, class T>
+__device__ inline T wmax_lanes(T v)
+{
+    return wminmax_lanes<G, true>(v);
+}
+template <int G, class T>
+__device__ inline T wmin_lanes(T v)
+{
+    return wminmax_lanes<G, false>(v);
+}
 template <class T>
 __device__ inline T wave_max64(T v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o, kWave);
-        v = v > u ? v : u;
-    }
-    return v;
+    return wmax_lanes<1>(v);
 }
 template <class T>
 __device__ inline T wave_min64(T v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o, kWave);
-        v = v < u ? v : u;
-    }
-    return v;
+    return wmin_lanes<1>(v);
 }
 
 // The targets of each wavefront (16 of a cell's 64) as a box [lo, hi] in the
@@ -325,7 +356,7 @@ __device__ inline void wave_box(WaveBoxes<T> *B, bool valid, T x, T y, T z)
     T hx = wave_max64(valid ? x : -big), hy = wave_max64(valid ? y : -big),
       hz = wave_max64(valid ? z : -big);
     if (lane_id() == 0) {
-        int w = threadIdx.x / kWave;
+        int w = wave_id();
         B->lo[w][0] = lx; B->lo[w][1] = ly; B->lo[w][2] = lz;
         B->hi[w][0] = hx; B->hi[w][1] = hy; B->hi[w][2] = hz;
     }
@@ -420,9 +451,13 @@ __device__ inline void stage_pos(const Tree &tr, const Geo &tg, uint32_t wrap, i
 {
 #pragma clang fp contract(off)
     const Box &bx = tr.box;
+    // the image shift is selected first and then added, so that a wrap
+    // common to the wavefront (a scalar) costs a select, not a branch that
+    // would wait for each coordinate's load in turn
     auto img = [&](double v, int k) {
-        uint32_t c = (wrap >> (2 * k)) & 3u;
-        return c == 1u ? v + bx.L[k] : (c == 2u ? v - bx.L[k] : v);
+        const uint32_t c = (wrap >> (2 * k)) & 3u;
+        const double sh = c == 1u ? bx.L[k] : (c == 2u ? -bx.L[k] : 0.0);
+        return v + sh;
     };
     p.x = (T)(img(tr.px[b], 0) - tg.cx);
     p.y = (T)(img(tr.py[b], 1) - tg.cy);
@@ -482,41 +517,21 @@ struct Acc {
     template <int W>
     __device__ void reduce()
     {
-#pragma unroll
-        for (int o = W / 2; o > 0; o >>= 1) {
-            T s2 = __shfl_xor(s, o, W), c2 = __shfl_xor(c, o, W);
-            T t = s + s2;
-            T bb = t - s;
-            T err = (s - (t - bb)) + (s2 - bb);
-            c = c + c2 - err;
-            s = t;
-        }
+        static_assert(W == 4, "4 lanes per target");
+        combine(lane_xor<2>(s), lane_xor<2>(c));
+        combine(lane_xor<1>(s), lane_xor<1>(c));
+    }
+    __device__ void combine(T s2, T c2)
+    {
+        T t = s + s2;
+        T bb = t - s;
+        T err = (s - (t - bb)) + (s2 - bb);
+        c = c + c2 - err;
+        s = t;
     }
     __device__ double value() const { return (double)s - (double)c; }
 };
 
-// Min / max over the groups of G lanes of a wavefront (every lane ends with
-// the result over the lanes j, j + G, j + 2G, ...).
-template <int G, class T>
-__device__ inline T wmin_lanes(T v)
-{
-#pragma unroll
-    for (int o = G; o < kWave; o <<= 1) {
-        T u = __shfl_xor(v, o, kWave);
-        v = v < u ? v : u;
-    }
-    return v;
-}
-template <int G, class T>
-__device__ inline T wmax_lanes(T v)
-{
-#pragma unroll
-    for (int o = G; o < kWave; o <<= 1) {
-        T u = __shfl_xor(v, o, kWave);
-        v = v > u ? v : u;
-    }
-    return v;
-}
 
 // Per-target candidate lists for the 16 targets of a wavefront (targets
 // 16 w + k, k = 0..15), built with G lanes per target (G = 16: sub-blocks of 4
@@ -539,7 +554,7 @@ __device__ inline void build_lists(int nstg, const vec4_t<T> *stg, uint16_t *sub
     static_assert(G == 8 || G == 16, "8 or 16 lanes per target");
     constexpr int TPS = kWave / G;   // targets per sub-block
     constexpr int NSB = 16 / TPS;    // sub-blocks per wavefront
-    const int w = threadIdx.x / kWave, lane = lane_id(), g = lane / G, j = lane % G;
+    const int w = wave_id(), lane = lane_id(), g = lane / G, j = lane % G;
     for (int sb = 0; sb < NSB; ++sb) {
         const int k = TPS * sb + g;  // this lane's target slot in the wave
         vec4_t<T> tp = pos(k);
