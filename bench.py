@@ -79,10 +79,10 @@ PEAK_HBM_GBS = 8000.0
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     "k_density<float, 0, false, false>": dict(
-        bytes_per_launch=141401626,
+        bytes_per_launch=41150874,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
-        sha256="b57ef0b46b120dbd308f2f2382a1fa4167597c081bd1f9d016d98f26e9a07902"),
+        sha256="3820de659cf8cfe930e50d597c9cdf643124332b9bcfbdcbe7dfaa0ff8f60494"),
 }
 
 

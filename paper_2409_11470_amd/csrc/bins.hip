@@ -300,8 +300,11 @@ int step_bins_t(apr_ctx *c, apr_state *s, int8_t *bin, const apr_zone *zones, in
         }
         // a substep whose pass changed nothing keeps the cells and refits them
         // to the drifted positions (the particles of a cell move together);
-        // every kRebuild-th substep sorts again, so that they stay compact
-        if (sub % kRebuild == 0 || changed || c->cells_n != n) {
+        // every kRebuild-th substep sorts again, so that they stay compact.
+        // Not in a periodic box: a particle the drift wrapped to the far side
+        // would stretch its cell across the box, and the cell's one periodic
+        // image shift would then be wrong for part of its particles
+        if (sub % kRebuild == 0 || changed || c->cells_n != n || c->p.periodic) {
             rc = build_cells(c, s, idx, true);
             if (rc) return rc;
             rc = remap_all<T>(c, bin, b, act, made, idx, n);

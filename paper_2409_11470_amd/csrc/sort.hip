@@ -163,19 +163,25 @@ constexpr int kRadixBits = 10;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
 constexpr int kBinsPerThread = kBins / kSortThreads;
-constexpr int kSortRounds = 8;
-constexpr int kSortTile = kSortThreads * kSortRounds;  // items per block
+// A block takes `rounds` rounds of 256 items (1 to 8): as many as keep about
+// one block per CU busy, so that a small sort still spreads over the chip
+// while a large one keeps its per-block histograms few.
+constexpr int kMaxSortRounds = 8;
+inline int sort_rounds(int64_t n)
+{
+    return (int)std::min<int64_t>(kMaxSortRounds, std::max<int64_t>(1, n / (kSortThreads * 256)));
+}
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, int64_t n,
                                                              int shift, uint32_t *hist,
-                                                             int64_t nblocks)
+                                                             int64_t nblocks, int rounds)
 {
     __shared__ uint32_t h[kBins];
 #pragma unroll
     for (int k = 0; k < kBinsPerThread; ++k) h[threadIdx.x + k * kSortThreads] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortRounds; ++r) {
+    int64_t base = (int64_t)blockIdx.x * kSortThreads * rounds;
+    for (int r = 0; r < rounds; ++r) {
         int64_t i = base + r * kSortThreads + threadIdx.x;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kBins - 1)], 1u);
     }
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
 // this round) + (in lower lanes of its wave, from the ballot-built peer mask).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n,
-    int shift, const uint32_t *offs, int64_t nblocks)
+    int shift, const uint32_t *offs, int64_t nblocks, int rounds)
 {
     constexpr int nw = kSortThreads / kWave;
     __shared__ uint32_t run[kBins];
@@ -205,8 +211,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     __syncthreads();
     int w = threadIdx.x / kWave;
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortRounds; ++r) {
+    int64_t base = (int64_t)blockIdx.x * kSortThreads * rounds;
+    for (int r = 0; r < rounds; ++r) {
         int64_t i = base + r * kSortThreads + threadIdx.x;
         bool valid = i < n;
         uint32_t key = valid ? kin[i] : 0u;
@@ -299,7 +305,8 @@ int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bi
     if (vals_out) *vals_out = vals;
     if (n <= 1) return APR_OK;
     if (n >= (int64_t)1 << 31) return fail(c, APR_ERR_INVALID, "too many particles to sort");
-    int64_t nb = ceil_div(n, kSortTile);
+    const int rounds = sort_rounds(n);
+    int64_t nb = ceil_div(n, (int64_t)kSortThreads * rounds);
     uint32_t *k2 = wsa<uint32_t>(c, "sort_k2", (size_t)n);
     uint32_t *v2 = wsa<uint32_t>(c, "sort_v2", (size_t)n);
     uint32_t *hist = wsa<uint32_t>(c, "sort_hist", (size_t)(kBins * nb));
@@ -309,12 +316,12 @@ int radix_sort_u32(apr_ctx *c, uint32_t *keys, uint32_t *vals, int64_t n, int bi
     for (int ps = 0; ps < passes; ++ps) {
         int shift = ps * kRadixBits;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, c->stream,
-                           ka, n, shift, hist, nb);
+                           ka, n, shift, hist, nb, rounds);
         APR_LAUNCHED(c);
         int rc = exclusive_scan_u32(c, hist, hist, kBins * nb, nullptr);
         if (rc) return rc;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0,
-                           c->stream, ka, va, kb, vb, n, shift, hist, nb);
+                           c->stream, ka, va, kb, vb, n, shift, hist, nb, rounds);
         APR_LAUNCHED(c);
         std::swap(ka, kb);
         std::swap(va, vb);
