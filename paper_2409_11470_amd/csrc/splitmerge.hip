@@ -611,6 +611,135 @@ __global__ void k_tree_partition(TreeArgs a, const uint32_t *left, const uint32_
     }
 }
 
+// A tree of at most kSmallTree elements (the few candidates of an
+// individual-timestep substep) in one workgroup: every depth of the
+// level-synchronous construction above, with the same statistics, cut and
+// stable partition, runs in LDS, one element per thread, until no node holds
+// more than two elements.  One launch instead of five per depth, and no host
+// check between depths.  es_out receives the final order (pairs adjacent).
+constexpr int kSmallTree = 256;
+
+__global__ __launch_bounds__(kSmallTree) void k_tree_small(int32_t m, const uint32_t *cand,
+                                                           const int32_t *q0, const int32_t *q1,
+                                                           const int32_t *q2, const int64_t *id,
+                                                           uint32_t *es_out)
+{
+    __shared__ uint32_t es[2][kSmallTree];
+    __shared__ int32_t lo[2][kSmallTree], hi[2][kSmallTree];
+    __shared__ Node nd[kSmallTree];
+    __shared__ uint32_t sc[kSmallTree], ex[kSmallTree];
+    __shared__ int s_more;
+    const int i = threadIdx.x;
+    const int32_t *q[3] = {q0, q1, q2};
+    if (i < m) {
+        es[0][i] = cand[i];
+        lo[0][i] = 0;
+        hi[0][i] = m;
+    }
+    int cur = 0;
+    bool more = m > 2;
+    // m is even, so every node is: each depth splits every node of four or
+    // more elements into two non-empty even parts, and m / 2 depths bound
+    // the loop
+    for (int depth = 0; more && depth < kSmallTree / 2; ++depth) {
+        if (i < m) clear_node(nd[i]);
+        __syncthreads();
+        const bool act = i < m && hi[cur][i] - lo[cur][i] > 2;
+        const int32_t L = act ? lo[cur][i] : 0, H = act ? hi[cur][i] : 0;
+        const uint32_t p = act ? es[cur][i] : 0u;
+        // min / max and coordinate sums of each node
+        if (act)
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&nd[L].mn[k], q[k][p]);
+                atomicMax(&nd[L].mx[k], q[k][p]);
+                atomicAdd(&nd[L].sum[k], (unsigned long long)q[k][p]);
+            }
+        __syncthreads();
+        // counts and extreme keys about the centroid on the widest axis
+        if (act) {
+            const int ax = node_axis(nd[L]);
+            if (i == L) nd[L].ax = ax;
+            const int64_t c = (int64_t)(nd[L].sum[ax] / (unsigned long long)(H - L));
+            const int64_t v = q[ax][p];
+            const unsigned long long key =
+                ((unsigned long long)v << kIdBits) | ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
+            const bool lt = v < c, eq = v == c;
+            if (lt) {
+                atomicAdd(&nd[L].kc, 1u);
+                atomicMax(&nd[L].amax_c, key);
+            } else {
+                atomicMin(&nd[L].amin_c, key);
+            }
+            if (eq) atomicAdd(&nd[L].keq, 1u);
+            if (lt || eq) atomicMax(&nd[L].amax_c1, key);
+            else atomicMin(&nd[L].amin_c1, key);
+        }
+        __syncthreads();
+        // each element's side (elements of finished nodes count as left and
+        // stay in place)
+        uint32_t left = 1u;
+        int32_t kp = 0;
+        if (act) {
+            const Cut cu = node_cut(nd[L], H - L);
+            kp = cu.kp;
+            if (cu.all_eq) {
+                left = (i - L) < cu.kp ? 1u : 0u;
+            } else {
+                const int64_t v = q[nd[L].ax][p];
+                bool l = v < cu.cut;
+                const unsigned long long key = ((unsigned long long)v << kIdBits) |
+                                               ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
+                if (key == cu.moved) l = !l;
+                left = l ? 1u : 0u;
+            }
+        }
+        // exclusive scan of the sides over the elements (inclusive in sc,
+        // then each element's exclusive value in ex)
+        sc[i] = i < m ? left : 0u;
+        __syncthreads();
+        for (int off = 1; off < kSmallTree; off <<= 1) {
+            const uint32_t u = i >= off ? sc[i - off] : 0u;
+            __syncthreads();
+            sc[i] += u;
+            __syncthreads();
+        }
+        ex[i] = sc[i] - (i < m ? left : 0u);
+        if (i == 0) s_more = 0;
+        __syncthreads();
+        // stable partition of every active node into [L, L + kp) and
+        // [L + kp, H); finished nodes keep their place
+        const int nx = 1 - cur;
+        if (i < m) {
+            if (!act) {
+                es[nx][i] = es[cur][i];
+                lo[nx][i] = lo[cur][i];
+                hi[nx][i] = hi[cur][i];
+            } else {
+                const int32_t lr = (int32_t)(ex[i] - ex[L]);
+                int32_t pos, nl, nh;
+                if (left) {
+                    pos = L + lr;
+                    nl = L;
+                    nh = L + kp;
+                } else {
+                    pos = L + kp + (i - L - lr);
+                    nl = L + kp;
+                    nh = H;
+                }
+                es[nx][pos] = p;
+                lo[nx][pos] = nl;
+                hi[nx][pos] = nh;
+                if (nh - nl > 2) s_more = 1;
+            }
+        }
+        __syncthreads();
+        cur = nx;
+        more = s_more != 0;
+        __syncthreads();  // s_more and the node statistics are rewritten next
+    }
+    if (i < m) es_out[i] = es[cur][i];
+}
+
 __global__ void k_tree_root(int64_t m, int32_t *lo, int32_t *hi, Node *node)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,6 +1041,16 @@ int split_merge(apr_ctx *c, apr_state *s, const apr_zone *zones, int nzones, int
             // the highest id (last) sits out when nc is odd; tree over the first m
             hipLaunchKernelGGL(k_quant, dim3(grid(m)), dim3(256), 0, c->stream, m, cand, A, b,
                                sc[0], sc[1], sc[2], q[0], q[1], q[2]);
+            if (m <= kSmallTree) {
+                // the whole tree in one workgroup, no host check between depths
+                hipLaunchKernelGGL(k_tree_small, dim3(1), dim3(kSmallTree), 0, c->stream,
+                                   (int32_t)m, cand, q[0], q[1], q[2], s->id, es[0]);
+                APR_LAUNCHED(c);
+                hipLaunchKernelGGL(k_merge_pairs, dim3(grid(m / 2)), dim3(256), 0, c->stream,
+                                   m / 2, es[0], A, Z, b, l, changed, removed, mcount);
+                APR_LAUNCHED(c);
+                continue;
+            }
             APR_HIP(c, hipMemcpyAsync(es[0], cand, (size_t)m * 4, hipMemcpyDeviceToDevice,
                                       c->stream));
             hipLaunchKernelGGL(k_tree_root, dim3(grid(m)), dim3(256), 0, c->stream, m, lo[0],

@@ -156,3 +156,21 @@ def test_merge_pairs_across_periodic_boundary():
     assert cnt[1] == g
     _compare(gp, o, cnt)
     assert np.all((o["x"] < 0.1) | (o["x"] >= 0.9))
+
+
+@pytest.mark.parametrize("nlev1", [40, 255, 256, 257, 258, 600])
+def test_merge_tree_sizes(nlev1):
+    """n randomly chosen level-1 particles of the box and no zone: every pair
+    merges.  The pairing tree of the n (n - 1 when odd) candidates is built in
+    one workgroup up to 256 elements and depth by depth beyond; both against
+    the oracle's tree."""
+    st, p = W.refine_box(nside=12)
+    p = dict(p, m0=1.0 / 12 ** 3)
+    rng = np.random.default_rng(5)
+    lev = np.zeros_like(st["level"])
+    lev[rng.choice(st["x"].shape[0], nlev1, replace=False)] = 1
+    st = dict(st, level=lev)
+    g, cnt = _gpu_pass(st, p, [], 3, 2)
+    o = _orc_pass(st, p, [], 3, 2)
+    assert cnt[1] == nlev1 // 2 and cnt[2] == nlev1 % 2
+    _compare(g, o, cnt)
