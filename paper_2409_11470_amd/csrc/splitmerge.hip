@@ -837,9 +837,41 @@ unsigned grid(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, 256); }
 // slot[0..m) into ascending id order: a stable LSD radix sort on the low 32
 // bits of the id, then on the high 32 when ids reach that far.  Every id is
 // below next_id, so the low-word sort needs only next_id's bit length.
+// At most kSmallSort slots in one workgroup: each slot's place is the number
+// of listed slots with a smaller id (the ids are unique, so the places are a
+// permutation, the order any sort by id gives).
+constexpr int kSmallSort = 1024;
+
+__global__ __launch_bounds__(kSmallSort) void k_sort_small(int32_t m, uint32_t *slot,
+                                                           const int64_t *id)
+{
+    __shared__ int64_t sid[kSmallSort];
+    const int i = threadIdx.x;
+    uint32_t p = 0;
+    int64_t v = 0;
+    if (i < m) {
+        p = slot[i];
+        v = id[p];
+        sid[i] = v;
+    }
+    __syncthreads();
+    int rank = 0;
+    if (i < m)
+        for (int k = 0; k < m; ++k) rank += sid[k] < v ? 1 : 0;
+    __syncthreads();  // every thread has read its slot before any is overwritten
+    if (i < m) slot[rank] = p;
+}
+
 int sort_slots_by_id(apr_ctx *c, uint32_t *slot, uint32_t *keys, int64_t m, const int64_t *id,
                      int64_t next_id)
 {
+    if (m <= 1) return APR_OK;
+    if (m <= kSmallSort) {
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallSort), 0, c->stream, (int32_t)m,
+                           slot, id);
+        APR_LAUNCHED(c);
+        return APR_OK;
+    }
     const bool high_ids = next_id > (int64_t)0xffffffffLL;
     int id_bits = 32;
     if (!high_ids) {
