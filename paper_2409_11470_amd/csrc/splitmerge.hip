@@ -611,13 +611,16 @@ __global__ void k_tree_partition(TreeArgs a, const uint32_t *left, const uint32_
     }
 }
 
-// A tree of at most kSmallTree elements (the few candidates of an
-// individual-timestep substep) in one workgroup: every depth of the
-// level-synchronous construction above, with the same statistics, cut and
-// stable partition, runs in LDS, one element per thread, until no node holds
-// more than two elements.  One launch instead of five per depth, and no host
-// check between depths.  es_out receives the final order (pairs adjacent).
-constexpr int kSmallTree = 256;
+// A tree of at most kSmallTree elements (the candidates of an
+// individual-timestep substep, or of a step's pass away from the zones'
+// edges) in one workgroup: every depth of the level-synchronous construction
+// above, with the same statistics, cut and stable partition, runs in LDS
+// (gfx950 gives a workgroup up to 160 KB), one element per thread, until no
+// node holds more than two elements.  One launch instead of five per depth,
+// and no host check between depths.  A wavefront whose active elements share
+// a node combines them before one lane updates it, as the kernels above do.
+// es_out receives the final order (pairs adjacent).
+constexpr int kSmallTree = 1024;
 
 __global__ __launch_bounds__(kSmallTree) void k_tree_small(int32_t m, const uint32_t *cand,
                                                            const int32_t *q0, const int32_t *q1,
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(kSmallTree) void k_tree_small(int32_t m, const uint
     __shared__ Node nd[kSmallTree];
     __shared__ uint32_t sc[kSmallTree], ex[kSmallTree];
     __shared__ int s_more;
-    const int i = threadIdx.x;
+    const int i = threadIdx.x, lane = __lane_id();
     const int32_t *q[3] = {q0, q1, q2};
     if (i < m) {
         es[0][i] = cand[i];
@@ -645,25 +648,67 @@ __global__ __launch_bounds__(kSmallTree) void k_tree_small(int32_t m, const uint
         if (i < m) clear_node(nd[i]);
         __syncthreads();
         const bool act = i < m && hi[cur][i] - lo[cur][i] > 2;
-        const int32_t L = act ? lo[cur][i] : 0, H = act ? hi[cur][i] : 0;
+        const int32_t L = act ? lo[cur][i] : -1, H = act ? hi[cur][i] : 0;
         const uint32_t p = act ? es[cur][i] : 0u;
         // min / max and coordinate sums of each node
-        if (act)
+        int first = 0;
+        if (wave_one_node(act, L, &first)) {
+            int32_t mn[3], mx[3];
+            unsigned long long sm[3];
+            for (int k = 0; k < 3; ++k) {
+                const int32_t v = act ? q[k][p] : 0;
+                mn[k] = wave_reduce(act ? v : INT32_MAX, imin);
+                mx[k] = wave_reduce(act ? v : INT32_MIN, imax);
+                sm[k] = wave_reduce(act ? (unsigned long long)v : 0ull, uadd64);
+            }
+            if (lane == first) {
+                Node &n0 = nd[L];
+                for (int k = 0; k < 3; ++k) {
+                    atomicMin(&n0.mn[k], mn[k]);
+                    atomicMax(&n0.mx[k], mx[k]);
+                    atomicAdd(&n0.sum[k], sm[k]);
+                }
+            }
+        } else if (act) {
             for (int k = 0; k < 3; ++k) {
                 atomicMin(&nd[L].mn[k], q[k][p]);
                 atomicMax(&nd[L].mx[k], q[k][p]);
                 atomicAdd(&nd[L].sum[k], (unsigned long long)q[k][p]);
             }
+        }
         __syncthreads();
         // counts and extreme keys about the centroid on the widest axis
+        bool lt = false, eq = false;
+        unsigned long long key = 0;
         if (act) {
             const int ax = node_axis(nd[L]);
             if (i == L) nd[L].ax = ax;
             const int64_t c = (int64_t)(nd[L].sum[ax] / (unsigned long long)(H - L));
             const int64_t v = q[ax][p];
-            const unsigned long long key =
-                ((unsigned long long)v << kIdBits) | ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
-            const bool lt = v < c, eq = v == c;
+            key = ((unsigned long long)v << kIdBits) |
+                  ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
+            lt = v < c;
+            eq = v == c;
+        }
+        if (wave_one_node(act, L, &first)) {
+            const uint32_t kc = (uint32_t)__popcll(__ballot(act && lt));
+            const uint32_t keq = (uint32_t)__popcll(__ballot(act && eq));
+            const unsigned long long amax_c = wave_reduce((act && lt) ? key : 0ull, umax64);
+            const unsigned long long amin_c = wave_reduce((act && !lt) ? key : ~0ull, umin64);
+            const unsigned long long amax_c1 =
+                wave_reduce((act && (lt || eq)) ? key : 0ull, umax64);
+            const unsigned long long amin_c1 =
+                wave_reduce((act && !(lt || eq)) ? key : ~0ull, umin64);
+            if (lane == first) {
+                Node &n0 = nd[L];
+                if (kc) atomicAdd(&n0.kc, kc);
+                if (keq) atomicAdd(&n0.keq, keq);
+                atomicMax(&n0.amax_c, amax_c);
+                atomicMin(&n0.amin_c, amin_c);
+                atomicMax(&n0.amax_c1, amax_c1);
+                atomicMin(&n0.amin_c1, amin_c1);
+            }
+        } else if (act) {
             if (lt) {
                 atomicAdd(&nd[L].kc, 1u);
                 atomicMax(&nd[L].amax_c, key);
@@ -687,9 +732,9 @@ __global__ __launch_bounds__(kSmallTree) void k_tree_small(int32_t m, const uint
             } else {
                 const int64_t v = q[nd[L].ax][p];
                 bool l = v < cu.cut;
-                const unsigned long long key = ((unsigned long long)v << kIdBits) |
-                                               ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
-                if (key == cu.moved) l = !l;
+                const unsigned long long k2 = ((unsigned long long)v << kIdBits) |
+                                              ((unsigned long long)id[p] & ((1ull << kIdBits) - 1));
+                if (k2 == cu.moved) l = !l;
                 left = l ? 1u : 0u;
             }
         }

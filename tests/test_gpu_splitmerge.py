@@ -158,13 +158,13 @@ def test_merge_pairs_across_periodic_boundary():
     assert np.all((o["x"] < 0.1) | (o["x"] >= 0.9))
 
 
-@pytest.mark.parametrize("nlev1", [40, 255, 256, 257, 258, 600, 1500])
+@pytest.mark.parametrize("nlev1", [40, 255, 600, 1023, 1024, 1025, 1026, 1500])
 def test_merge_tree_sizes(nlev1):
     """n randomly chosen level-1 particles of the box and no zone: every pair
-    merges.  The pairing tree of the n (n - 1 when odd) candidates is built in
-    one workgroup up to 256 elements and depth by depth beyond, and the
-    candidates are ordered by id in one workgroup up to 1024 and by radix
-    sort beyond; all against the oracle."""
+    merges.  The candidates are ordered by id in one workgroup up to 1024 and
+    by radix sort beyond, and the pairing tree of the n (n - 1 when odd) is
+    built in one workgroup up to 1024 elements and depth by depth beyond;
+    all against the oracle."""
     st, p = W.refine_box(nside=12)
     p = dict(p, m0=1.0 / 12 ** 3)
     rng = np.random.default_rng(5)
