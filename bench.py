@@ -82,7 +82,7 @@ MEASURED_TRAFFIC = {
         bytes_per_launch=41150874,
         sources=("paper_2409_11470_amd/csrc/density.hip", "paper_2409_11470_amd/csrc/search.hpp",
                  "paper_2409_11470_amd/csrc/common.hpp"),
-        sha256="3820de659cf8cfe930e50d597c9cdf643124332b9bcfbdcbe7dfaa0ff8f60494"),
+        sha256="0f3e4317188dcade6ecf6e927d60e324900168c7773a74007d8877cf0ad7d405"),
 }
 
 

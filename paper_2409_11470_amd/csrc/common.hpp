@@ -161,9 +161,6 @@ __device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 // The wavefront's index in its workgroup, as a scalar (uniform) value.
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)); }
-// A value every lane of the wavefront holds alike (an LDS broadcast read),
-// moved to a scalar register.
-__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // The value of lane (lane ^ O), for every lane of the wavefront, with no
 // address register (a ds_bpermute needs one per distance, and the compiler
