@@ -376,6 +376,12 @@ int apr_sync_status(apr_ctx *ctx, int64_t *count);
 enum { APR_PROF_DENSITY = 0, APR_PROF_FORCES = 1, APR_PROF_CELLS = 2, APR_PROF_SPLITMERGE = 3,
        APR_PROF_VJP = 4, APR_PROF_CAND = 5, APR_PROF_N = 6 };
 int apr_profile_enable(apr_ctx *ctx, int on);
+/* Restricts the timing to the indices whose bit (1 << index) is set in mask
+ * (every index by default; 0 records no event even while enabled).  Each
+ * timed launch adds two event records to the stream, and each record waits
+ * for the work before it, so a caller that times a whole step brackets only
+ * the kernel it needs.  Takes effect at the next launch; no GPU work. */
+int apr_profile_select(apr_ctx *ctx, uint32_t mask);
 /* Work counters since the last reset (diagnostics), written to
  * c[0 .. APR_COUNTERS_N-1]:
  * [0] h-rho solves that hit max_iter, [1] smoothing lengths at the periodic limit,

@@ -17,6 +17,6 @@ from .api import (  # noqa: F401
     Context, DeviceState, apr_ctx_create, apr_ctx_destroy, apr_set_cell_grid, apr_build_cells,
     apr_density,
     apr_forces, apr_vjp, apr_relax, apr_bins_init, apr_step_bins, apr_neighbours, apr_split_merge, apr_step, apr_accel, apr_timestep, apr_timestep_noalloc,
-    apr_sync_status, apr_profile_enable, apr_profile_read, apr_counters, make_params, make_zones,
+    apr_sync_status, apr_profile_enable, apr_profile_select, apr_profile_read, apr_counters, make_params, make_zones,
     make_sinks)
 from .autograd import apr_sums  # noqa: F401,E402

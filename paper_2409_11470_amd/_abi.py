@@ -101,6 +101,7 @@ def lib():
     L.apr_timestep.argtypes = [_vp, C.POINTER(CState), C.c_double, C.POINTER(C.c_double)]
     L.apr_sync_status.argtypes = [_vp, _i64p]
     L.apr_profile_enable.argtypes = [_vp, C.c_int]
+    L.apr_profile_select.argtypes = [_vp, C.c_uint32]
     L.apr_counters.argtypes = [_vp, _i64p, C.c_int]
     L.apr_profile_read.argtypes = [_vp, C.POINTER(C.c_double), _i64p, C.c_int]
     for f in ("apr_ctx_create", "apr_ctx_destroy", "apr_ctx_set_stream", "apr_set_cell_grid",
@@ -109,7 +110,7 @@ def lib():
               "apr_step_bins", "apr_neighbours",
               "apr_split_merge", "apr_step",
               "apr_accel", "apr_timestep", "apr_timestep_noalloc", "apr_sync_status",
-              "apr_profile_enable",
+              "apr_profile_enable", "apr_profile_select",
               "apr_profile_read", "apr_counters"):
         getattr(L, f).restype = C.c_int
     _LIB = L

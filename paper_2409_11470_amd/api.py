@@ -344,6 +344,12 @@ def apr_profile_enable(ctx, on=True):
     ctx.check(lib().apr_profile_enable(ctx.ptr, int(bool(on))))
 
 
+def apr_profile_select(ctx, indices=None):
+    """Times only the given APR_PROF_* indices (None: all of them)."""
+    mask = 0xFFFFFFFF if indices is None else sum(1 << int(k) for k in indices)
+    ctx.check(lib().apr_profile_select(ctx.ptr, mask))
+
+
 def apr_profile_read(ctx, reset=True):
     """{index: (total ms, launches)} for the timed kernels; synchronises."""
     ms = (C.c_double * APR_PROF_N)()

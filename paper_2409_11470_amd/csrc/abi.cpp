@@ -89,7 +89,7 @@ void *ws_keep(apr_ctx *c, const char *name, size_t bytes, size_t keep)
 
 int prof_begin(apr_ctx *c, int idx)
 {
-    if (!c->prof) return -1;
+    if (!c->prof || !((c->prof_mask >> idx) & 1u)) return -1;
     apr_ctx::EvPair e;
     if (!c->ev_free.empty()) {
         e = c->ev_free.back();
@@ -486,6 +486,13 @@ int apr_profile_enable(apr_ctx *c, int on)
 {
     if (!c) return APR_ERR_INVALID;
     c->prof = on != 0;
+    return APR_OK;
+}
+
+int apr_profile_select(apr_ctx *c, uint32_t mask)
+{
+    if (!c) return APR_ERR_INVALID;
+    c->prof_mask = mask;
     return APR_OK;
 }
 

@@ -106,6 +106,7 @@ struct apr_ctx {
     bool in_bins = false;          // set while the step driver itself reorders
     // kernel timing: pairs of events per index, summed at read time
     bool prof = false;
+    uint32_t prof_mask = ~0u;      // indices timed while prof is on (bit 1 << index)
     struct EvPair {
         int idx;
         hipEvent_t a, b;

@@ -81,3 +81,29 @@ def test_coincident_particles():
     da = np.sqrt(sum((gf[k] - of[k]) ** 2 for k in ("ax", "ay", "az")))
     assert np.max(da / of["anorm"]) < 1e-9
     assert np.max(np.abs(gf["dudt"] - of["dudt"]) / of["unorm"]) < 1e-9
+
+
+def test_profile_select_times_only_the_chosen_kernels():
+    """apr_profile_select restricts the event timing: with only the density
+    index selected a step times its density pass and nothing else; with every
+    index (the default) the force pass, the cell build and the candidate
+    walks are timed too."""
+    st, p = W.lattice_box(nside=16)
+    ctx = A.Context(params_for(p, "fp32"))
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_accel(ctx, ds)
+    A.apr_profile_enable(ctx, True)
+    A.apr_profile_select(ctx, [A.APR_PROF_DENSITY])
+    A.apr_profile_read(ctx, reset=True)
+    A.apr_step(ctx, ds, [], [], 1e-3, 0)
+    prof = A.apr_profile_read(ctx, reset=True)
+    assert prof[A.APR_PROF_DENSITY][1] == 1 and prof[A.APR_PROF_DENSITY][0] > 0.0
+    for k in (A.APR_PROF_FORCES, A.APR_PROF_CELLS, A.APR_PROF_CAND):
+        assert prof[k][1] == 0, k
+    A.apr_profile_select(ctx, None)
+    A.apr_step(ctx, ds, [], [], 1e-3, 1)
+    prof = A.apr_profile_read(ctx, reset=True)
+    for k in (A.APR_PROF_DENSITY, A.APR_PROF_FORCES, A.APR_PROF_CELLS, A.APR_PROF_CAND):
+        assert prof[k][1] >= 1, k
+    A.apr_profile_enable(ctx, False)
+    assert A.apr_sync_status(ctx) == 0
