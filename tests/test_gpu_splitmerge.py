@@ -158,7 +158,7 @@ def test_merge_pairs_across_periodic_boundary():
     assert np.all((o["x"] < 0.1) | (o["x"] >= 0.9))
 
 
-@pytest.mark.parametrize("nlev1", [40, 255, 600, 1023, 1024, 1025, 1026, 1500])
+@pytest.mark.parametrize("nlev1", [2, 3, 4, 5, 6, 40, 255, 600, 1023, 1024, 1025, 1026, 1500])
 def test_merge_tree_sizes(nlev1):
     """n randomly chosen level-1 particles of the box and no zone: every pair
     merges.  The candidates are ordered by id in one workgroup up to 1024 and
