@@ -31,15 +31,24 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 
 namespace {
 
+// Staging windows (entries) and workgroups per CU of the adjoint gathers.
+// FP32: windows sized so that the LDS of a workgroup stays within the 40 KB
+// that four per CU allow, and four per CU (at most 128 VGPRs, the force
+// adjoint spilling 48 B per lane): more windows per cell, but the extra
+// wavefronts hide more latency (refined box adjoint 0.75 -> 0.69 ms against
+// 384 / 768-entry windows at three per CU).  FP64: the compiler's choice (a
+// bound spills hundreds of bytes per lane and is slower).
 template <class T>
 struct VJPStage;
 template <>
 struct VJPStage<float> {
-    static constexpr int force = 384, dens = 768;
+    static constexpr int force = 288, dens = 512;
+    static constexpr int blocks = 4;
 };
 template <>
 struct VJPStage<double> {
     static constexpr int force = 256, dens = 512;
+    static constexpr int blocks = 1;
 };
 
 template <class T, int K>
@@ -190,7 +199,7 @@ struct DensVJP {
 };
 
 template <class T, int K, bool REST>
-__global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<T, K> op,
+__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::blocks) void k_vjp_force(Tree tr, ForceVJP<T, K> op,
                                                               CandList pre, int32_t *status,
                                                               int64_t first)
 {
@@ -198,7 +207,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_vjp_force(Tree tr, ForceVJP<
 }
 
 template <class T, int K, bool REST>
-__global__ __launch_bounds__(kSearchThreads) void k_vjp_dens(Tree tr, DensVJP<T, K> op,
+__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::blocks) void k_vjp_dens(Tree tr, DensVJP<T, K> op,
                                                              CandList pre, int32_t *status,
                                                              int64_t first)
 {
