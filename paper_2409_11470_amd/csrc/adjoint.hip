@@ -32,23 +32,25 @@ int eos_pack(apr_ctx *c, const apr_state *s, const void *rho, const void *omega)
 namespace {
 
 // Staging windows (entries) and workgroups per CU of the adjoint gathers.
-// FP32: windows sized so that the LDS of a workgroup stays within the 40 KB
-// that four per CU allow, and four per CU (at most 128 VGPRs, the force
-// adjoint spilling 48 B per lane): more windows per cell, but the extra
-// wavefronts hide more latency (refined box adjoint 0.75 -> 0.69 ms against
-// 384 / 768-entry windows at three per CU).  FP64: the compiler's choice (a
-// bound spills hundreds of bytes per lane and is slower).
+// The FP32 density adjoint runs four per CU, its window sized so that its
+// LDS stays within the 40 KB that four allow (it needs at most 128 VGPRs
+// anyway): more windows per cell, but the extra wavefronts hide more latency
+// (refined box: its 768-entry windows at three per CU were 5 % slower; 8M
+// disc 13.3 -> 12.8 ms).  The force adjoint keeps the compiler's choice: at
+// four per CU it spills 48 B per lane, 2.4 GB of writes per launch on the 8M
+// disc, for no gain there.  FP64: the compiler's choice (a bound spills
+// hundreds of bytes per lane and is slower).
 template <class T>
 struct VJPStage;
 template <>
 struct VJPStage<float> {
-    static constexpr int force = 288, dens = 512;
-    static constexpr int blocks = 4;
+    static constexpr int force = 384, dens = 512;
+    static constexpr int force_blocks = 1, dens_blocks = 4;
 };
 template <>
 struct VJPStage<double> {
     static constexpr int force = 256, dens = 512;
-    static constexpr int blocks = 1;
+    static constexpr int force_blocks = 1, dens_blocks = 1;
 };
 
 template <class T, int K>
@@ -199,7 +201,7 @@ struct DensVJP {
 };
 
 template <class T, int K, bool REST>
-__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::blocks) void k_vjp_force(Tree tr, ForceVJP<T, K> op,
+__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::force_blocks) void k_vjp_force(Tree tr, ForceVJP<T, K> op,
                                                               CandList pre, int32_t *status,
                                                               int64_t first)
 {
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kSearchThreads, VJPStage<T>::blocks) void k_vjp_for
 }
 
 template <class T, int K, bool REST>
-__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::blocks) void k_vjp_dens(Tree tr, DensVJP<T, K> op,
+__global__ __launch_bounds__(kSearchThreads, VJPStage<T>::dens_blocks) void k_vjp_dens(Tree tr, DensVJP<T, K> op,
                                                              CandList pre, int32_t *status,
                                                              int64_t first)
 {
