@@ -47,6 +47,85 @@ def test_planet_disc_1M_sampled(prec):
     assert np.array_equal(g["nneigh"][tg], exact_counts(st, p, tg, g["h"]))
 
 
+def _final_state(ctx, ds):
+    """Density and hydro forces of the state as a step left it (cells built
+    again), all in storage order: (state arrays, density dict, forces dict)."""
+    A.apr_build_cells(ctx, ds)
+    rho = torch.zeros(ds.n, dtype=ctx.dtype, device="cuda")
+    om = torch.zeros_like(rho)
+    A.apr_density(ctx, ds, rho, om)
+    f = {k: torch.zeros_like(rho) for k in ("ax", "ay", "az", "dudt", "vsig")}
+    A.apr_forces(ctx, ds, rho, om, f["ax"], f["ay"], f["az"], f["dudt"], f["vsig"])
+    assert A.apr_sync_status(ctx) == 0
+    s = ds.to_numpy()
+    g = dict(h=s["h"], rho=rho.double().cpu().numpy(), omega=om.double().cpu().numpy(),
+             failures=0)
+    return s, g, {k: v.double().cpu().numpy() for k, v in f.items()}
+
+
+def test_shock_box_262k_20_steps_fp32():
+    # The benchmarked sequence at its full size: the 64^3 jittered box with its
+    # two states, 20 leapfrog steps in the FP32 form at dt = 0.3 min(h / v_sig)
+    # of t = 0; at the final state, the density and hydro forces of sampled
+    # balls (four about the interface x = 0.5, four anywhere) against the
+    # oracle at the GPU's own positions.
+    st, p = W.shock_box()
+    ctx = A.Context(params_for(p, "fp32"))
+    ds = A.DeviceState.from_numpy(st)
+    A.apr_accel(ctx, ds)
+    dt = A.apr_timestep(ctx, ds, 0.3)
+    for k in range(20):
+        A.apr_step(ctx, ds, [], [], dt, k)
+    assert A.apr_sync_status(ctx) == 0
+    s, g, gf = _final_state(ctx, ds)
+    del ctx, ds
+    n = s["x"].shape[0]
+    rng = np.random.default_rng(24)
+    near = np.nonzero(np.abs(s["x"] - 0.5) < 0.02)[0]
+    centres = np.concatenate([rng.choice(near, 4, replace=False),
+                              rng.choice(n, 4, replace=False)])
+    tg, od, of = oracle_balls(s, p, 8, 48, seed=24, centres=centres)
+    _check(g, gf, tg, od, of, "fp32")
+
+
+def test_planet_disc_1M_10_steps_with_refinement():
+    # The 1M disc's ten leapfrog steps with its refinement sphere (r = 1 about
+    # (5, 0, 0), random split axes, r_sep = 0.5 h, the sink at the origin), as
+    # the benchmark runs them (FP32 form, dt = 2e-3): particles split as they
+    # enter the sphere and pairs merge as they leave, every step.  At any size:
+    # no failure, the mass in units of the smallest particle unchanged, ids
+    # unique, every particle well inside the sphere at its level and none above
+    # it.  At the final state: the density and hydro forces of sampled balls
+    # against the oracle at the GPU's own positions.
+    st, p = W.planet_disc()
+    ctx = A.Context(params_for(p, "fp32", r_sep_factor=p["r_sep_factor"], nn_cap=p["nn_cap"],
+                               split_mode=int(p["split_mode"]), seed=3,
+                               G=float(p.get("G", 1.0))))
+    ds = A.DeviceState.from_numpy(st, capacity=st["x"].shape[0] * 5 // 4)
+    units = lambda lv: int(np.sum(2 ** (8 - lv.astype(np.int64))))
+    u0 = units(st["level"])
+    A.apr_accel(ctx, ds, p["sinks"])
+    for k in range(10):
+        A.apr_step(ctx, ds, p["zones"], p["sinks"], 2e-3, k)
+    assert A.apr_sync_status(ctx) == 0
+    fin = ds.to_numpy()
+    assert units(fin["level"]) == u0
+    assert fin["x"].shape[0] > st["x"].shape[0]
+    assert np.unique(fin["id"]).shape[0] == fin["id"].shape[0]
+    c = np.array(p["zones"][0]["c"])
+    r2 = (fin["x"] - c[0]) ** 2 + (fin["y"] - c[1]) ** 2 + (fin["z"] - c[2]) ** 2
+    assert np.all(fin["level"][r2 < 0.9 ** 2] == 1) and np.all(fin["level"] <= 1)
+    s, g, gf = _final_state(ctx, ds)
+    del ctx, ds
+    n = s["x"].shape[0]
+    # three balls anywhere, three about children (both masses in their reach)
+    rng = np.random.default_rng(22)
+    centres = np.concatenate([rng.choice(n, 3, replace=False),
+                              rng.choice(np.nonzero(s["level"] == 1)[0], 3, replace=False)])
+    tg, od, of = oracle_balls(s, p, 6, 48, seed=22, centres=centres)
+    _check(g, gf, tg, od, of, "fp32")
+
+
 @pytest.fixture(scope="module")
 def cb_disc():
     return W.circumbinary_disc()
