@@ -291,6 +291,37 @@ def test_circumbinary_8M_vjp_sampled(cb_disc, prec, level):
                    gtol={"fp64": 1e-6, "fp32": 1e-3}[prec])
 
 
+@pytest.fixture(scope="module")
+def refined_box():
+    # the split pass's result, given a seeded velocity field (N(0, 0.1) per
+    # component, a tenth of the sound speed) so that du/dt and the viscosity
+    # take part in the adjoint
+    st, p = W.refine_box()
+    s1 = _orc_pass(st, p, p["zones"], 3, 1)
+    v = np.random.default_rng(41).normal(0.0, 0.1, size=(3, s1["x"].shape[0]))
+    return dict(s1, vx=v[0], vy=v[1], vz=v[2]), p
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("level", [1, 4])
+def test_refine_box_vjp_sampled(refined_box, prec, level):
+    # the adjoint on the refined box after its split pass (362k particles,
+    # levels 0, 1, 3, 4, in motion): one ball on the sphere's edge about a child of each
+    # split level, so the ball holds children and their unsplit neighbours;
+    # x-bar and m-bar over all particles against the dense gradient oracle on
+    # the ball's dependency set; gates 1e-6 (FP64) and 1e-3 (FP32) of the
+    # max-norm
+    from _gpu import ball_vjp_check
+    s1, p = refined_box
+    z = p["zones"][0]
+    r = np.sqrt((s1["x"] - z["c"][0]) ** 2 + (s1["y"] - z["c"][1]) ** 2 +
+                (s1["z"] - z["c"][2]) ** 2)
+    ch = np.nonzero(s1["level"] == level)[0]
+    centre = int(ch[np.argmin(np.abs(r[ch] - z["r"][0]))])
+    ball_vjp_check(("refined_box", level), s1, p, prec, centre, seed=40 + level,
+                   gtol={"fp64": 1e-6, "fp32": 1e-3}[prec])
+
+
 def test_beyond_16M_particles_scans_cells_density():
     # 272^3 = 20.1M particles (the benchmarked box's shape): the cell build,
     # the density and the neighbour export run scans of more than 4096 tiles
